@@ -1,0 +1,161 @@
+"""ctypes wrapper around rici_oracle.c -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this module.  Array checks and marshalling only; every result is computed by the
+C oracle (FP64 geometry, int64 distances).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+NBINS = 64
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rici_oracle.c")
+_LIB = os.path.join(_HERE, "librici_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-D_GNU_SOURCE",
+               "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build(force=False)
+            lib = ctypes.CDLL(_LIB)
+            P = ctypes.c_void_p
+            U32, I32, I64, F32 = ctypes.c_uint32, ctypes.c_int, ctypes.c_int64, ctypes.c_float
+            lib.oracle_rici_rowrange.argtypes = [P, U32, P, U32, P, P, U32, F32, P, P, P, I32]
+            lib.oracle_rici_rowrange.restype = I32
+            lib.oracle_rici_brute.argtypes = [P, U32, P, U32, P, P, U32, F32, P, P, I32]
+            lib.oracle_rici_brute.restype = I32
+            lib.oracle_project.argtypes = [P, P, P, I64, I32, P, P, P]
+            lib.oracle_project.restype = None
+            lib.oracle_crd.argtypes = [P, P]
+            lib.oracle_crd.restype = I64
+            lib.oracle_rank.argtypes = [P, U32, P, U32, P, P, P, I32]
+            lib.oracle_rank.restype = I32
+            lib.oracle_distance_matrix.argtypes = [P, U32, P, U32, P, I32]
+            lib.oracle_distance_matrix.restype = I32
+            lib.oracle_threads.argtypes = [I32]
+            lib.oracle_threads.restype = I32
+            _lib = lib
+    return _lib
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _mesh_args(positions, triangles, op_positions, op_normals):
+    pos = _c(positions, np.float32).reshape(-1, 3)
+    tri = _c(triangles, np.uint32).reshape(-1, 3)
+    opp = _c(op_positions, np.float32).reshape(-1, 3)
+    opn = _c(op_normals, np.float32).reshape(-1, 3)
+    if opp.shape != opn.shape:
+        raise ValueError("op_positions and op_normals differ in shape")
+    return pos, tri, opp, opn
+
+
+def threads(nthreads: int = 0) -> int:
+    return int(load().oracle_threads(int(nthreads)))
+
+
+def rici_rowrange(positions, triangles, op_positions, op_normals, support_radius: float,
+                  nthreads: int = 0):
+    """Row-range oracle: returns (images u32 [N,64,64], flags bool [N,64,64],
+    work u64 [N,3] = (triangles visited, slices, pixel updates))."""
+    pos, tri, opp, opn = _mesh_args(positions, triangles, op_positions, op_normals)
+    n = opp.shape[0]
+    images = np.zeros((n, NBINS, NBINS), dtype=np.uint32)
+    flags = np.zeros((n, NBINS, NBINS), dtype=np.uint8)
+    work = np.zeros((n, 3), dtype=np.uint64)
+    rc = load().oracle_rici_rowrange(_ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], _ptr(opp), _ptr(opn),
+                                     n, float(support_radius), _ptr(images), _ptr(flags), _ptr(work),
+                                     int(nthreads))
+    if rc != 0:
+        raise ValueError("triangle index out of range")
+    return images, flags.astype(bool), work
+
+
+def rici_brute(positions, triangles, op_positions, op_normals, support_radius: float,
+               nthreads: int = 0):
+    """Brute-force oracle (plain definition): returns (images, flags)."""
+    pos, tri, opp, opn = _mesh_args(positions, triangles, op_positions, op_normals)
+    n = opp.shape[0]
+    images = np.zeros((n, NBINS, NBINS), dtype=np.uint32)
+    flags = np.zeros((n, NBINS, NBINS), dtype=np.uint8)
+    rc = load().oracle_rici_brute(_ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], _ptr(opp), _ptr(opn),
+                                  n, float(support_radius), _ptr(images), _ptr(flags), int(nthreads))
+    if rc != 0:
+        raise ValueError("triangle index out of range")
+    return images, flags.astype(bool)
+
+
+def project(spin_vertex, spin_normal, points, printed_eq1: bool = False):
+    """Eq. 1-5 projection: returns (alpha, beta, (T_x, T_y)) in FP64."""
+    sv = _c(spin_vertex, np.float32).reshape(3)
+    sn = _c(spin_normal, np.float32).reshape(3)
+    pts = _c(points, np.float64).reshape(-1, 3)
+    n = pts.shape[0]
+    alpha = np.zeros(n)
+    beta = np.zeros(n)
+    txy = np.zeros((n, 2))
+    load().oracle_project(_ptr(sv), _ptr(sn), _ptr(pts), n, int(bool(printed_eq1)), _ptr(alpha), _ptr(beta),
+                          _ptr(txy))
+    return alpha, beta, txy
+
+
+def crd(needle, haystack) -> int:
+    nd = _c(needle, np.uint32).reshape(NBINS, NBINS)
+    hs = _c(haystack, np.uint32).reshape(NBINS, NBINS)
+    return int(load().oracle_crd(_ptr(nd), _ptr(hs)))
+
+
+def distance_matrix(needles, haystack, nthreads: int = 0) -> np.ndarray:
+    nd = _c(needles, np.uint32).reshape(-1, NBINS, NBINS)
+    hs = _c(haystack, np.uint32).reshape(-1, NBINS, NBINS)
+    out = np.zeros((nd.shape[0], hs.shape[0]), dtype=np.int64)
+    load().oracle_distance_matrix(_ptr(nd), nd.shape[0], _ptr(hs), hs.shape[0], _ptr(out), int(nthreads))
+    return out
+
+
+def rank(needles, haystack, true_index, nthreads: int = 0):
+    """Returns (rank u32 [Nn], true distance i64 [Nn])."""
+    nd = _c(needles, np.uint32).reshape(-1, NBINS, NBINS)
+    hs = _c(haystack, np.uint32).reshape(-1, NBINS, NBINS)
+    ti = _c(true_index, np.uint32).reshape(-1)
+    if ti.shape[0] != nd.shape[0]:
+        raise ValueError("true_index must have one entry per needle")
+    rk = np.zeros(nd.shape[0], dtype=np.uint32)
+    ds = np.zeros(nd.shape[0], dtype=np.int64)
+    rc = load().oracle_rank(_ptr(nd), nd.shape[0], _ptr(hs), hs.shape[0], _ptr(ti), _ptr(rk), _ptr(ds),
+                            int(nthreads))
+    if rc != 0:
+        raise ValueError("true_index out of range")
+    return rk, ds
