@@ -1,0 +1,140 @@
+/*
+ * rici.h -- C ABI of the MI355X (gfx950) implementation of the Radial
+ * Intersection Count Image (RICI) pipeline of van Blokland & Theoharis,
+ * "Radial intersection count image: a clutter resistant 3D shape descriptor"
+ * (2020): descriptor generation (Sec. 3.1) and clutter-resistant-distance rank
+ * search (Sec. 3.2, Sec. 4.1).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers on the handle's device, allocated and
+ *     owned by the caller.  The library never frees or retains them beyond the
+ *     work it enqueues.  Outputs must not overlap inputs.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     work is enqueued on it and the call returns without waiting.
+ *   - Every call returns a rici_status.  Argument errors are detected on the
+ *     host before anything is enqueued; rici_last_error() then describes them.
+ *     Errors found by the kernels (a triangle index >= num_vertices, a
+ *     non-finite coordinate) set a sticky per-handle device word that the next
+ *     rici_sync() reports (and clears); the images of such a call are
+ *     unspecified.
+ *   - A handle owns its scratch memory and is NOT safe for concurrent calls:
+ *     use one handle per stream that issues work concurrently.  Scratch grows
+ *     on demand; growing it synchronises the device.
+ *   - Zero-sized work (num_points == 0, num_needles == 0) is a valid no-op.
+ *
+ * Image layout: uint32 [N][64][64], row-major.  Row r is the circle plane at
+ * height beta_r = -R/2 + (r + 1/2) R/64 along the Central Axis, column c the
+ * circle of radius rho_c = (c + 1/2) R/64, so pixel (r, c) counts the points
+ * where that circle meets the scene's triangles (Sec. 3.1; the square support
+ * plane of width and height R of Sec. 2.1, sampled at bin centres).
+ */
+#ifndef RICI_H
+#define RICI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RICI_BINS 64
+
+typedef struct rici_ctx* rici_handle;
+
+typedef enum {
+    RICI_OK = 0,
+    RICI_ERR_INVALID = -1,      /* bad argument (null pointer, size, radius, overlap) */
+    RICI_ERR_OOM = -2,          /* scratch allocation failed                          */
+    RICI_ERR_HIP = -3,          /* a HIP runtime call failed                          */
+    RICI_ERR_DEVICE = -4,       /* a kernel flagged bad input (reported by rici_sync) */
+    RICI_ERR_UNSUPPORTED = -5   /* no gfx950 device / size beyond the documented cap  */
+} rici_status;
+
+/* Device-side error bits reported through rici_sync / rici_device_errors. */
+#define RICI_DEVERR_INDEX 1u       /* a triangle index >= num_vertices */
+#define RICI_DEVERR_NONFINITE 2u   /* a non-finite position, normal    */
+
+/* Create a handle bound to HIP device `device` (must be gfx950).  */
+int rici_create(rici_handle* out, int device);
+/* Release the handle and its scratch (waits for the handle's device). */
+void rici_destroy(rici_handle h);
+/* Message describing the last failing call made by this thread ("" if none). */
+const char* rici_last_error(void);
+/* Wait for `stream`, then report and clear the handle's sticky device errors:
+ * RICI_OK, RICI_ERR_DEVICE (bits readable via rici_device_errors) or RICI_ERR_HIP. */
+int rici_sync(rici_handle h, void* stream);
+/* Device error bits seen by the last rici_sync on this handle. */
+uint32_t rici_device_errors(rici_handle h);
+
+/*
+ * rici_generate -- one RICI per oriented point (Sec. 3.1; one descriptor per
+ * unique vertex, Sec. 4.1 step 5).
+ *   positions     [num_vertices][3] fp32 scene vertices.
+ *   triangles     [num_triangles][3] uint32 vertex indices (every triangle of
+ *                 the scene contributes, Sec. 3.1: O(T) per image).
+ *   op_positions  [num_points][3] fp32 Spin Vertices S_v.
+ *   op_normals    [num_points][3] fp32 Spin Normals S_n (any length; a zero
+ *                 normal selects the +z axis, the identity rotation of Sec. 3.1.1).
+ *   support_radius  R, finite and > 0.
+ *   out_images    [num_points][64][64] uint32, overwritten.
+ * Projection: Eq. 1-5 with the second rotation normalising the first
+ * rotation's output; intersection counting: Sec. 3.1.2 (single range
+ * (min|E|, max|E|), double range (|C|, min|E|)); all decisions in FP64.
+ * num_triangles == 0 gives all-zero images.  Limits: num_triangles < 2^29,
+ * num_points < 2^31.
+ */
+int rici_generate(rici_handle h,
+                  const float* positions, uint32_t num_vertices,
+                  const uint32_t* triangles, uint32_t num_triangles,
+                  const float* op_positions, const float* op_normals, uint32_t num_points,
+                  float support_radius, uint32_t* out_images, void* stream);
+
+/*
+ * rici_distance_rank -- rank of the true match (Sec. 4.1 step 6c) under the
+ * clutter-resistant distance CRD (Sec. 3.2, Eq. 6-7):
+ *   CRD(n, h) = sum over rows r in [0, 64), columns c in [1, 64) with
+ *               D(n,r,c) != 0 of (D(n,r,c) - D(h,r,c))^2,
+ *   D(x,r,c)  = x(r,c) - x(r,c-1) (signed).
+ *   rank[i]   = #{ j : CRD(n_i, h_j) < CRD(n_i, h_true[i]) }   (ties take the
+ *               best rank, Sec. 4.2), so 0 <= rank[i] <= num_haystack - 1.
+ *   needles       [num_needles][64][64] uint32.
+ *   haystack      [num_haystack][64][64] uint32 (may be the same memory).
+ *   true_index    [num_needles] uint32, each < num_haystack (checked on device;
+ *                 an out-of-range entry yields rank = num_haystack).
+ *   out_rank      [num_needles] uint32.
+ *   out_true_distance  [num_needles] int64 CRD(n_i, h_true[i]), or NULL.
+ * Exact integer arithmetic: int8 x int8 -> int32 MFMA contractions when the
+ * column deltas fit (|D| <= 127 for every image, |D_h| <= 11 for the two-plane
+ * form), exact int64 VALU arithmetic for any image outside that range.
+ */
+int rici_distance_rank(rici_handle h,
+                       const uint32_t* needles, uint32_t num_needles,
+                       const uint32_t* haystack, uint32_t num_haystack,
+                       const uint32_t* true_index,
+                       uint32_t* out_rank, int64_t* out_true_distance, void* stream);
+
+/*
+ * rici_distance_matrix -- out[i][j] = CRD(needle_i, haystack_j), int64,
+ * row-major [num_needles][num_haystack] (same arithmetic as rici_distance_rank).
+ */
+int rici_distance_matrix(rici_handle h,
+                         const uint32_t* needles, uint32_t num_needles,
+                         const uint32_t* haystack, uint32_t num_haystack,
+                         int64_t* out, void* stream);
+
+/*
+ * Kernel timing (measurement support).  When enabled, every kernel the handle
+ * launches is bracketed by HIP events on its stream; rici_timing_get sums the
+ * elapsed times of the completed launches of the named kernel ("gen",
+ * "gen_prep", "delta_needle", "delta_haystack", "true_distance", "search",
+ * "fallback", "matrix").  Reading synchronises the handle's device.
+ */
+int rici_timing_enable(rici_handle h, int on);
+int rici_timing_reset(rici_handle h);
+int rici_timing_get(rici_handle h, const char* kernel, double* total_ms, uint64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RICI_H */

@@ -48,6 +48,7 @@
 #define EPS 1e-9          /* decision band in scene units (R4)                  */
 #define VBAND 1e-6        /* radial band around a vertex that sits on a row plane */
 #define FLAT_DZ 1e-6      /* a crossing edge flatter than this is ill-conditioned */
+#define SHORT_SLICE 1e-6  /* a slice shorter than this has an ill-conditioned |C| */
 
 /* ------------------------------------------------------------------ pixel grid */
 
@@ -274,6 +275,11 @@ static void rici_one_image(const gen_job_t* J, int64_t img)
              * the intersection point out of reach of FP64 rounding bounds */
             if (fabs(z[ia] - z[lone]) < FLAT_DZ || fabs(z[ib] - z[lone]) < FLAT_DZ)
                 flag_band(flr, r, R, (dbl ? cdist : lo) - VBAND, hi + VBAND);
+            /* C-D (vi): for a very short slice the direction E0 -> E1, hence
+             * |C| and the double/single decision, is ill-conditioned; every
+             * radius it can affect lies within SHORT_SLICE of lo */
+            if (len < SHORT_SLICE)
+                flag_band(flr, r, R, lo - SHORT_SLICE - VBAND, hi + VBAND);
         }
     }
     if (J->work) {

@@ -1,0 +1,161 @@
+"""MI355X (gfx950) RICI pipeline: descriptor generation and clutter-resistant
+rank search (van Blokland & Theoharis 2020, Sec. 3.1-3.2, Sec. 4.1).
+
+Thin binding over librici.so (include/rici.h).  Tensors are ROCm torch tensors;
+PyTorch only supplies device memory and the current stream, every step runs in
+the library's HIP kernels.
+
+    ctx = Context()
+    images = ctx.generate(positions, triangles, op_positions, op_normals, 0.3)
+    rank, dist = ctx.distance_rank(needle_images, haystack_images, true_index)
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+from ._lib import EXPORTS, LIB_PATH, RiciError, check, load  # noqa: F401
+
+NBINS = 64
+
+__all__ = ["Context", "RiciError", "NBINS", "load", "EXPORTS", "LIB_PATH"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name, dtype, shape_tail=None, device=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU (got {t.device})")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the context on cuda:{device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [N, {', '.join(map(str, shape_tail))}] (got {tuple(t.shape)})")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+class Context:
+    """One librici handle bound to one GPU.  Not safe for concurrent calls:
+    use one Context per stream that issues work concurrently."""
+
+    def __init__(self, device: int | None = None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no ROCm GPU visible: the RICI pipeline runs only on gfx950")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self._lib = load()
+        h = ctypes.c_void_p()
+        check(self._lib.rici_create(ctypes.byref(h), self.device))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.rici_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------------- calls
+    def generate(self, positions, triangles, op_positions, op_normals, support_radius: float,
+                 out=None, stream=None):
+        """RICIs of the oriented points: uint32 [N, 64, 64] (int32 tensor viewed as uint32)."""
+        torch = _torch()
+        dev = self.device
+        pos = _dev(positions, "positions", torch.float32, (3,), dev)
+        tri = _dev(triangles, "triangles", torch.int32, (3,), dev)
+        opp = _dev(op_positions, "op_positions", torch.float32, (3,), dev)
+        opn = _dev(op_normals, "op_normals", torch.float32, (3,), dev)
+        if opp.shape != opn.shape:
+            raise ValueError("op_positions and op_normals differ in shape")
+        n = opp.shape[0]
+        if out is None:
+            out = torch.empty((n, NBINS, NBINS), dtype=torch.int32, device=opp.device)
+        else:
+            _dev(out, "out", torch.int32, (NBINS, NBINS), dev)
+            if out.shape[0] != n:
+                raise ValueError("out must have one image per oriented point")
+        check(self._lib.rici_generate(self._h, _ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], _ptr(opp),
+                                      _ptr(opn), n, float(support_radius), _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def distance_rank(self, needles, haystack, true_index, out_rank=None, out_true_distance=None, stream=None):
+        """(rank int32 [Nn], true-match CRD int64 [Nn]) of each needle's true match."""
+        torch = _torch()
+        dev = self.device
+        nd = _dev(needles, "needles", torch.int32, (NBINS, NBINS), dev)
+        hs = _dev(haystack, "haystack", torch.int32, (NBINS, NBINS), dev)
+        ti = _dev(true_index, "true_index", torch.int32, None, dev)
+        nn = nd.shape[0]
+        if ti.dim() != 1 or ti.shape[0] != nn:
+            raise ValueError("true_index must be [num_needles]")
+        if out_rank is None:
+            out_rank = torch.empty(nn, dtype=torch.int32, device=nd.device)
+        if out_true_distance is None:
+            out_true_distance = torch.empty(nn, dtype=torch.int64, device=nd.device)
+        _dev(out_rank, "out_rank", torch.int32, None, dev)
+        _dev(out_true_distance, "out_true_distance", torch.int64, None, dev)
+        check(self._lib.rici_distance_rank(self._h, _ptr(nd), nn, _ptr(hs), hs.shape[0], _ptr(ti), _ptr(out_rank),
+                                           _ptr(out_true_distance), _stream_ptr(stream)))
+        return out_rank, out_true_distance
+
+    def distance_matrix(self, needles, haystack, out=None, stream=None):
+        """CRD(needle_i, haystack_j) as int64 [Nn, Nh]."""
+        torch = _torch()
+        dev = self.device
+        nd = _dev(needles, "needles", torch.int32, (NBINS, NBINS), dev)
+        hs = _dev(haystack, "haystack", torch.int32, (NBINS, NBINS), dev)
+        if out is None:
+            out = torch.empty((nd.shape[0], hs.shape[0]), dtype=torch.int64, device=nd.device)
+        _dev(out, "out", torch.int64, (hs.shape[0],), dev)
+        check(self._lib.rici_distance_matrix(self._h, _ptr(nd), nd.shape[0], _ptr(hs), hs.shape[0], _ptr(out),
+                                             _stream_ptr(stream)))
+        return out
+
+    def sync(self, stream=None):
+        """Wait for the stream and raise on errors the kernels reported."""
+        check(self._lib.rici_sync(self._h, _stream_ptr(stream)))
+
+    def device_errors(self) -> int:
+        return int(self._lib.rici_device_errors(self._h))
+
+    # --------------------------------------------------------------- timing
+    def timing(self, on: bool = True):
+        check(self._lib.rici_timing_enable(self._h, int(bool(on))))
+
+    def timing_reset(self):
+        check(self._lib.rici_timing_reset(self._h))
+
+    def timing_get(self, kernel: str):
+        ms = ctypes.c_double()
+        n = ctypes.c_uint64()
+        check(self._lib.rici_timing_get(self._h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

@@ -1,0 +1,78 @@
+"""ctypes loader for librici.so (the C ABI of include/rici.h).
+
+Argument marshalling only: every step of the pipeline runs in the library's
+HIP kernels.  Loading fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librici.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "rici.h")
+
+EXPORTS = [
+    "rici_create", "rici_destroy", "rici_last_error", "rici_sync", "rici_device_errors",
+    "rici_generate", "rici_distance_rank", "rici_distance_matrix",
+    "rici_timing_enable", "rici_timing_reset", "rici_timing_get",
+]
+
+RICI_OK = 0
+STATUS = {0: "RICI_OK", -1: "RICI_ERR_INVALID", -2: "RICI_ERR_OOM", -3: "RICI_ERR_HIP",
+          -4: "RICI_ERR_DEVICE", -5: "RICI_ERR_UNSUPPORTED"}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class RiciError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS.get(code, code)}: {message}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load librici.so and declare its prototypes (raises if it is missing)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with paper_2007_02306_amd/build.py "
+                              "(there is no CPU fallback)")
+        lib = ctypes.CDLL(path)
+        P, U32, I32, F32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_float
+        lib.rici_create.argtypes = [ctypes.POINTER(P), I32]
+        lib.rici_create.restype = I32
+        lib.rici_destroy.argtypes = [P]
+        lib.rici_destroy.restype = None
+        lib.rici_last_error.argtypes = []
+        lib.rici_last_error.restype = ctypes.c_char_p
+        lib.rici_sync.argtypes = [P, P]
+        lib.rici_sync.restype = I32
+        lib.rici_device_errors.argtypes = [P]
+        lib.rici_device_errors.restype = U32
+        lib.rici_generate.argtypes = [P, P, U32, P, U32, P, P, U32, F32, P, P]
+        lib.rici_generate.restype = I32
+        lib.rici_distance_rank.argtypes = [P, P, U32, P, U32, P, P, P, P]
+        lib.rici_distance_rank.restype = I32
+        lib.rici_distance_matrix.argtypes = [P, P, U32, P, U32, P, P]
+        lib.rici_distance_matrix.restype = I32
+        lib.rici_timing_enable.argtypes = [P, I32]
+        lib.rici_timing_enable.restype = I32
+        lib.rici_timing_reset.argtypes = [P]
+        lib.rici_timing_reset.restype = I32
+        lib.rici_timing_get.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_uint64)]
+        lib.rici_timing_get.restype = I32
+        _lib = lib
+    return _lib
+
+
+def check(code: int) -> None:
+    if code != RICI_OK:
+        msg = load().rici_last_error()
+        raise RiciError(code, msg.decode() if msg else "")

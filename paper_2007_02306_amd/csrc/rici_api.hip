@@ -1,0 +1,426 @@
+// Host side of librici: handles, scratch, argument checks, kernel timing and
+// the extern "C" entry points declared in include/rici.h.
+#include "rici.h"
+#include "rici_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+struct TimedLaunch {
+    const char* name;
+    hipEvent_t start, stop;
+};
+
+struct rici_ctx {
+    int device = 0;
+    uint32_t* d_err = nullptr;      // sticky device error word
+    uint32_t last_dev_err = 0;
+    void* ws = nullptr;             // scratch
+    size_t ws_size = 0;
+    bool timing = false;
+    std::vector<TimedLaunch> launches;
+    std::vector<hipEvent_t> free_events;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(RICI_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Makes the handle's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+hipEvent_t get_event(rici_ctx* h)
+{
+    if (!h->free_events.empty()) {
+        hipEvent_t e = h->free_events.back();
+        h->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs one launch, bracketed by events when timing is on.
+template <class F>
+hipError_t timed(rici_ctx* h, const char* name, hipStream_t s, F&& launch)
+{
+    if (!h->timing) return launch();
+    TimedLaunch t{name, get_event(h), get_event(h)};
+    if (t.start) (void)hipEventRecord(t.start, s);
+    hipError_t e = launch();
+    if (t.stop) (void)hipEventRecord(t.stop, s);
+    if (t.start && t.stop) h->launches.push_back(t);
+    return e;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Grows the handle's scratch to at least `bytes` (synchronises the device).
+int ensure_ws(rici_ctx* h, size_t bytes)
+{
+    if (bytes <= h->ws_size) return RICI_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    if (h->ws) {
+        (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_size = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    e = hipMalloc(&h->ws, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        h->ws = nullptr;
+        e = hipMalloc(&h->ws, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            h->ws = nullptr;
+            return fail(RICI_ERR_OOM, "cannot allocate %zu bytes of scratch", bytes);
+        }
+        want = bytes;
+    }
+    h->ws_size = want;
+    return RICI_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb)
+{
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rici_last_error(void) { return g_last_error.c_str(); }
+
+int rici_create(rici_handle* out, int device)
+{
+    if (!out) return fail(RICI_ERR_INVALID, "rici_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(RICI_ERR_UNSUPPORTED, "rici_create: no HIP device");
+    if (device < 0 || device >= count) return fail(RICI_ERR_INVALID, "rici_create: device %d of %d", device, count);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(RICI_ERR_UNSUPPORTED, "rici_create: device %d is %s, this library is built for gfx950",
+                    device, prop.gcnArchName);
+    DeviceGuard g(device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    rici_ctx* h = new rici_ctx();
+    h->device = device;
+    e = hipMalloc(&h->d_err, sizeof(uint32_t));
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipMalloc(error word)");
+    }
+    e = hipMemset(h->d_err, 0, sizeof(uint32_t));
+    if (e != hipSuccess) {
+        (void)hipFree(h->d_err);
+        delete h;
+        return hip_fail(e, "hipMemset(error word)");
+    }
+    // the search kernel needs more dynamic LDS than the default cap
+    // (set per function in launch_search; nothing to do here)
+    *out = h;
+    return RICI_OK;
+}
+
+void rici_destroy(rici_handle h)
+{
+    if (!h) return;
+    DeviceGuard g(h->device);
+    (void)hipDeviceSynchronize();
+    for (auto& t : h->launches) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    for (auto e : h->free_events) (void)hipEventDestroy(e);
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->d_err) (void)hipFree(h->d_err);
+    delete h;
+}
+
+int rici_sync(rici_handle h, void* stream)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_sync: NULL handle");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    uint32_t word = 0;
+    e = hipMemcpy(&word, h->d_err, sizeof word, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(error word)");
+    h->last_dev_err = word;
+    if (word) {
+        e = hipMemset(h->d_err, 0, sizeof(uint32_t));
+        if (e != hipSuccess) return hip_fail(e, "hipMemset(error word)");
+        return fail(RICI_ERR_DEVICE, "device reported bad input:%s%s",
+                    (word & RICI_DEVERR_INDEX) ? " triangle index out of range" : "",
+                    (word & RICI_DEVERR_NONFINITE) ? " non-finite coordinate" : "");
+    }
+    return RICI_OK;
+}
+
+uint32_t rici_device_errors(rici_handle h) { return h ? h->last_dev_err : 0u; }
+
+int rici_generate(rici_handle h, const float* positions, uint32_t num_vertices, const uint32_t* triangles,
+                  uint32_t num_triangles, const float* op_positions, const float* op_normals, uint32_t num_points,
+                  float support_radius, uint32_t* out_images, void* stream)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_generate: NULL handle");
+    if (!(isfinite(support_radius) && support_radius > 0.0f))
+        return fail(RICI_ERR_INVALID, "rici_generate: support_radius must be finite and > 0");
+    if (num_triangles >= (1u << 29)) return fail(RICI_ERR_UNSUPPORTED, "rici_generate: num_triangles >= 2^29");
+    if (num_points >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "rici_generate: num_points >= 2^31");
+    if (num_points == 0) return RICI_OK;
+    if (!op_positions || !op_normals || !out_images)
+        return fail(RICI_ERR_INVALID, "rici_generate: NULL oriented-point or output pointer");
+    if (num_triangles > 0 && (!triangles || !positions || num_vertices == 0))
+        return fail(RICI_ERR_INVALID, "rici_generate: NULL mesh pointer or no vertices");
+    const size_t out_bytes = (size_t)num_points * rici::NPIX * sizeof(uint32_t);
+    if (overlaps(out_images, out_bytes, positions, (size_t)num_vertices * 12) ||
+        overlaps(out_images, out_bytes, triangles, (size_t)num_triangles * 12) ||
+        overlaps(out_images, out_bytes, op_positions, (size_t)num_points * 12) ||
+        overlaps(out_images, out_bytes, op_normals, (size_t)num_points * 12))
+        return fail(RICI_ERR_INVALID, "rici_generate: output overlaps an input");
+
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t cull_bytes = align256((size_t)num_triangles * rici::kTriCullBytes);
+    const size_t vert_bytes = align256((size_t)num_triangles * rici::kTriVertBytes);
+    int rc = ensure_ws(h, cull_bytes + vert_bytes + 256);
+    if (rc) return rc;
+    float4* cull = (float4*)h->ws;
+    float4* verts = (float4*)((char*)h->ws + cull_bytes);
+    hipError_t e = timed(h, "gen_prep", s, [&] {
+        return rici::launch_gen_prep(positions, num_vertices, triangles, num_triangles, cull, verts, h->d_err, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "gen_prep launch");
+    e = timed(h, "gen", s, [&] {
+        return rici::launch_gen(cull, verts, num_triangles, op_positions, op_normals, num_points, support_radius,
+                                out_images, h->d_err, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "gen launch");
+    return RICI_OK;
+}
+
+namespace {
+
+struct SearchScratch {
+    rici::SearchPrep np, hp;
+    int32_t* thr = nullptr;
+    int64_t* dstar = nullptr;
+    uint32_t* lists = nullptr;
+};
+
+int search_scratch(rici_ctx* h, uint32_t nn, uint32_t nh, bool want_dstar, SearchScratch& S)
+{
+    const size_t ga = rici::search_groups(nn), gb = rici::search_groups(nh);
+    const size_t a_planes = align256(2 * ga * rici::kPlaneGroupBytes);
+    const size_t b_planes = align256(3 * gb * rici::kPlaneGroupBytes);
+    const size_t sumsq = align256(ga * rici::kGroup * sizeof(int64_t));
+    const size_t nmax = align256(ga * rici::kGroup * sizeof(uint32_t));
+    const size_t hmax = align256(gb * rici::kGroup * sizeof(uint32_t));
+    const size_t thr = align256((size_t)nn * sizeof(int32_t));
+    const size_t dstar = want_dstar ? align256((size_t)nn * sizeof(int64_t)) : 0;
+    const size_t lists = align256((2 + (size_t)nn + nh) * sizeof(uint32_t));
+    const size_t total = a_planes + b_planes + sumsq + nmax + hmax + thr + dstar + lists;
+    int rc = ensure_ws(h, total);
+    if (rc) return rc;
+    char* p = (char*)h->ws;
+    S.np.planes = (int8_t*)p; p += a_planes;
+    S.hp.planes = (int8_t*)p; p += b_planes;
+    S.np.sumsq = (int64_t*)p; p += sumsq;
+    S.hp.sumsq = nullptr;
+    S.np.maxabs = (uint32_t*)p; p += nmax;
+    S.hp.maxabs = (uint32_t*)p; p += hmax;
+    S.thr = (int32_t*)p; p += thr;
+    S.dstar = want_dstar ? (int64_t*)p : nullptr; p += dstar;
+    S.lists = (uint32_t*)p;
+    S.np.ngroups = (uint32_t)ga;
+    S.hp.ngroups = (uint32_t)gb;
+    return RICI_OK;
+}
+
+int check_search_args(const char* fn, const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh)
+{
+    if (nn > 0 && !needles) return fail(RICI_ERR_INVALID, "%s: NULL needles", fn);
+    if (nh == 0 && nn > 0) return fail(RICI_ERR_INVALID, "%s: empty haystack", fn);
+    if (nh > 0 && !hay) return fail(RICI_ERR_INVALID, "%s: NULL haystack", fn);
+    if (nn >= (1u << 31) || nh >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "%s: more than 2^31 images", fn);
+    return RICI_OK;
+}
+
+int prep_both(rici_ctx* h, SearchScratch& S, const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
+              hipStream_t s)
+{
+    hipError_t e = timed(h, "delta_needle", s, [&] { return rici::launch_delta_prep(needles, nn, 1, S.np, s); });
+    if (e != hipSuccess) return hip_fail(e, "delta_needle launch");
+    e = timed(h, "delta_haystack", s, [&] { return rici::launch_delta_prep(hay, nh, 0, S.hp, s); });
+    if (e != hipSuccess) return hip_fail(e, "delta_haystack launch");
+    return RICI_OK;
+}
+
+}  // namespace
+
+int rici_distance_rank(rici_handle h, const uint32_t* needles, uint32_t num_needles, const uint32_t* haystack,
+                       uint32_t num_haystack, const uint32_t* true_index, uint32_t* out_rank,
+                       int64_t* out_true_distance, void* stream)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_distance_rank: NULL handle");
+    int rc = check_search_args("rici_distance_rank", needles, num_needles, haystack, num_haystack);
+    if (rc) return rc;
+    if (num_needles == 0) return RICI_OK;
+    if (!true_index || !out_rank) return fail(RICI_ERR_INVALID, "rici_distance_rank: NULL true_index or out_rank");
+    const size_t nb = (size_t)num_needles;
+    const size_t img_n = nb * rici::NPIX * 4, img_h = (size_t)num_haystack * rici::NPIX * 4;
+    if (overlaps(out_rank, nb * 4, needles, img_n) || overlaps(out_rank, nb * 4, haystack, img_h) ||
+        overlaps(out_rank, nb * 4, true_index, nb * 4) ||
+        (out_true_distance && (overlaps(out_true_distance, nb * 8, needles, img_n) ||
+                               overlaps(out_true_distance, nb * 8, haystack, img_h) ||
+                               overlaps(out_true_distance, nb * 8, out_rank, nb * 4) ||
+                               overlaps(out_true_distance, nb * 8, true_index, nb * 4))))
+        return fail(RICI_ERR_INVALID, "rici_distance_rank: an output overlaps another array");
+
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    SearchScratch S;
+    rc = search_scratch(h, num_needles, num_haystack, out_true_distance == nullptr, S);
+    if (rc) return rc;
+    int64_t* dstar = out_true_distance ? out_true_distance : S.dstar;
+    rc = prep_both(h, S, needles, num_needles, haystack, num_haystack, s);
+    if (rc) return rc;
+    hipError_t e = timed(h, "true_distance", s, [&] {
+        return rici::launch_true_distance(needles, num_needles, haystack, num_haystack, true_index, S.np.sumsq,
+                                          S.np.maxabs, dstar, S.thr, out_rank, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "true_distance launch");
+    e = timed(h, "search", s, [&] {
+        return rici::launch_search(S.np, num_needles, S.hp, num_haystack, S.thr, S.np.sumsq, out_rank, nullptr, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "search launch");
+    e = timed(h, "fallback", s, [&] {
+        return rici::launch_fallback(needles, num_needles, haystack, num_haystack, S.np.maxabs, S.hp.maxabs, dstar,
+                                     out_rank, nullptr, S.lists, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "fallback launch");
+    return RICI_OK;
+}
+
+int rici_distance_matrix(rici_handle h, const uint32_t* needles, uint32_t num_needles, const uint32_t* haystack,
+                         uint32_t num_haystack, int64_t* out, void* stream)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_distance_matrix: NULL handle");
+    int rc = check_search_args("rici_distance_matrix", needles, num_needles, haystack, num_haystack);
+    if (rc) return rc;
+    if (num_needles == 0) return RICI_OK;
+    if (!out) return fail(RICI_ERR_INVALID, "rici_distance_matrix: NULL out");
+    const size_t ob = (size_t)num_needles * num_haystack * 8;
+    if (overlaps(out, ob, needles, (size_t)num_needles * rici::NPIX * 4) ||
+        overlaps(out, ob, haystack, (size_t)num_haystack * rici::NPIX * 4))
+        return fail(RICI_ERR_INVALID, "rici_distance_matrix: output overlaps an input");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    SearchScratch S;
+    rc = search_scratch(h, num_needles, num_haystack, false, S);
+    if (rc) return rc;
+    rc = prep_both(h, S, needles, num_needles, haystack, num_haystack, s);
+    if (rc) return rc;
+    hipError_t e = timed(h, "matrix", s, [&] {
+        return rici::launch_search(S.np, num_needles, S.hp, num_haystack, nullptr, S.np.sumsq, nullptr, out, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "matrix launch");
+    e = timed(h, "fallback", s, [&] {
+        return rici::launch_fallback(needles, num_needles, haystack, num_haystack, S.np.maxabs, S.hp.maxabs, nullptr,
+                                     nullptr, out, S.lists, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "fallback launch");
+    return RICI_OK;
+}
+
+int rici_timing_enable(rici_handle h, int on)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_timing_enable: NULL handle");
+    h->timing = on != 0;
+    return RICI_OK;
+}
+
+int rici_timing_reset(rici_handle h)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_timing_reset: NULL handle");
+    DeviceGuard g(h->device);
+    (void)hipDeviceSynchronize();
+    for (auto& t : h->launches) {
+        h->free_events.push_back(t.start);
+        h->free_events.push_back(t.stop);
+    }
+    h->launches.clear();
+    return RICI_OK;
+}
+
+int rici_timing_get(rici_handle h, const char* kernel, double* total_ms, uint64_t* launches)
+{
+    if (!h || !kernel || !total_ms || !launches) return fail(RICI_ERR_INVALID, "rici_timing_get: NULL argument");
+    DeviceGuard g(h->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    double sum = 0.0;
+    uint64_t n = 0;
+    for (auto& t : h->launches) {
+        if (strcmp(t.name, kernel) != 0) continue;
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, t.start, t.stop);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        sum += ms;
+        ++n;
+    }
+    *total_ms = sum;
+    *launches = n;
+    return RICI_OK;
+}
+
+}  // extern "C"

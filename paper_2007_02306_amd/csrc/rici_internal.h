@@ -1,0 +1,60 @@
+// Internal declarations shared by the HIP translation units of librici.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rici {
+
+constexpr int NB = 64;              // bins per image side (64 x 64 images)
+constexpr int NPIX = NB * NB;       // pixels per image
+
+// ---------------------------------------------------------------- generation
+// Scratch per triangle: a conservative bounding sphere (cx, cy, cz, radius) and
+// the three vertices as float4 (w unused).
+constexpr size_t kTriCullBytes = 16;
+constexpr size_t kTriVertBytes = 48;
+
+hipError_t launch_gen_prep(const float* pos, uint32_t nv, const uint32_t* tri, uint32_t nt,
+                           float4* cull, float4* verts, uint32_t* err, hipStream_t s);
+hipError_t launch_gen(const float4* cull, const float4* verts, uint32_t nt,
+                      const float* op_pos, const float* op_nrm, uint32_t n, float R,
+                      uint32_t* out, uint32_t* err, hipStream_t s);
+
+// -------------------------------------------------------------------- search
+// Column-delta planes in "fragment-major" order: for every group of 16 images
+// and every image row (64 deltas = one 64-wide K chunk), the 16 x 64 int8 values
+// sit in 1 KiB exactly as the 64 lanes of one v_mfma_i32_16x16x64_i8 operand
+// read them: lane l = 16 * (c / 16) + (image % 16) holds columns c .. c + 15.
+constexpr int kGroup = 16;                       // images per fragment group
+constexpr size_t kFragBytes = 1024;              // 16 images x 64 columns
+constexpr size_t kPlaneGroupBytes = NB * kFragBytes;   // one group, all 64 rows
+
+// needle planes: 0 = -D (int8), 1 = mask [D != 0] (0/1)
+// haystack planes: 0 = D, 1 = D^2 mod 128, 2 = D^2 / 128
+struct SearchPrep {
+    int8_t* planes;        // [nplanes][ngroups][64][1024]
+    int64_t* sumsq;        // needles: |D|^2 per image
+    uint32_t* maxabs;      // max |D| per image (saturating)
+    uint32_t ngroups;      // ceil(n / 16) rounded up to the search tile
+};
+
+hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side,
+                             const SearchPrep& p, hipStream_t s);
+hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
+                                const uint32_t* true_idx, const int64_t* sumsq, const uint32_t* nmax,
+                                int64_t* dstar, int32_t* thr, uint32_t* rank, hipStream_t s);
+hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
+                         const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix,
+                         hipStream_t s);
+// `lists` scratch: 2 + nn + nh uint32
+hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
+                           const uint32_t* nmax, const uint32_t* hmax, const int64_t* dstar,
+                           uint32_t* rank, int64_t* matrix, uint32_t* lists, hipStream_t s);
+
+size_t search_groups(uint32_t n);   // fragment groups allocated for n images
+size_t search_lds_bytes();          // dynamic LDS of the search kernel
+uint32_t search_tile_m();
+uint32_t search_tile_n();
+
+}  // namespace rici

@@ -1,0 +1,478 @@
+// Clutter-resistant distance (CRD) search for gfx950 (Sec. 3.2, Eq. 6-7) and
+// the rank of the true match (Sec. 4.1 step 6c, ties to the best rank).
+//
+// The masked sum of Eq. 7 is split into contractions (exact, because the
+// needle mask m = [D_n != 0] times D_n is D_n):
+//     CRD(n, h) = |D_n|^2 - 2 <D_n, D_h> + <m_n, D_h^2>.
+// |D_n|^2 is one number per needle, so a (needle, haystack) pair costs two
+// length-4096 int8 dot products -- a dense int8 x int8 -> int32 GEMM over all
+// pairs, which is what MFMA does best.  Operands stay exact int8 under a range
+// check: needles with |D| <= 127 use planes (-D_n, m_n); haystack images with
+// |D| <= 127 use (D_h, D_h^2 mod 128, D_h^2 div 128).  The accumulator is
+// scaled between phases so a single int32 accumulator holds
+//     128 <m, q> ... (x64) ... - <D_n, D_h> ... (x2) ... + <m, r>
+//   = <m, D_h^2> - 2 <D_n, D_h>          with D_h^2 = 128 q + r,
+// and the q phase is skipped for haystack tiles where every |D_h| <= 11.
+// All partial sums stay below 2^31 (4032 * 127^2 * 3 < 2^31).  Any image
+// outside the int8 range goes to an exact int64 VALU path instead.
+//
+// Ranking never sorts: rank_i = #{ h : CRD(n_i, h) < CRD(n_i, h_true) } is a
+// sum of per-tile counts, so tiles add their counts with integer atomics and
+// the result is exact and independent of the order of tiles.
+#include "rici_internal.h"
+
+#include <limits.h>
+
+namespace rici {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kSlow = 127;     // largest |D| an int8 operand holds
+constexpr uint32_t kSmallD = 11;    // |D| <= 11  =>  D^2 <= 121 fits int8 directly
+constexpr uint32_t kPad = 0xFFFFFFFFu;
+
+// ------------------------------------------------------------------ delta prep
+
+// One block per group of 16 images; thread (row-in-step, lane) with
+// lane = 16 * q + i writes columns 16 q .. 16 q + 15 of image i.
+__global__ void __launch_bounds__(256)
+k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
+             int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
+             uint32_t* __restrict__ maxabs)
+{
+    __shared__ uint32_t smax[4][kGroup];
+    __shared__ int64_t ssum[4][kGroup];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t grp = blockIdx.x;
+    const int i = lane & 15, q = lane >> 4;
+    const uint32_t img = grp * kGroup + i;
+    const bool live = img < n;
+    const size_t plane_stride = (size_t)ngroups * kPlaneGroupBytes;
+
+    uint32_t mx = 0;
+    int64_t ss = 0;
+    for (int r = wave; r < NB; r += 4) {
+        int32_t d[16];
+        if (live) {
+            const uint32_t* row = images + (size_t)img * NPIX + r * NB + 16 * q;
+            const uint4* row4 = reinterpret_cast<const uint4*>(row);
+            uint32_t v[17];
+            v[0] = q > 0 ? row[-1] : 0u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                uint4 u = row4[k];
+                v[1 + 4 * k] = u.x; v[2 + 4 * k] = u.y; v[3 + 4 * k] = u.z; v[4 + 4 * k] = u.w;
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                // Eq. 6 in signed 64-bit; column 0 has no left neighbour and no term
+                int64_t dd = (q == 0 && k == 0) ? 0 : (int64_t)v[k + 1] - (int64_t)v[k];
+                uint64_t a = dd < 0 ? (uint64_t)(-dd) : (uint64_t)dd;
+                mx = (uint32_t)max((uint64_t)mx, min(a, (uint64_t)0xFFFFFFFEu));
+                ss += dd * dd;
+                d[k] = (int32_t)max(min(dd, (int64_t)127), (int64_t)-127);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) d[k] = 0;
+        }
+        // pack into the fragment-major planes
+        const size_t frag = ((size_t)grp * NB + r) * kFragBytes + (size_t)lane * 16;
+        uint32_t w0[4], w1[4], w2[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint32_t a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int32_t x = d[4 * k + b];
+                const uint32_t sq = (uint32_t)(x * x);
+                uint32_t p0, p1, p2;
+                if (needle_side) {
+                    p0 = (uint32_t)(uint8_t)(int8_t)(-x);
+                    p1 = x != 0 ? 1u : 0u;
+                    p2 = 0u;
+                } else {
+                    p0 = (uint32_t)(uint8_t)(int8_t)x;
+                    p1 = sq & 127u;
+                    p2 = sq >> 7;
+                }
+                a0 |= p0 << (8 * b); a1 |= p1 << (8 * b); a2 |= p2 << (8 * b);
+            }
+            w0[k] = a0; w1[k] = a1; w2[k] = a2;
+        }
+        *reinterpret_cast<uint4*>(planes + frag) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+        *reinterpret_cast<uint4*>(planes + plane_stride + frag) = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+        if (!needle_side)
+            *reinterpret_cast<uint4*>(planes + 2 * plane_stride + frag) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
+    }
+    // per-image reductions: 4 lanes (q) per wave and 4 waves share image i
+#pragma unroll
+    for (int o = 16; o < 64; o <<= 1) {
+        mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+        ss += __shfl_xor(ss, o, 64);
+    }
+    if (q == 0) { smax[wave][i] = mx; ssum[wave][i] = ss; }
+    __syncthreads();
+    if (tid < kGroup) {
+        const uint32_t im = grp * kGroup + tid;
+        uint32_t m = max(max(smax[0][tid], smax[1][tid]), max(smax[2][tid], smax[3][tid]));
+        int64_t s = ssum[0][tid] + ssum[1][tid] + ssum[2][tid] + ssum[3][tid];
+        maxabs[im] = im < n ? m : kPad;
+        if (sumsq) sumsq[im] = im < n ? s : 0;
+    }
+}
+
+// ------------------------------------------------------------ exact int64 CRD
+
+// CRD(n, h) by Eq. 7 for one pair, summed by one wavefront: lane = column.
+__device__ __forceinline__ int64_t crd_wave(const uint32_t* __restrict__ nimg, const uint32_t* __restrict__ himg,
+                                            int lane)
+{
+    int64_t s = 0;
+    for (int r = 0; r < NB; ++r) {
+        const int64_t a = nimg[r * NB + lane], b = himg[r * NB + lane];
+        const int64_t ap = __shfl_up(a, 1, 64), bp = __shfl_up(b, 1, 64);
+        if (lane > 0) {
+            const int64_t dn = a - ap, dh = b - bp;
+            if (dn != 0) s += (dn - dh) * (dn - dh);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
+}
+
+// d*_i = CRD(n_i, h_true(i)); MFMA threshold thr_i = d*_i - |D_n|^2 (clamped;
+// INT_MIN disables the MFMA count for needles outside the int8 range and for a
+// bad true index); rank zeroed.
+__global__ void __launch_bounds__(256)
+k_true_distance(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_t* __restrict__ hay, uint32_t nh,
+                const uint32_t* __restrict__ true_idx, const int64_t* __restrict__ sumsq,
+                const uint32_t* __restrict__ nmax, int64_t* __restrict__ dstar, int32_t* __restrict__ thr,
+                uint32_t* __restrict__ rank)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= nn) return;
+    const uint32_t t = true_idx[i];
+    if (t >= nh) {
+        if (lane == 0) { dstar[i] = -1; thr[i] = INT_MIN; rank[i] = nh; }
+        return;
+    }
+    const int64_t d = crd_wave(needles + (size_t)i * NPIX, hay + (size_t)t * NPIX, lane);
+    if (lane == 0) {
+        dstar[i] = d;
+        int64_t th = d - sumsq[i];
+        th = min(max(th, (int64_t)INT_MIN + 1), (int64_t)INT_MAX);
+        thr[i] = nmax[i] <= kSlow ? (int32_t)th : INT_MIN;
+        rank[i] = 0;
+    }
+}
+
+// ----------------------------------------------------------------- MFMA search
+
+template <int WM, int WN, int MB, int NBK, int KC>
+struct SearchCfg {
+    static constexpr int kWM = WM, kWN = WN, kMB = MB, kNBK = NBK, kKC = KC;
+    static constexpr int kWaves = WM * WN;
+    static constexpr int kThreads = kWaves * 64;
+    static constexpr int BM = WM * MB * 16;          // needles per tile
+    static constexpr int BN = WN * NBK * 16;         // haystack images per tile
+    static constexpr int GA = BM / 16, GB = BN / 16; // fragment groups per tile
+    static constexpr int kStageA = GA * KC * (int)kFragBytes;
+    static constexpr int kStageB = GB * KC * (int)kFragBytes;
+    static constexpr int kStage = kStageA + kStageB;
+    static constexpr int kLoads = kStage / (16 * kThreads);   // 16 B loads per thread per stage
+    static constexpr int kSPP = NB / KC;                      // stages per phase (64 rows)
+    static_assert(kStage % (16 * kThreads) == 0, "stage must split evenly");
+    static_assert(NB % KC == 0, "KC must divide 64");
+};
+
+// 256 x 256 (needle x haystack) tile, 8 waves of 128 x 64, one K row (64 deltas) per stage
+using Cfg = SearchCfg<2, 4, 8, 4, 1>;
+
+struct SearchArgs {
+    const int8_t* a_planes; uint32_t a_groups; uint32_t nn;
+    const int8_t* b_planes; uint32_t b_groups; uint32_t nh;
+    const uint32_t* nmax;
+    const uint32_t* hmax;
+    const int32_t* thr;
+    const int64_t* sumsq;
+    uint32_t* rank;
+    int64_t* matrix;
+    uint32_t tiles_m, tiles_n, per_xcd;
+};
+
+template <class C>
+__global__ void __launch_bounds__(C::kThreads)
+k_search(SearchArgs A)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / C::kWN, wn = wave % C::kWN;
+
+    // Tile order: consecutive workgroup ids land on different XCDs (round
+    // robin), so first gather each XCD's ids into one contiguous range, then
+    // walk that range in groups of 8 needle tiles so the tiles resident on one
+    // XCD share needle and haystack fragments in its L2.
+    const uint32_t b = blockIdx.x;
+    const uint32_t logical = (b & 7u) * A.per_xcd + (b >> 3);
+    if (logical >= A.tiles_m * A.tiles_n) return;
+    constexpr uint32_t GM = 8;
+    const uint32_t in_group = GM * A.tiles_n;
+    const uint32_t first_m = (logical / in_group) * GM;
+    const uint32_t gsz = min(A.tiles_m - first_m, GM);
+    const uint32_t tm = first_m + (logical % in_group) % gsz;
+    const uint32_t tn = (logical % in_group) / gsz;
+    const uint32_t ga0 = tm * C::GA, gb0 = tn * C::GB;
+
+    // q phase needed iff some usable haystack image of the tile has 11 < |D| <= 127
+    int need_q = 0;
+    for (int j = tid; j < C::BN; j += C::kThreads) {
+        const uint32_t m = A.hmax[gb0 * 16 + j];
+        need_q |= (m > kSmallD && m <= kSlow) ? 1 : 0;
+    }
+    const bool hq = __syncthreads_or(need_q) != 0;
+    const int nphase = hq ? 3 : 2;
+    const int nstage = nphase * C::kSPP;
+
+    const size_t a_ps = (size_t)A.a_groups * kPlaneGroupBytes;
+    const size_t b_ps = (size_t)A.b_groups * kPlaneGroupBytes;
+
+    // Stage layout in LDS: A = [GA groups][KC rows][1 KiB], then B likewise.
+    // Thread tid copies the 16-byte chunks tid + k * kThreads; which operand a
+    // chunk belongs to is known at compile time (kStageA is a multiple of the
+    // per-k stride).
+    static_assert(C::kStageA % (16 * C::kThreads) == 0, "A part must split evenly");
+    constexpr int kLoadsA = C::kStageA / (16 * C::kThreads);
+    constexpr int kGroupSpan = C::kKC * (int)kFragBytes;   // bytes of one group per stage
+    const int8_t* a_tile = A.a_planes + (size_t)ga0 * kPlaneGroupBytes;
+    const int8_t* b_tile = A.b_planes + (size_t)gb0 * kPlaneGroupBytes;
+
+    auto chunk_src = [&](int k, int s, bool hqv) -> const int8_t* {
+        const int p = s / C::kSPP;
+        // phase -> plane: needle planes 0 = -D, 1 = mask; haystack planes
+        // 0 = D, 1 = D^2 mod 128, 2 = D^2 div 128
+        const int pa = hqv ? ((p == 1) ? 0 : 1) : p;
+        const int pb = hqv ? ((p == 0) ? 2 : (p == 1 ? 0 : 1)) : p;
+        const size_t row_off = (size_t)((s % C::kSPP) * C::kKC) * kFragBytes;
+        const int off = (tid + k * C::kThreads) * 16;
+        if (k < kLoadsA) {
+            const int g = off / kGroupSpan, rem = off % kGroupSpan;
+            return a_tile + (size_t)pa * a_ps + (size_t)g * kPlaneGroupBytes + row_off + rem;
+        }
+        const int o2 = off - C::kStageA;
+        const int g = o2 / kGroupSpan, rem = o2 % kGroupSpan;
+        return b_tile + (size_t)pb * b_ps + (size_t)g * kPlaneGroupBytes + row_off + rem;
+    };
+    v4i acc[C::kMB][C::kNBK];
+#pragma unroll
+    for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = v4i{0, 0, 0, 0};
+
+    v4i stg[C::kLoads];
+#pragma unroll
+    for (int k = 0; k < C::kLoads; ++k) stg[k] = *reinterpret_cast<const v4i*>(chunk_src(k, 0, hq));
+#pragma unroll
+    for (int k = 0; k < C::kLoads; ++k) *reinterpret_cast<v4i*>(lds + (tid + k * C::kThreads) * 16) = stg[k];
+    __syncthreads();
+
+    for (int s = 0; s < nstage; ++s) {
+        if (s + 1 < nstage) {
+#pragma unroll
+            for (int k = 0; k < C::kLoads; ++k) stg[k] = *reinterpret_cast<const v4i*>(chunk_src(k, s + 1, hq));
+        }
+        if (s > 0 && s % C::kSPP == 0) {
+            // end of a phase: scale the partial sum (x64 after q, x2 after -D.D)
+            const int p = s / C::kSPP;
+            const int sh = (hq && p == 1) ? 6 : 1;
+#pragma unroll
+            for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << sh;
+        }
+        const int8_t* sA = lds + (s & 1) * C::kStage;
+        const int8_t* sB = sA + C::kStageA;
+#pragma unroll
+        for (int kc = 0; kc < C::kKC; ++kc) {
+            v4i fb[C::kNBK];
+#pragma unroll
+            for (int nb = 0; nb < C::kNBK; ++nb)
+                fb[nb] = *reinterpret_cast<const v4i*>(sB + ((wn * C::kNBK + nb) * C::kKC + kc) * (int)kFragBytes + lane * 16);
+#pragma unroll
+            for (int mb = 0; mb < C::kMB; ++mb) {
+                const v4i fa = *reinterpret_cast<const v4i*>(sA + ((wm * C::kMB + mb) * C::kKC + kc) * (int)kFragBytes + lane * 16);
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa, fb[nb], acc[mb][nb], 0, 0, 0);
+            }
+        }
+        if (s + 1 < nstage) {
+            int8_t* dst = lds + ((s + 1) & 1) * C::kStage;
+#pragma unroll
+            for (int k = 0; k < C::kLoads; ++k) *reinterpret_cast<v4i*>(dst + (tid + k * C::kThreads) * 16) = stg[k];
+        }
+        __syncthreads();
+    }
+
+    // Epilogue.  16x16 accumulator layout: lane l holds column l % 16 and
+    // rows 4 * (l / 16) + v of its block, v = 0..3.
+    const int cl = lane & 15, rq = lane >> 4;
+    bool colok[C::kNBK];
+    uint32_t col[C::kNBK];
+#pragma unroll
+    for (int nb = 0; nb < C::kNBK; ++nb) {
+        col[nb] = (gb0 + wn * C::kNBK + nb) * 16 + cl;
+        colok[nb] = col[nb] < A.nh && A.hmax[col[nb]] <= kSlow;
+    }
+#pragma unroll
+    for (int mb = 0; mb < C::kMB; ++mb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t row = (ga0 + wm * C::kMB + mb) * 16 + 4 * rq + v;
+            const bool rowok = row < A.nn;
+            if (A.matrix) {
+                if (rowok && A.nmax[row] <= kSlow) {
+                    const int64_t base = A.sumsq[row];
+#pragma unroll
+                    for (int nb = 0; nb < C::kNBK; ++nb)
+                        if (colok[nb]) A.matrix[(size_t)row * A.nh + col[nb]] = base + (int64_t)acc[mb][nb][v];
+                }
+            } else {
+                const int32_t t = rowok ? A.thr[row] : INT_MIN;
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; ++nb) cnt += (colok[nb] && acc[mb][nb][v] < t) ? 1u : 0u;
+                cnt += __shfl_xor(cnt, 1, 64);
+                cnt += __shfl_xor(cnt, 2, 64);
+                cnt += __shfl_xor(cnt, 4, 64);
+                cnt += __shfl_xor(cnt, 8, 64);
+                if (cl == 0 && rowok && cnt) atomicAdd(A.rank + row, cnt);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------- out-of-range images
+
+// lists[0] = #needles with |D| > 127, lists[1] = #haystack images with
+// |D| > 127, then the needle ids (nn slots) and the haystack ids (nh slots).
+__global__ void __launch_bounds__(1024)
+k_slow_lists(const uint32_t* __restrict__ nmax, uint32_t nn, const uint32_t* __restrict__ hmax, uint32_t nh,
+             uint32_t* __restrict__ lists)
+{
+    __shared__ uint32_t cn, ch;
+    if (threadIdx.x == 0) { cn = 0; ch = 0; }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nn; i += blockDim.x)
+        if (nmax[i] > kSlow) lists[2 + atomicAdd(&cn, 1u)] = i;
+    for (uint32_t j = threadIdx.x; j < nh; j += blockDim.x)
+        if (hmax[j] > kSlow) lists[2 + (size_t)nn + atomicAdd(&ch, 1u)] = j;
+    __syncthreads();
+    if (threadIdx.x == 0) { lists[0] = cn; lists[1] = ch; }
+}
+
+// Every (needle, haystack) pair with an out-of-range image, by Eq. 7 in int64.
+// A fixed grid of wavefronts walks the pair list; the list length is bounded
+// by nn * nh, so every wave reaches the end.
+__global__ void __launch_bounds__(256)
+k_fallback(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_t* __restrict__ hay, uint32_t nh,
+           const uint32_t* __restrict__ nmax, const uint32_t* __restrict__ lists,
+           const int64_t* __restrict__ dstar, uint32_t* __restrict__ rank, int64_t* __restrict__ matrix)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t ns = lists[0], nhs = lists[1];
+    const uint64_t part_a = ns * nh, total = part_a + nhs * nn;
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t w = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < total; w += nwaves) {
+        uint32_t i, j;
+        if (w < part_a) {
+            i = lists[2 + w / nh];
+            j = (uint32_t)(w % nh);
+        } else {
+            const uint64_t w2 = w - part_a;
+            j = lists[2 + (size_t)nn + w2 / nn];
+            i = (uint32_t)(w2 % nn);
+            if (nmax[i] > kSlow) continue;   // already done in part A
+        }
+        const int64_t d = crd_wave(needles + (size_t)i * NPIX, hay + (size_t)j * NPIX, lane);
+        if (lane == 0) {
+            if (matrix) matrix[(size_t)i * nh + j] = d;
+            else if (dstar[i] >= 0 && d < dstar[i]) atomicAdd(rank + i, 1u);
+        }
+    }
+}
+
+}  // namespace
+
+size_t search_groups(uint32_t n)
+{
+    const size_t g = (n + kGroup - 1) / kGroup;
+    const size_t t = Cfg::GA > Cfg::GB ? Cfg::GA : Cfg::GB;
+    return ((g + t - 1) / t) * t;
+}
+
+hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side, const SearchPrep& p,
+                             hipStream_t s)
+{
+    if (p.ngroups == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_delta_prep, dim3(p.ngroups), dim3(256), 0, s, images, n, needle_side, p.planes, p.ngroups,
+                       p.sumsq, p.maxabs);
+    return hipGetLastError();
+}
+
+hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
+                                const uint32_t* true_idx, const int64_t* sumsq, const uint32_t* nmax,
+                                int64_t* dstar, int32_t* thr, uint32_t* rank, hipStream_t s)
+{
+    if (nn == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_true_distance, dim3((nn + 3) / 4), dim3(256), 0, s, needles, nn, hay, nh, true_idx, sumsq,
+                       nmax, dstar, thr, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
+                         const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix, hipStream_t s)
+{
+    if (nn == 0 || nh == 0) return hipSuccess;
+    SearchArgs A;
+    A.a_planes = np.planes; A.a_groups = np.ngroups; A.nn = nn;
+    A.b_planes = hp.planes; A.b_groups = hp.ngroups; A.nh = nh;
+    A.nmax = np.maxabs; A.hmax = hp.maxabs;
+    A.thr = thr; A.sumsq = sumsq; A.rank = rank; A.matrix = matrix;
+    A.tiles_m = (nn + Cfg::BM - 1) / Cfg::BM;
+    A.tiles_n = (nh + Cfg::BN - 1) / Cfg::BN;
+    const uint32_t total = A.tiles_m * A.tiles_n;
+    A.per_xcd = (total + 7) / 8;
+    const size_t lds = 2 * (size_t)Cfg::kStage;
+    static bool lds_raised = false;   // per process; the attribute is per function
+    if (!lds_raised) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<Cfg>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        lds_raised = true;
+    }
+    hipLaunchKernelGGL(k_search<Cfg>, dim3(8 * A.per_xcd), dim3(Cfg::kThreads), lds, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
+                           const uint32_t* nmax, const uint32_t* hmax, const int64_t* dstar,
+                           uint32_t* rank, int64_t* matrix, uint32_t* lists, hipStream_t s)
+{
+    if (nn == 0 || nh == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slow_lists, dim3(1), dim3(1024), 0, s, nmax, nn, hmax, nh, lists);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fallback, dim3(512), dim3(256), 0, s, needles, nn, hay, nh, nmax, lists, dstar, rank,
+                       matrix);
+    return hipGetLastError();
+}
+
+size_t search_lds_bytes() { return 2 * (size_t)Cfg::kStage; }
+uint32_t search_tile_m() { return Cfg::BM; }
+uint32_t search_tile_n() { return Cfg::BN; }
+
+}  // namespace rici

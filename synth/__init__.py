@@ -19,6 +19,7 @@ from .meshes import (  # noqa: F401
     transform,
     concat,
 )
+from .images import step_images, perturb  # noqa: F401
 from .configs import (  # noqa: F401
     Scene,
     config1_icosphere,

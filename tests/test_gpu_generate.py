@@ -1,0 +1,166 @@
+"""GPU parity of RICI generation (rici_generate) against the FP64 oracle and
+closed forms: bit-exact at every pixel the oracle does not flag as degenerate."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_images_match, dev_f32, dev_u32, gpu_images, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2007_02306_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def test_config1_every_image(ctx):
+    s = synth.config1_icosphere()
+    g = gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    o, fl, _ = oracle.rici_rowrange(s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    assert_images_match(g, o, fl, "icosphere")
+    assert g.max() > 0
+
+
+@pytest.mark.parametrize("seed,n", [(0, 1), (1, 7), (2, 8), (3, 9), (4, 23), (5, 64)])
+def test_tiny_random_scenes(ctx, seed, n):
+    rng = np.random.default_rng(500 + seed)
+    nt = int(rng.integers(1, 300))
+    pts = rng.uniform(-1, 1, size=(3 * nt, 3)).astype(np.float32)
+    tri = np.arange(3 * nt, dtype=np.uint32).reshape(nt, 3)
+    opp = rng.uniform(-0.5, 0.5, size=(n, 3)).astype(np.float32)
+    opn = rng.normal(size=(n, 3)).astype(np.float32)
+    R = float(rng.uniform(0.3, 2.0))
+    g = gpu_images(ctx, pts, tri, opp, opn, R)
+    o, fl, _ = oracle.rici_rowrange(pts, tri, opp, opn, R)
+    assert_images_match(g, o, fl, f"random scene {seed}")
+
+
+def test_config2_sampled_at_full_size(ctx):
+    """The benchmark workload (union of 12 superquadrics, 23 352 images over
+    46 656 triangles) in one launch; a seeded sample checked one by one."""
+    s = synth.config2_union12()
+    g = gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    n = s.num_haystack
+    rng = np.random.default_rng(22)
+    sel = np.unique(np.concatenate([[0, 1, n - 2, n - 1], (n // 8) * 8 + np.arange(min(8, n - (n // 8) * 8)),
+                                    rng.choice(n, 120, replace=False)]))
+    o, fl, _ = oracle.rici_rowrange(s.positions, s.triangles, s.op_positions[sel], s.op_normals[sel],
+                                    s.support_radius)
+    flagged = assert_images_match(g[sel], o, fl, "union12")
+    say(f"  union12: {len(sel)} sampled images, {flagged} flagged pixels")
+    assert g[sel].max() > 0
+    assert ((g % 2) == 0).mean() > 0.999   # closed surfaces give even counts
+
+
+def test_config3_clutter_sampled(ctx):
+    """Clutter scene (10 objects, ~0.7 M triangles): sampled haystack images and
+    sampled needle images (object 0 alone in canonical pose)."""
+    s = synth.config3_clutter()
+    rng = np.random.default_rng(33)
+    hsel = np.sort(rng.choice(s.num_haystack, 24, replace=False))
+    g = gpu_images(ctx, s.positions, s.triangles, s.op_positions[hsel], s.op_normals[hsel], s.support_radius)
+    o, fl, _ = oracle.rici_rowrange(s.positions, s.triangles, s.op_positions[hsel], s.op_normals[hsel],
+                                    s.support_radius)
+    assert_images_match(g, o, fl, "clutter haystack")
+    nsel = np.sort(rng.choice(s.num_needles, 24, replace=False))
+    g = gpu_images(ctx, s.needle_positions, s.needle_triangles, s.needle_op_positions[nsel],
+                   s.needle_op_normals[nsel], s.support_radius)
+    o, fl, _ = oracle.rici_rowrange(s.needle_positions, s.needle_triangles, s.needle_op_positions[nsel],
+                                    s.needle_op_normals[nsel], s.support_radius)
+    assert_images_match(g, o, fl, "clutter needles")
+
+
+def test_planar_square_closed_form(ctx):
+    L1, L2, b0, b1 = 0.7, 0.45, -0.31, 0.23
+    v = np.array([[-L1, 0, b0], [L2, 0, b0], [L2, 0, b1], [-L1, 0, b1]], np.float32)
+    t = np.array([[0, 1, 2], [0, 2, 3]], np.uint32)
+    g = gpu_images(ctx, v, t, np.zeros((1, 3), np.float32), np.array([[0, 0, 1]], np.float32), 1.0)
+    d = 1.0 / 64
+    rho = (np.arange(64) + 0.5) * d
+    beta = -0.5 + (np.arange(64) + 0.5) * d
+    L1f, L2f, b0f, b1f = (np.float64(np.float32(x)) for x in (L1, L2, b0, b1))
+    exp = ((beta > b0f) & (beta < b1f))[:, None] * ((rho < L1f).astype(int) + (rho < L2f).astype(int))[None, :]
+    assert np.array_equal(g[0], exp.astype(np.uint32))
+
+
+def test_off_axis_sphere_closed_form(ctx):
+    a, dist, q, R = 0.3, 0.1, 0.02, 1.0
+    m = synth.icosphere(5)
+    sv = np.array([0.1, -0.2, 0.3])
+    n = np.array([0.0, 0.0, 1.0])
+    pos = (m.positions * a + sv + q * n + dist * np.array([1.0, 0, 0])).astype(np.float32)
+    g = gpu_images(ctx, pos, m.triangles, sv.astype(np.float32)[None], n.astype(np.float32)[None], R)
+    rho = (np.arange(64) + 0.5) / 64
+    beta = -0.5 + (np.arange(64) + 0.5) / 64
+    B, P = np.meshgrid(beta, rho, indexing="ij")
+    h2 = a * a - (B - q) ** 2
+    s = np.sqrt(np.maximum(h2, 0))
+    exp = np.where((h2 > 0) & (np.abs(P - s) < dist) & (dist < P + s), 2, 0)
+    margin = np.minimum.reduce([np.abs(np.abs(B - q) - a), np.abs(np.abs(P - s) - dist), np.abs(P + s - dist)])
+    ok = margin > 4 * a * 1.2e-3
+    assert (exp[ok] == 2).sum() > 20
+    assert np.array_equal(g[0][ok], exp[ok])
+
+
+def test_empty_scene_and_no_points(ctx):
+    import torch
+    opp = np.array([[0, 0, 0], [1, 2, 3]], np.float32)
+    opn = np.array([[0, 0, 1], [1, 0, 0]], np.float32)
+    g = gpu_images(ctx, np.zeros((0, 3), np.float32), np.zeros((0, 3), np.uint32), opp, opn, 0.3)
+    assert g.shape == (2, 64, 64) and (g == 0).all()
+    out = ctx.generate(dev_f32(np.zeros((3, 3))), dev_u32(np.zeros((1, 3))), torch.zeros((0, 3), device="cuda"),
+                       torch.zeros((0, 3), device="cuda"), 0.3)
+    ctx.sync()
+    assert out.shape == (0, 64, 64)
+
+
+def test_zero_normal_is_plus_z(ctx):
+    s = synth.config1_icosphere()
+    op = s.op_positions[:5]
+    a = gpu_images(ctx, s.positions, s.triangles, op, np.zeros_like(op), 1.0)
+    b = gpu_images(ctx, s.positions, s.triangles, op, np.tile(np.float32([0, 0, 1]), (5, 1)), 1.0)
+    assert np.array_equal(a, b)
+
+
+def test_power_of_two_scaling_bit_identical(ctx):
+    s = synth.config1_icosphere()
+    a = gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals, 1.0)
+    f = np.float32(8.0)
+    b = gpu_images(ctx, s.positions * f, s.triangles, s.op_positions * f, s.op_normals, 8.0)
+    assert np.array_equal(a, b)
+
+
+def test_repeatable(ctx):
+    s = synth.config1_icosphere()
+    a = gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals, 1.0)
+    b = gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals, 1.0)
+    assert np.array_equal(a, b)
+
+
+def test_bad_inputs_are_reported(ctx):
+    from paper_2007_02306_amd import RiciError
+    s = synth.config1_icosphere()
+    bad = s.triangles.copy()
+    bad[5, 1] = s.positions.shape[0] + 3
+    with pytest.raises(RiciError) as e:
+        gpu_images(ctx, s.positions, bad, s.op_positions[:3], s.op_normals[:3], 1.0)
+    assert "RICI_ERR_DEVICE" in str(e.value) and ctx.device_errors() & 1
+    pos = s.positions.copy()
+    pos[7, 2] = np.nan
+    with pytest.raises(RiciError):
+        gpu_images(ctx, pos, s.triangles, s.op_positions[:3], s.op_normals[:3], 1.0)
+    assert ctx.device_errors() & 2
+    with pytest.raises(RiciError) as e:
+        gpu_images(ctx, s.positions, s.triangles, s.op_positions[:3], s.op_normals[:3], -1.0)
+    assert "RICI_ERR_INVALID" in str(e.value)
+    # the handle stays usable
+    g = gpu_images(ctx, s.positions, s.triangles, s.op_positions[:3], s.op_normals[:3], 1.0)
+    assert g.max() > 0

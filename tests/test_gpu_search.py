@@ -1,0 +1,155 @@
+"""GPU parity of the clutter-resistant distance search (rici_distance_matrix,
+rici_distance_rank) against the oracle: exact integers, always."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev_u32, gpu_images, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2007_02306_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def gpu_matrix(ctx, n, h):
+    say(f"  gpu matrix: {len(n)} x {len(h)}")
+    out = ctx.distance_matrix(dev_u32(n), dev_u32(h))
+    ctx.sync()
+    return out.cpu().numpy()
+
+
+def gpu_rank(ctx, n, h, t):
+    say(f"  gpu rank: {len(n)} needles x {len(h)} haystack")
+    rk, ds = ctx.distance_rank(dev_u32(n), dev_u32(h), dev_u32(np.asarray(t, np.uint32)))
+    ctx.sync()
+    return rk.cpu().numpy().view(np.uint32), ds.cpu().numpy()
+
+
+@pytest.mark.parametrize("nn,nh,scale", [(1, 1, 2), (37, 53, 2), (16, 256, 3), (257, 300, 2), (300, 17, 11)])
+def test_matrix_small_deltas(ctx, nn, nh, scale):
+    rng = np.random.default_rng(nn * 1000 + nh)
+    n = synth.step_images(rng, nn, delta_scale=scale)
+    h = synth.step_images(rng, nh, delta_scale=scale)
+    assert np.array_equal(gpu_matrix(ctx, n, h), oracle.distance_matrix(n, h))
+
+
+@pytest.mark.parametrize("nmax,hmax", [(11, 12), (11, 127), (127, 11), (127, 127), (128, 11), (11, 128), (300, 500)])
+def test_matrix_delta_ranges(ctx, nmax, hmax):
+    """Every arithmetic path: |D_h| <= 11 (two phases), 11 < |D_h| <= 127
+    (three phases), |D| > 127 (int64 path) on either side."""
+    rng = np.random.default_rng(nmax * 7 + hmax)
+    n = synth.step_images(rng, 70, delta_scale=3)
+    h = synth.step_images(rng, 90, delta_scale=3)
+    n[5] = synth.step_images(rng, 1, max_delta=nmax, density=0.05)[0]
+    n[5, 3, 10] += nmax          # force the extreme delta
+    h[40] = synth.step_images(rng, 1, max_delta=hmax, density=0.05)[0]
+    h[40, 60, 33] += hmax
+    n[6] = h[40]
+    got = gpu_matrix(ctx, n, h)
+    assert np.array_equal(got, oracle.distance_matrix(n, h))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_rank_with_ties(ctx, seed):
+    rng = np.random.default_rng(seed)
+    nh, nn = 333, 129
+    h = synth.step_images(rng, nh, density=0.03)
+    h[10] = h[11]
+    h[12] = h[11]
+    t = rng.integers(0, nh, nn).astype(np.uint32)
+    t[0] = 11
+    n = synth.perturb(rng, h[t], frac=0.01)
+    n[0] = h[11]
+    rk, ds = gpu_rank(ctx, n, h, t)
+    ork, ods = oracle.rank(n, h, t)
+    assert np.array_equal(ds, ods)
+    assert np.array_equal(rk, ork)
+    assert rk[0] == 0 and rk.max() <= nh - 1
+
+
+def test_rank_mixed_ranges(ctx):
+    rng = np.random.default_rng(9)
+    h = synth.step_images(rng, 500, delta_scale=2)
+    h[100:110] = synth.step_images(rng, 10, max_delta=60, density=0.04)
+    h[200:203] = synth.step_images(rng, 3, max_delta=400, density=0.02)
+    t = rng.integers(0, 500, 90).astype(np.uint32)
+    t[:6] = [100, 101, 200, 201, 5, 6]
+    n = synth.perturb(rng, h[t], frac=0.02)
+    n[50] = synth.step_images(rng, 1, max_delta=200, density=0.03)[0]
+    rk, ds = gpu_rank(ctx, n, h, t)
+    ork, ods = oracle.rank(n, h, t)
+    assert np.array_equal(ds, ods) and np.array_equal(rk, ork)
+
+
+def test_rank_large_haystack_sampled(ctx):
+    """70 000 haystack images (beyond 2^16), 600 needles; the oracle ranks a
+    seeded sample of needles over the full haystack."""
+    rng = np.random.default_rng(77)
+    nh, nn = 70_000, 600
+    h = synth.step_images(rng, nh, density=0.06)
+    t = rng.integers(0, nh, nn).astype(np.uint32)
+    n = synth.perturb(rng, h[t], frac=0.03)
+    rk, ds = gpu_rank(ctx, n, h, t)
+    sel = np.unique(np.concatenate([[0, nn - 1], rng.choice(nn, 10, replace=False)]))
+    ork, ods = oracle.rank(n[sel], h, t[sel])
+    assert np.array_equal(ds[sel], ods) and np.array_equal(rk[sel], ork)
+    assert (rk < nh).all()
+
+
+def test_config1_end_to_end(ctx):
+    """Icosphere: GPU images -> GPU ranks versus oracle images -> oracle ranks,
+    with a shuffled true-match map so that ranks are not trivially 0."""
+    s = synth.config1_icosphere()
+    g = gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    o, fl, _ = oracle.rici_rowrange(s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    assert not fl.any()
+    rng = np.random.default_rng(1)
+    t = rng.permutation(s.num_haystack).astype(np.uint32)
+    rk, ds = gpu_rank(ctx, g, g, t)
+    ork, ods = oracle.rank(o, o, t)
+    assert np.array_equal(rk, ork) and np.array_equal(ds, ods)
+    assert rk.max() > 0
+    rk0, ds0 = gpu_rank(ctx, g, g, np.arange(s.num_haystack))
+    assert (rk0 == 0).all() and (ds0 == 0).all()
+    assert np.array_equal(gpu_matrix(ctx, g, g), oracle.distance_matrix(o, o))
+
+
+def test_benchmark_sized_search_sampled(ctx):
+    """Search at the benchmark's size (23 352 x 23 352) on seeded step images;
+    a sample of needles is ranked by the oracle over the full haystack."""
+    rng = np.random.default_rng(2)
+    n_img = 23_352
+    h = synth.step_images(rng, n_img, density=0.05)
+    t = rng.permutation(n_img).astype(np.uint32)
+    n = synth.perturb(rng, h[t], frac=0.01)
+    rk, ds = gpu_rank(ctx, n, h, t)
+    sel = np.unique(np.concatenate([[0, n_img - 1], rng.choice(n_img, 14, replace=False)]))
+    ork, ods = oracle.rank(n[sel], h, t[sel])
+    assert np.array_equal(ds[sel], ods) and np.array_equal(rk[sel], ork)
+
+
+def test_bad_true_index_and_empty(ctx):
+    rng = np.random.default_rng(3)
+    h = synth.step_images(rng, 20)
+    t = np.array([0, 25, 2], np.uint32)
+    rk, ds = gpu_rank(ctx, h[:3], h, t)
+    assert rk[1] == 20 and rk[0] == 0 and rk[2] == 0
+    import torch
+    from paper_2007_02306_amd import RiciError
+    e_rk, e_ds = ctx.distance_rank(torch.zeros((0, 64, 64), dtype=torch.int32, device="cuda"), dev_u32(h),
+                                   torch.zeros(0, dtype=torch.int32, device="cuda"))
+    ctx.sync()
+    assert e_rk.numel() == 0
+    with pytest.raises(RiciError):
+        ctx.distance_rank(dev_u32(h[:2]), torch.zeros((0, 64, 64), dtype=torch.int32, device="cuda"),
+                          dev_u32(np.zeros(2, np.uint32)))
