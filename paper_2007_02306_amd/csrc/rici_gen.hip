@@ -27,7 +27,7 @@
 namespace rici {
 namespace {
 
-constexpr int kG = 8;          // images per workgroup
+constexpr int kG = 4;          // images per workgroup
 constexpr int kWaves = 8;      // wavefronts per workgroup
 constexpr int kRing = 128;     // per-wave survivor ring (entries)
 
@@ -80,127 +80,67 @@ k_gen_prep(const float* __restrict__ pos, uint32_t nv, const uint32_t* __restric
 
 // ------------------------------------------------------------ exact pieces
 
+// Per-image frame in FP64 (Eq. 1), with the second rotation and the in-plane
+// y row pre-multiplied by 64/R so that projected coordinates come out in bin
+// units: bin radii are c + 1/2 and row heights r - 31.5, exactly.
 struct Frame {
-    double sx, sy, sz;       // Spin Vertex
-    double nax, nay;         // Eq. 1, first rotation (about z)
-    double nbx, nbz;         // Eq. 1, second rotation (about y), normalising the rotated normal
+    double sx, sy, sz;        // Spin Vertex
+    double nax, nay;          // first rotation (about z)
+    double nax_d, nay_d;      // first rotation x 64/R (y coordinate)
+    double nbx_d, nbz_d;      // second rotation (about y) x 64/R
     double pad;
 };
 
-// column index helpers: rho_c = (c + 1/2) * delta, exact in FP64
-__device__ __forceinline__ double rho_sq(int c, double delta)
-{
-    double rho = ((double)c + 0.5) * delta;
-    return rho * rho;
-}
+// One surviving (image, triangle) pair in bin units, vertices sorted by
+// height (a lowest, c highest), with the slopes d(x, y)/dz of its edges.
+struct __align__(16) Rec {
+    double xa, ya, za, zb;
+    double xb, yb;
+    double sxl, syl;          // along a -> c (crosses every row of the range)
+    double sx1, sy1;          // along a -> b (rows with beta <= z_b)
+    double sx2, sy2;          // along b -> c (rows with beta >  z_b)
+};
 
-// first column c in [0, 64] with rho_c^2 > s (64 if none); s >= 0 or NaN-free
-__device__ __forceinline__ int first_col_above(double s, double delta, float inv_delta)
+// First column c in [0, 64] whose bin radius c + 1/2 exceeds sqrt(s), s >= 0,
+// decided by an exact FP64 comparison.  The FP32 square root is biased low so
+// the guess is the answer or one below it.
+__device__ __forceinline__ int first_col(double s)
 {
-    float f = sqrtf(fminf((float)s, 3.0e38f)) * inv_delta - 0.5f;
-    f = fminf(fmaxf(f, -1.0f), 64.0f);
-    int c = (int)floorf(f) + 1;
-    c = min(max(c, 0), 64);
-    if (c > 0 && rho_sq(c - 1, delta) > s) --c;
-    if (c < 64 && rho_sq(c, delta) <= s) ++c;
+    float f = sqrtf(fminf((float)s, 1.0e4f) * 0.99998f);
+    int c = (int)floorf(f - 0.5f) + 1;
+    c = min(c, 64);
+    const double t = (double)c + 0.5;
+    c += (c < 64 && t * t <= s) ? 1 : 0;
     return c;
 }
 
-__device__ __forceinline__ double beta_of(int r, double R, double delta)
+// Same for the ratio cr2 / dd (dd > 0): first c with (c + 1/2)^2 dd > cr2.
+__device__ __forceinline__ int first_col_ratio(double cr2, double dd)
 {
-    return -0.5 * R + ((double)r + 0.5) * delta;   // exact for fp32 R
+    const double approx = cr2 * __builtin_amdgcn_rcp(dd);
+    float f = sqrtf(fminf((float)approx, 1.0e4f) * 0.99990f);
+    int c = (int)floorf(f - 0.5f) + 1;
+    c = min(max(c, 0), 64);
+    const double t = (double)c + 0.5;
+    c += (c < 64 && t * t * dd <= cr2) ? 1 : 0;
+    return c;
 }
 
-__device__ __forceinline__ void lds_add(uint32_t* row, int c, uint32_t v)
+__device__ __forceinline__ void csort(double& x0, double& y0, double& z0, double& x1, double& y1, double& z1)
 {
-    if (c < NB) atomicAdd(row + c, v);
+    const bool sw = z1 < z0;
+    const double tx = sw ? x1 : x0, ty = sw ? y1 : y0, tz = sw ? z1 : z0;
+    x1 = sw ? x0 : x1; y1 = sw ? y0 : y1; z1 = sw ? z0 : z1;
+    x0 = tx; y0 = ty; z0 = tz;
 }
 
-// One (image, triangle) survivor: the three steps of Sec. 3.1 in FP64.
-__device__ void slice_triangle(const Frame& F, const float4 va, const float4 vb, const float4 vc,
-                               double R, double delta, float inv_delta, uint32_t* diff_img)
+__device__ __forceinline__ double recip(double d)
 {
-    double x[3], y[3], z[3];
-    const float4 v[3] = { va, vb, vc };
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        double px = (double)v[k].x - F.sx;                 // Eq. 2
-        double py = (double)v[k].y - F.sy;
-        double pz = (double)v[k].z - F.sz;
-        double qx = F.nax * px + F.nay * py;               // Eq. 3
-        double qy = -F.nay * px + F.nax * py;
-        x[k] = F.nbz * qx - F.nbx * pz;                    // Eq. 4
-        y[k] = qy;
-        z[k] = F.nbx * qx + F.nbz * pz;
-    }
-    const double zmin = fmin(z[0], fmin(z[1], z[2]));
-    const double zmax = fmax(z[0], fmax(z[1], z[2]));
-    const double inv_d = 1.0 / delta;
-
-    // rows whose plane has vertices on both sides under "above iff z >= beta":
-    // beta_r in (zmin, zmax]
-    double fr0 = floor(fmin(fmax(zmin * inv_d + 31.5, -2.0), 70.0)) + 1.0;
-    int r0 = min(max((int)fr0, 0), 64);
-    if (r0 > 0 && beta_of(r0 - 1, R, delta) > zmin) --r0;
-    if (r0 < 64 && beta_of(r0, R, delta) <= zmin) ++r0;
-    double fr1 = floor(fmin(fmax(zmax * inv_d + 31.5, -2.0), 70.0));
-    int r1 = min(max((int)fr1, -1), 63);
-    if (r1 < 63 && beta_of(r1 + 1, R, delta) <= zmax) ++r1;
-    if (r1 >= 0 && beta_of(r1, R, delta) > zmax) --r1;
-    if (r0 > r1) return;
-
-    // reciprocal vertical extent of the edges 0->1, 1->2, 2->0
-    const double i01 = 1.0 / (z[1] - z[0]);
-    const double i12 = 1.0 / (z[2] - z[1]);
-    const double i20 = 1.0 / (z[0] - z[2]);
-
-    for (int r = r0; r <= r1; ++r) {
-        const double beta = beta_of(r, R, delta);
-        const bool a0 = z[0] >= beta, a1 = z[1] >= beta, a2 = z[2] >= beta;
-        // the vertex alone on its side of the plane (l) and the two edges
-        // leaving it, towards a = l + 1 and b = l + 2 (mod 3)
-        const bool l0 = (a0 != a1) && (a0 != a2);
-        const bool l1 = !l0 && (a1 != a0) && (a1 != a2);
-        const double xl = l0 ? x[0] : (l1 ? x[1] : x[2]);
-        const double yl = l0 ? y[0] : (l1 ? y[1] : y[2]);
-        const double zl = l0 ? z[0] : (l1 ? z[1] : z[2]);
-        const double xa = l0 ? x[1] : (l1 ? x[2] : x[0]);
-        const double ya = l0 ? y[1] : (l1 ? y[2] : y[0]);
-        const double xb = l0 ? x[2] : (l1 ? x[0] : x[1]);
-        const double yb = l0 ? y[2] : (l1 ? y[0] : y[1]);
-        const double inv_a = l0 ? i01 : (l1 ? i12 : i20);      // 1 / (z_a - z_l)
-        const double inv_b = l0 ? -i20 : (l1 ? -i01 : -i12);   // 1 / (z_b - z_l)
-        const double hl = beta - zl;
-        const double ta = hl * inv_a, tb = hl * inv_b;
-        const double e0x = xl + ta * (xa - xl);
-        const double e0y = yl + ta * (ya - yl);
-        const double e1x = xl + tb * (xb - xl);
-        const double e1y = yl + tb * (yb - yl);
-
-        const double d0 = e0x * e0x + e0y * e0y;
-        const double d1 = e1x * e1x + e1y * e1y;
-        const double lo2 = fmin(d0, d1), hi2 = fmax(d0, d1);
-        const double dx = e1x - e0x, dy = e1y - e0y;
-        const double dd = dx * dx + dy * dy;
-        const bool between = (e0x * dx + e0y * dy) < 0.0 && (e1x * dx + e1y * dy) > 0.0;
-
-        uint32_t* row = diff_img + r * NB;
-        const int c_lo = first_col_above(lo2, delta, inv_delta);
-        const int c_hi = first_col_above(hi2, delta, inv_delta);
-        if (between) {
-            // |C|^2 = (E0 x E1)^2 / |E1 - E0|^2: distance of the axis from the line E0E1
-            const double cr = e0x * e1y - e0y * e1x;
-            const int c_c = first_col_above(cr * cr / dd, delta, inv_delta);
-            if (c_c < c_lo) {
-                lds_add(row, c_c, 2u);
-                lds_add(row, c_lo, (uint32_t)-2);
-            }
-        }
-        if (c_lo < c_hi) {
-            lds_add(row, c_lo, 1u);
-            lds_add(row, c_hi, (uint32_t)-1);
-        }
-    }
+    // 1/d: hardware estimate refined by two Newton steps (a few ulp)
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return r;
 }
 
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane)
@@ -213,26 +153,130 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane)
     return v;
 }
 
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kDiffStride = 65;   // column 64 of each row is a sink for "past the image"
+constexpr int kMapCap = 1024;     // slices mapped per round
+
+struct GenLds {
+    uint32_t diff[kG][NB * kDiffStride];
+    uint32_t ring[kWaves][kRing];
+    Rec rec[kWaves][64];
+    uint32_t meta[kWaves][64];    // image | first row << 2
+    uint32_t pre[kWaves][64];     // exclusive prefix of row counts
+    uint8_t map[kWaves][kMapCap]; // slice -> survivor lane
+    Frame frames[kG];
+    float cp[kG][8];              // FP32 cull parameters
+};
+
+// Exact work for up to 64 queued (image, triangle) pairs of one wavefront.
+__device__ void process_batch(GenLds& L, int wave, int lane, uint32_t head, uint32_t cnt,
+                              const float4* __restrict__ verts)
+{
+    wave_sync_lds();
+    uint32_t nrows = 0;
+    if ((uint32_t)lane < cnt) {
+        const uint32_t e = L.ring[wave][(head + lane) & (kRing - 1)];
+        const uint32_t g = e & (kG - 1), t = e / kG;
+        const Frame& F = L.frames[g];
+        const float4 v0 = verts[3 * (size_t)t], v1 = verts[3 * (size_t)t + 1], v2 = verts[3 * (size_t)t + 2];
+        double X[3], Y[3], Z[3];
+        const float4 v[3] = { v0, v1, v2 };
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double px = (double)v[k].x - F.sx;          // Eq. 2
+            const double py = (double)v[k].y - F.sy;
+            const double pz = (double)v[k].z - F.sz;
+            const double qx = F.nax * px + F.nay * py;        // Eq. 3 (x)
+            Y[k] = -F.nay_d * px + F.nax_d * py;              // Eq. 3 (y), bin units
+            X[k] = F.nbz_d * qx - F.nbx_d * pz;               // Eq. 4, bin units
+            Z[k] = F.nbx_d * qx + F.nbz_d * pz;
+        }
+        double xa = X[0], ya = Y[0], za = Z[0], xb = X[1], yb = Y[1], zb = Z[1], xc = X[2], yc = Y[2], zc = Z[2];
+        csort(xa, ya, za, xb, yb, zb);
+        csort(xb, yb, zb, xc, yc, zc);
+        csort(xa, ya, za, xb, yb, zb);
+        // rows r with r - 31.5 in (z_a, z_c]: a vertex is above iff z >= beta
+        const double f0 = floor(fmin(fmax(za + 31.5, -2.0), 70.0)) + 1.0;
+        const double f1 = floor(fmin(fmax(zc + 31.5, -2.0), 70.0));
+        const int r0 = max((int)f0, 0), r1 = min((int)f1, 63);
+        const double il = recip(zc - za);
+        const double i1 = recip(zb - za);
+        const double i2 = recip(zc - zb);
+        nrows = (r1 >= r0 && zc > za) ? (uint32_t)(r1 - r0 + 1) : 0u;
+        Rec& R = L.rec[wave][lane];
+        R.xa = xa; R.ya = ya; R.za = za; R.zb = zb; R.xb = xb; R.yb = yb;
+        R.sxl = (xc - xa) * il; R.syl = (yc - ya) * il;
+        R.sx1 = (xb - xa) * i1; R.sy1 = (yb - ya) * i1;
+        R.sx2 = (xc - xb) * i2; R.sy2 = (yc - yb) * i2;
+        L.meta[wave][lane] = g | ((uint32_t)max(r0, 0) << 2);
+    }
+    const uint32_t incl = wave_inclusive_scan(nrows, lane);
+    const uint32_t pre = incl - nrows;
+    const uint32_t total = __shfl(incl, 63, 64);
+    L.pre[wave][lane] = pre;
+
+    for (uint32_t base = 0; base < total; base += kMapCap) {
+        const uint32_t lo = max(pre, base), hi = min(pre + nrows, base + kMapCap);
+        for (uint32_t k = lo; k < hi; ++k) L.map[wave][k - base] = (uint8_t)lane;
+        wave_sync_lds();
+        const uint32_t n_round = min(total - base, (uint32_t)kMapCap);
+        for (uint32_t k = lane; k < n_round; k += 64) {
+            const uint32_t sidx = L.map[wave][k];
+            const Rec R = L.rec[wave][sidx];
+            const uint32_t m = L.meta[wave][sidx];
+            const int r = (int)(m >> 2) + (int)(base + k - L.pre[wave][sidx]);
+            const uint32_t g = m & (kG - 1);
+            const double beta = (double)r - 31.5;
+            // Sec. 3.1.2 step 1: crossings on the long edge and on the short
+            // edge whose z-range holds beta
+            const double hl = beta - R.za;
+            const double e0x = R.xa + hl * R.sxl, e0y = R.ya + hl * R.syl;
+            const bool low = beta <= R.zb;
+            const double h1 = low ? hl : beta - R.zb;
+            const double e1x = (low ? R.xa : R.xb) + h1 * (low ? R.sx1 : R.sx2);
+            const double e1y = (low ? R.ya : R.yb) + h1 * (low ? R.sy1 : R.sy2);
+            // steps 3-4: squared distances from the axis; single range (lo, hi)
+            const double d0 = e0x * e0x + e0y * e0y, d1 = e1x * e1x + e1y * e1y;
+            const double lo2 = fmin(d0, d1), hi2 = fmax(d0, d1);
+            // steps 5-6: double range (|C|, lo) iff the foot C of the axis on
+            // line E0E1 lies strictly inside the segment
+            const double dx = e1x - e0x, dy = e1y - e0y;
+            const double dd = dx * dx + dy * dy;
+            const bool between = (e0x * dx + e0y * dy) < 0.0 && (e1x * dx + e1y * dy) > 0.0;
+            const double cr = e0x * e1y - e0y * e1x;
+            const bool ok = lo2 <= 1.0e300 && hi2 <= 1.0e300;
+            int c_lo = first_col(lo2), c_hi = first_col(hi2);
+            int c_c = between ? min(first_col_ratio(cr * cr, dd), c_lo) : c_lo;
+            if (!ok) { c_lo = c_hi = c_c = 64; }
+            // +2 on [c_c, c_lo), +1 on [c_lo, c_hi) as a difference row
+            uint32_t* row = L.diff[g] + r * kDiffStride;
+            atomicAdd(row + c_c, 2u);
+            atomicAdd(row + c_lo, (uint32_t)-1);
+            atomicAdd(row + c_hi, (uint32_t)-1);
+        }
+        wave_sync_lds();
+    }
+}
+
 __global__ void __launch_bounds__(kWaves * 64)
 k_gen(const float4* __restrict__ cull, const float4* __restrict__ verts, uint32_t nt,
       const float* __restrict__ op_pos, const float* __restrict__ op_nrm, uint32_t n, float Rf,
       uint32_t* __restrict__ out, uint32_t* __restrict__ err)
 {
-    __shared__ uint32_t diff[kG][NPIX];
-    __shared__ uint32_t ring[kWaves][kRing];
-    __shared__ Frame frames[kG];
-    __shared__ __align__(16) float cp[kG][8];     // FP32 cull parameters per image
-
+    __shared__ GenLds L;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t img0 = blockIdx.x * kG;
-    const double R = (double)Rf;
-    const double delta = R / NB;
-    const float inv_delta = (float)(NB / R);
 
-    for (int i = tid; i < kG * NPIX; i += kWaves * 64) (&diff[0][0])[i] = 0u;
+    for (int i = tid; i < kG * NB * kDiffStride; i += kWaves * 64) (&L.diff[0][0])[i] = 0u;
     if (tid < kG) {
         Frame f = {};
-        float* c = cp[tid];
+        float* c = L.cp[tid];
         const uint32_t img = img0 + tid;
         bool live = img < n;
         if (live) {
@@ -242,20 +286,25 @@ k_gen(const float4* __restrict__ cull, const float4* __restrict__ verts, uint32_
                 atomicOr(err, 2u);
                 live = false;
             } else {
+                const double inv_d = (double)NB / (double)Rf;
                 f.sx = sp[0]; f.sy = sp[1]; f.sz = sp[2];
                 const double nx = sn[0], ny = sn[1], nz = sn[2];
                 // Eq. 1: [N_ax, N_ay] = Normalize[S_nx, S_ny]; identity if both vanish
+                double nax = 1.0, nay = 0.0, nbx = 0.0, nbz = 1.0;
                 const double la = sqrt(nx * nx + ny * ny);
-                if (la > 0.0) { f.nax = nx / la; f.nay = ny / la; } else { f.nax = 1.0; f.nay = 0.0; }
-                // second rotation normalises the normal's x after the first rotation
-                const double rx = f.nax * nx + f.nay * ny;
+                if (la > 0.0) { nax = nx / la; nay = ny / la; }
+                // the second rotation normalises the normal's x after the first one
+                const double rx = nax * nx + nay * ny;
                 const double lb = sqrt(rx * rx + nz * nz);
-                if (lb > 0.0) { f.nbx = rx / lb; f.nbz = nz / lb; } else { f.nbx = 0.0; f.nbz = 1.0; }
+                if (lb > 0.0) { nbx = rx / lb; nbz = nz / lb; }
+                f.nax = nax; f.nay = nay;
+                f.nax_d = nax * inv_d; f.nay_d = nay * inv_d;
+                f.nbx_d = nbx * inv_d; f.nbz_d = nbz * inv_d;
                 // Central Axis direction for the cull: the pre-image of +z
                 c[0] = sp[0]; c[1] = sp[1]; c[2] = sp[2];
-                c[3] = (float)(f.nbx * f.nax);
-                c[4] = (float)(f.nbx * f.nay);
-                c[5] = (float)f.nbz;
+                c[3] = (float)(nbx * nax);
+                c[4] = (float)(nbx * nay);
+                c[5] = (float)nbz;
                 const float mag = fmaxf(fabsf(sp[0]), fmaxf(fabsf(sp[1]), fabsf(sp[2])));
                 const float margin = 1e-5f * (mag + Rf) + 1e-30f;
                 c[6] = 0.5f * Rf + margin;    // slab half height
@@ -264,60 +313,55 @@ k_gen(const float4* __restrict__ cull, const float4* __restrict__ verts, uint32_
         }
         if (!live) {
             c[0] = c[1] = c[2] = 0.f; c[3] = c[4] = 0.f; c[5] = 1.f;
-            c[6] = -INFINITY; c[7] = -INFINITY;
+            c[6] = -INFINITY; c[7] = 0.f;
         }
-        frames[tid] = f;
+        L.frames[tid] = f;
     }
     __syncthreads();
 
-    uint32_t* my_ring = ring[wave];
+    // cull parameters of the G images, wave-uniform (scalar registers)
+    float P[kG][8];
+#pragma unroll
+    for (int g = 0; g < kG; ++g)
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            P[g][k] = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(L.cp[g][k])));
+
     uint32_t head = 0, tail = 0;   // wave-uniform ring counters
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     for (uint32_t base = (uint32_t)wave * 64; base < nt; base += kWaves * 64) {
         const uint32_t t = base + lane;
         const float4 s = t < nt ? cull[t] : make_float4(0.f, 0.f, 0.f, -INFINITY);
-#pragma unroll 1
+        uint32_t mask = 0;
+#pragma unroll
         for (int g = 0; g < kG; ++g) {
-            // uniform LDS reads (broadcast) of this image's cull parameters
-            const float4 p0 = *reinterpret_cast<const float4*>(&cp[g][0]);
-            const float4 p1 = *reinterpret_cast<const float4*>(&cp[g][4]);
-            const float dx = s.x - p0.x, dy = s.y - p0.y, dz = s.z - p0.z;
-            const float h = p0.w * dx + p1.x * dy + p1.y * dz;
+            const float dx = s.x - P[g][0], dy = s.y - P[g][1], dz = s.z - P[g][2];
+            const float h = P[g][3] * dx + P[g][4] * dy + P[g][5] * dz;
             const float d2 = dx * dx + dy * dy + dz * dz;
             const float a2 = d2 - h * h;
-            const float la = p1.w + s.w;
-            const bool pass = fabsf(h) <= p1.z + s.w && a2 <= la * la && la > 0.f;
-            const uint64_t m = __ballot(pass);
-            if (pass) {
-                const uint32_t slot = tail + (uint32_t)__popcll(m & lt_mask);
-                my_ring[slot & (kRing - 1)] = (t << 3) | (uint32_t)g;
+            const float la = P[g][7] + s.w;
+            const bool pass = (fabsf(h) <= P[g][6] + s.w) & (a2 <= la * la);
+            mask |= (pass ? 1u : 0u) << g;
+        }
+        // append the pairs to the ring, one image bit per round
+        while (__ballot(mask != 0)) {
+            const bool has = mask != 0;
+            const uint32_t g = (uint32_t)__builtin_ctz(mask | 0x10u);
+            mask &= mask - 1;
+            const uint64_t bal = __ballot(has);
+            if (has) {
+                const uint32_t slot = tail + (uint32_t)__popcll(bal & lt_mask);
+                L.ring[wave][slot & (kRing - 1)] = t * kG + g;
             }
-            tail += (uint32_t)__popcll(m);
+            tail += (uint32_t)__popcll(bal);
             if (tail - head >= 64) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const uint32_t e = my_ring[(head + lane) & (kRing - 1)];
+                process_batch(L, wave, lane, head, 64, verts);
                 head += 64;
-                const uint32_t gi = e & 7u, ti = e >> 3;
-                slice_triangle(frames[gi], verts[3 * (size_t)ti], verts[3 * (size_t)ti + 1],
-                               verts[3 * (size_t)ti + 2], R, delta, inv_delta, diff[gi]);
             }
         }
     }
-    {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint32_t left = tail - head;
-        if ((uint32_t)lane < left) {
-            const uint32_t e = my_ring[(head + lane) & (kRing - 1)];
-            const uint32_t gi = e & 7u, ti = e >> 3;
-            slice_triangle(frames[gi], verts[3 * (size_t)ti], verts[3 * (size_t)ti + 1],
-                           verts[3 * (size_t)ti + 2], R, delta, inv_delta, diff[gi]);
-        }
-    }
+    if (tail > head) process_batch(L, wave, lane, head, tail - head, verts);
     __syncthreads();
 
     // row prefix sums of the difference arrays -> counts; one row per wave step
@@ -325,7 +369,7 @@ k_gen(const float4* __restrict__ cull, const float4* __restrict__ verts, uint32_
         const int g = row / NB, r = row % NB;
         const uint32_t img = img0 + g;
         if (img >= n) continue;
-        uint32_t v = wave_inclusive_scan(diff[g][r * NB + lane], lane);
+        const uint32_t v = wave_inclusive_scan(L.diff[g][r * kDiffStride + lane], lane);
         out[(size_t)img * NPIX + r * NB + lane] = v;
     }
 }
