@@ -172,25 +172,24 @@ k_true_distance(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_
 
 // ----------------------------------------------------------------- MFMA search
 
-template <int WM, int WN, int MB, int NBK, int KC>
+template <int WM, int WN, int MB, int NBK, int NS>
 struct SearchCfg {
-    static constexpr int kWM = WM, kWN = WN, kMB = MB, kNBK = NBK, kKC = KC;
+    static constexpr int kWM = WM, kWN = WN, kMB = MB, kNBK = NBK, kNS = NS;
     static constexpr int kWaves = WM * WN;
     static constexpr int kThreads = kWaves * 64;
     static constexpr int BM = WM * MB * 16;          // needles per tile
     static constexpr int BN = WN * NBK * 16;         // haystack images per tile
     static constexpr int GA = BM / 16, GB = BN / 16; // fragment groups per tile
-    static constexpr int kStageA = GA * KC * (int)kFragBytes;
-    static constexpr int kStageB = GB * KC * (int)kFragBytes;
-    static constexpr int kStage = kStageA + kStageB;
-    static constexpr int kLoads = kStage / (16 * kThreads);   // 16 B loads per thread per stage
-    static constexpr int kSPP = NB / KC;                      // stages per phase (64 rows)
-    static_assert(kStage % (16 * kThreads) == 0, "stage must split evenly");
-    static_assert(NB % KC == 0, "KC must divide 64");
+    static constexpr int kFrags = GA + GB;           // 1 KiB fragments per stage (one image row)
+    static constexpr int kStage = kFrags * (int)kFragBytes;
+    static constexpr int kLPW = kFrags / kWaves;     // fragment loads per wave per stage
+    static constexpr int kLds = NS * kStage + 4096;  // ring of NS stages (+ slack)
+    static_assert(kFrags % kWaves == 0, "fragments must split evenly over the waves");
 };
 
-// 256 x 256 (needle x haystack) tile, 8 waves of 128 x 64, one K row (64 deltas) per stage
-using Cfg = SearchCfg<2, 4, 8, 4, 1>;
+// 256 x 256 (needle x haystack) tile, 8 waves of 128 x 64, a 4-deep ring of
+// one-row stages filled by direct global -> LDS loads
+using Cfg = SearchCfg<2, 4, 8, 4, 4>;
 
 struct SearchArgs {
     const int8_t* a_planes; uint32_t a_groups; uint32_t nn;
@@ -203,6 +202,25 @@ struct SearchArgs {
     int64_t* matrix;
     uint32_t tiles_m, tiles_n, per_xcd;
 };
+
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding)
+template <int V>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(V >= 0 && V < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((V & 15) | (7 << 4) | (15 << 8) | ((V >> 4) << 14));
+}
+
+// Workgroup barrier without a memory fence: the LDS data of a stage is
+// published by each wave's own vmcnt wait on its direct-to-LDS loads (a
+// fence would also drain the prefetches of later stages).  The empty asm
+// statements keep the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void stage_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
 template <class C>
 __global__ void __launch_bounds__(C::kThreads)
@@ -234,87 +252,74 @@ k_search(SearchArgs A)
         need_q |= (m > kSmallD && m <= kSlow) ? 1 : 0;
     }
     const bool hq = __syncthreads_or(need_q) != 0;
-    const int nphase = hq ? 3 : 2;
-    const int nstage = nphase * C::kSPP;
+    const int nstage = (hq ? 3 : 2) * NB;
 
-    const size_t a_ps = (size_t)A.a_groups * kPlaneGroupBytes;
-    const size_t b_ps = (size_t)A.b_groups * kPlaneGroupBytes;
+    // Stage s = phase s / 64, image row s % 64.  Phase -> planes: needle planes
+    // 0 = -D, 1 = mask; haystack planes 0 = D, 1 = D^2 mod 128, 2 = D^2 div 128.
+    // Each wave moves kLPW whole fragments (1 KiB, one instruction each) from
+    // global memory straight into the stage's LDS slot; every address but the
+    // lane's 16-byte offset is wave-uniform.
+    static_assert(C::GA % C::kLPW == 0, "a wave loads fragments of one operand only");
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int f0 = wv * C::kLPW;                       // first fragment of this wave
+    const bool is_a = f0 < C::GA;
+    const int8_t* wbase = is_a ? A.a_planes + (size_t)(ga0 + f0) * kPlaneGroupBytes
+                               : A.b_planes + (size_t)(gb0 + f0 - C::GA) * kPlaneGroupBytes;
+    const size_t wps = is_a ? (size_t)A.a_groups * kPlaneGroupBytes : (size_t)A.b_groups * kPlaneGroupBytes;
+    const uint32_t lane_off = (uint32_t)lane * 16;
 
-    // Stage layout in LDS: A = [GA groups][KC rows][1 KiB], then B likewise.
-    // Thread tid copies the 16-byte chunks tid + k * kThreads; which operand a
-    // chunk belongs to is known at compile time (kStageA is a multiple of the
-    // per-k stride).
-    static_assert(C::kStageA % (16 * C::kThreads) == 0, "A part must split evenly");
-    constexpr int kLoadsA = C::kStageA / (16 * C::kThreads);
-    constexpr int kGroupSpan = C::kKC * (int)kFragBytes;   // bytes of one group per stage
-    const int8_t* a_tile = A.a_planes + (size_t)ga0 * kPlaneGroupBytes;
-    const int8_t* b_tile = A.b_planes + (size_t)gb0 * kPlaneGroupBytes;
-
-    auto chunk_src = [&](int k, int s, bool hqv) -> const int8_t* {
-        const int p = s / C::kSPP;
-        // phase -> plane: needle planes 0 = -D, 1 = mask; haystack planes
-        // 0 = D, 1 = D^2 mod 128, 2 = D^2 div 128
-        const int pa = hqv ? ((p == 1) ? 0 : 1) : p;
-        const int pb = hqv ? ((p == 0) ? 2 : (p == 1 ? 0 : 1)) : p;
-        const size_t row_off = (size_t)((s % C::kSPP) * C::kKC) * kFragBytes;
-        const int off = (tid + k * C::kThreads) * 16;
-        if (k < kLoadsA) {
-            const int g = off / kGroupSpan, rem = off % kGroupSpan;
-            return a_tile + (size_t)pa * a_ps + (size_t)g * kPlaneGroupBytes + row_off + rem;
-        }
-        const int o2 = off - C::kStageA;
-        const int g = o2 / kGroupSpan, rem = o2 % kGroupSpan;
-        return b_tile + (size_t)pb * b_ps + (size_t)g * kPlaneGroupBytes + row_off + rem;
+    auto issue = [&](int s) {
+        const int p = s / NB, row = s % NB;
+        const int pa = hq ? ((p == 1) ? 0 : 1) : p;
+        const int pb = hq ? ((p == 0) ? 2 : (p == 1 ? 0 : 1)) : p;
+        const int8_t* src = wbase + (size_t)(is_a ? pa : pb) * wps + (size_t)row * kFragBytes;
+        int8_t* dst = lds + (s % C::kNS) * C::kStage + f0 * (int)kFragBytes;
+#pragma unroll
+        for (int j = 0; j < C::kLPW; ++j)
+            __builtin_amdgcn_global_load_lds(
+                (const void __attribute__((address_space(1)))*)(src + (size_t)j * kPlaneGroupBytes + lane_off),
+                (void __attribute__((address_space(3)))*)(dst + j * (int)kFragBytes), 16, 0, 0);
     };
+
     v4i acc[C::kMB][C::kNBK];
 #pragma unroll
     for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
         for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = v4i{0, 0, 0, 0};
 
-    v4i stg[C::kLoads];
 #pragma unroll
-    for (int k = 0; k < C::kLoads; ++k) stg[k] = *reinterpret_cast<const v4i*>(chunk_src(k, 0, hq));
-#pragma unroll
-    for (int k = 0; k < C::kLoads; ++k) *reinterpret_cast<v4i*>(lds + (tid + k * C::kThreads) * 16) = stg[k];
-    __syncthreads();
+    for (int s = 0; s < C::kNS - 1; ++s) issue(s);   // nstage >= 128 > kNS
 
     for (int s = 0; s < nstage; ++s) {
-        if (s + 1 < nstage) {
-#pragma unroll
-            for (int k = 0; k < C::kLoads; ++k) stg[k] = *reinterpret_cast<const v4i*>(chunk_src(k, s + 1, hq));
-        }
-        if (s > 0 && s % C::kSPP == 0) {
+        // this wave's loads for stage s are done once at most the later ones
+        // (stages s+1 .. s+NS-2) are outstanding; then the barrier makes every
+        // wave's part of the stage visible and frees the slot of stage s-1
+        if (s + C::kNS - 2 < nstage) wait_vmcnt<(C::kNS - 2) * C::kLPW>();
+        else wait_vmcnt<0>();
+        stage_barrier();
+        if (s > 0 && s % NB == 0) {
             // end of a phase: scale the partial sum (x64 after q, x2 after -D.D)
-            const int p = s / C::kSPP;
-            const int sh = (hq && p == 1) ? 6 : 1;
+            const int sh = (hq && s == NB) ? 6 : 1;
 #pragma unroll
             for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
                 for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << sh;
         }
-        const int8_t* sA = lds + (s & 1) * C::kStage;
-        const int8_t* sB = sA + C::kStageA;
+        const int8_t* sA = lds + (s % C::kNS) * C::kStage + lane * 16;
+        const int8_t* sB = sA + C::GA * (int)kFragBytes;
+        v4i fb[C::kNBK], fa[C::kMB];
 #pragma unroll
-        for (int kc = 0; kc < C::kKC; ++kc) {
-            v4i fb[C::kNBK];
+        for (int nb = 0; nb < C::kNBK; ++nb)
+            fb[nb] = *reinterpret_cast<const v4i*>(sB + (wn * C::kNBK + nb) * (int)kFragBytes);
+#pragma unroll
+        for (int mb = 0; mb < C::kMB; ++mb)
+            fa[mb] = *reinterpret_cast<const v4i*>(sA + (wm * C::kMB + mb) * (int)kFragBytes);
+        if (s + C::kNS - 1 < nstage) issue(s + C::kNS - 1);
+#pragma unroll
+        for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < C::kNBK; ++nb)
-                fb[nb] = *reinterpret_cast<const v4i*>(sB + ((wn * C::kNBK + nb) * C::kKC + kc) * (int)kFragBytes + lane * 16);
-#pragma unroll
-            for (int mb = 0; mb < C::kMB; ++mb) {
-                const v4i fa = *reinterpret_cast<const v4i*>(sA + ((wm * C::kMB + mb) * C::kKC + kc) * (int)kFragBytes + lane * 16);
-#pragma unroll
-                for (int nb = 0; nb < C::kNBK; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa, fb[nb], acc[mb][nb], 0, 0, 0);
-            }
-        }
-        if (s + 1 < nstage) {
-            int8_t* dst = lds + ((s + 1) & 1) * C::kStage;
-#pragma unroll
-            for (int k = 0; k < C::kLoads; ++k) *reinterpret_cast<v4i*>(dst + (tid + k * C::kThreads) * 16) = stg[k];
-        }
-        __syncthreads();
+                acc[mb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[mb], fb[nb], acc[mb][nb], 0, 0, 0);
     }
 
     // Epilogue.  16x16 accumulator layout: lane l holds column l % 16 and
@@ -446,7 +451,7 @@ hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp
     A.tiles_n = (nh + Cfg::BN - 1) / Cfg::BN;
     const uint32_t total = A.tiles_m * A.tiles_n;
     A.per_xcd = (total + 7) / 8;
-    const size_t lds = 2 * (size_t)Cfg::kStage;
+    const size_t lds = (size_t)Cfg::kLds;
     static bool lds_raised = false;   // per process; the attribute is per function
     if (!lds_raised) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<Cfg>),
@@ -471,7 +476,7 @@ hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t*
     return hipGetLastError();
 }
 
-size_t search_lds_bytes() { return 2 * (size_t)Cfg::kStage; }
+size_t search_lds_bytes() { return (size_t)Cfg::kLds; }
 uint32_t search_tile_m() { return Cfg::BM; }
 uint32_t search_tile_n() { return Cfg::BN; }
 
