@@ -257,16 +257,20 @@ struct SearchScratch {
 
 int search_scratch(rici_ctx* h, uint32_t nn, uint32_t nh, bool want_dstar, SearchScratch& S)
 {
-    const size_t ga = rici::search_groups(nn), gb = rici::search_groups(nh);
+    const size_t ga = rici::search_groups(nn);
+    const size_t hslots = rici::haystack_slots(nh), gb = hslots / rici::kGroup;
     const size_t a_planes = align256(2 * ga * rici::kPlaneGroupBytes);
     const size_t b_planes = align256(3 * gb * rici::kPlaneGroupBytes);
     const size_t sumsq = align256(ga * rici::kGroup * sizeof(int64_t));
     const size_t nmax = align256(ga * rici::kGroup * sizeof(uint32_t));
-    const size_t hmax = align256(gb * rici::kGroup * sizeof(uint32_t));
+    const size_t hmax = align256(hslots * sizeof(uint32_t));
+    const size_t hmax_img = align256((size_t)nh * sizeof(uint32_t));
+    const size_t hperm = align256(hslots * sizeof(uint32_t));
+    const size_t counters = 256;
     const size_t thr = align256((size_t)nn * sizeof(int32_t));
     const size_t dstar = want_dstar ? align256((size_t)nn * sizeof(int64_t)) : 0;
     const size_t lists = align256((2 + (size_t)nn + nh) * sizeof(uint32_t));
-    const size_t total = a_planes + b_planes + sumsq + nmax + hmax + thr + dstar + lists;
+    const size_t total = a_planes + b_planes + sumsq + nmax + hmax + hmax_img + hperm + counters + thr + dstar + lists;
     int rc = ensure_ws(h, total);
     if (rc) return rc;
     char* p = (char*)h->ws;
@@ -275,7 +279,13 @@ int search_scratch(rici_ctx* h, uint32_t nn, uint32_t nh, bool want_dstar, Searc
     S.np.sumsq = (int64_t*)p; p += sumsq;
     S.hp.sumsq = nullptr;
     S.np.maxabs = (uint32_t*)p; p += nmax;
+    S.np.maxabs_img = S.np.maxabs;
+    S.np.perm = nullptr;
+    S.np.counters = nullptr;
     S.hp.maxabs = (uint32_t*)p; p += hmax;
+    S.hp.maxabs_img = (uint32_t*)p; p += hmax_img;
+    S.hp.perm = (uint32_t*)p; p += hperm;
+    S.hp.counters = (uint32_t*)p; p += counters;
     S.thr = (int32_t*)p; p += thr;
     S.dstar = want_dstar ? (int64_t*)p : nullptr; p += dstar;
     S.lists = (uint32_t*)p;
@@ -343,7 +353,7 @@ int rici_distance_rank(rici_handle h, const uint32_t* needles, uint32_t num_need
     });
     if (e != hipSuccess) return hip_fail(e, "search launch");
     e = timed(h, "fallback", s, [&] {
-        return rici::launch_fallback(needles, num_needles, haystack, num_haystack, S.np.maxabs, S.hp.maxabs, dstar,
+        return rici::launch_fallback(needles, num_needles, haystack, num_haystack, S.np.maxabs, S.hp.maxabs_img, dstar,
                                      out_rank, nullptr, S.lists, s);
     });
     if (e != hipSuccess) return hip_fail(e, "fallback launch");
@@ -375,7 +385,7 @@ int rici_distance_matrix(rici_handle h, const uint32_t* needles, uint32_t num_ne
     });
     if (e != hipSuccess) return hip_fail(e, "matrix launch");
     e = timed(h, "fallback", s, [&] {
-        return rici::launch_fallback(needles, num_needles, haystack, num_haystack, S.np.maxabs, S.hp.maxabs, nullptr,
+        return rici::launch_fallback(needles, num_needles, haystack, num_haystack, S.np.maxabs, S.hp.maxabs_img, nullptr,
                                      nullptr, out, S.lists, s);
     });
     if (e != hipSuccess) return hip_fail(e, "fallback launch");

@@ -32,15 +32,25 @@ constexpr size_t kPlaneGroupBytes = NB * kFragBytes;   // one group, all 64 rows
 
 // needle planes: 0 = -D (int8), 1 = mask [D != 0] (0/1)
 // haystack planes: 0 = D, 1 = D^2 mod 128, 2 = D^2 / 128
+// Needles keep their order (slot = image).  The haystack is permuted: images
+// whose deltas all satisfy |D| <= 11 take slots from the front, the others
+// from the back, with at least one whole tile of padding in between, so that a
+// search tile holds only one kind and only tiles of the second kind pay the
+// third contraction phase.  Ranks are counts, so the order is free; the
+// distance matrix maps slots back through `perm`.
 struct SearchPrep {
     int8_t* planes;        // [nplanes][ngroups][64][1024]
-    int64_t* sumsq;        // needles: |D|^2 per image
-    uint32_t* maxabs;      // max |D| per image (saturating)
-    uint32_t ngroups;      // ceil(n / 16) rounded up to the search tile
+    int64_t* sumsq;        // needles: |D|^2 per slot
+    uint32_t* maxabs;      // max |D| per slot (saturating; padding = 0xFFFFFFFF)
+    uint32_t* maxabs_img;  // max |D| per original image (== maxabs for needles)
+    uint32_t* perm;        // haystack: slot -> image (0xFFFFFFFF = padding); needles: nullptr
+    uint32_t* counters;    // haystack: two slot counters
+    uint32_t ngroups;      // slots / 16
 };
 
 hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side,
                              const SearchPrep& p, hipStream_t s);
+size_t haystack_slots(uint32_t nh);   // slots allocated for a haystack of nh images
 hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                                 const uint32_t* true_idx, const int64_t* sumsq, const uint32_t* nmax,
                                 int64_t* dstar, int32_t* thr, uint32_t* rank, hipStream_t s);

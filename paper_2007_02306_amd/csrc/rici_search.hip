@@ -39,15 +39,16 @@ constexpr uint32_t kPad = 0xFFFFFFFFu;
 __global__ void __launch_bounds__(256)
 k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
              int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
-             uint32_t* __restrict__ maxabs)
+             uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm)
 {
     __shared__ uint32_t smax[4][kGroup];
     __shared__ int64_t ssum[4][kGroup];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t grp = blockIdx.x;
     const int i = lane & 15, q = lane >> 4;
-    const uint32_t img = grp * kGroup + i;
-    const bool live = img < n;
+    const uint32_t slot = grp * kGroup + i;
+    const uint32_t img = perm ? perm[slot] : slot;
+    const bool live = perm ? img != kPad : slot < n;
     const size_t plane_stride = (size_t)ngroups * kPlaneGroupBytes;
 
     uint32_t mx = 0;
@@ -106,6 +107,7 @@ k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
         if (!needle_side)
             *reinterpret_cast<uint4*>(planes + 2 * plane_stride + frag) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
     }
+    if (perm) return;   // the haystack's statistics come from k_hay_classify
     // per-image reductions: 4 lanes (q) per wave and 4 waves share image i
 #pragma unroll
     for (int o = 16; o < 64; o <<= 1) {
@@ -120,6 +122,53 @@ k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
         int64_t s = ssum[0][tid] + ssum[1][tid] + ssum[2][tid] + ssum[3][tid];
         maxabs[im] = im < n ? m : kPad;
         if (sumsq) sumsq[im] = im < n ? s : 0;
+    }
+}
+
+// Haystack slot assignment.  k_hay_init marks every slot as padding and clears
+// the two counters; k_hay_classify (one wavefront per image) finds max |D| and
+// takes a slot from the front (|D| <= 11 everywhere) or from the back.
+__global__ void __launch_bounds__(256)
+k_hay_init(uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs, uint32_t nslots,
+           uint32_t* __restrict__ counters)
+{
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nslots) { perm[s] = kPad; maxabs[s] = kPad; }
+    if (s < 2) counters[s] = 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_hay_classify(const uint32_t* __restrict__ images, uint32_t n, uint32_t nslots,
+               uint32_t* __restrict__ maxabs_img, uint32_t* __restrict__ perm,
+               uint32_t* __restrict__ maxabs, uint32_t* __restrict__ counters)
+{
+    // one wavefront per image; each load instruction covers four rows: lane l
+    // holds columns 4 (l % 16) .. 4 (l % 16) + 3 of row 4 it + l / 16
+    const int lane = threadIdx.x & 63;
+    const uint32_t img = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (img >= n) return;
+    const uint4* im = reinterpret_cast<const uint4*>(images + (size_t)img * NPIX);
+    const bool first = (lane & 15) == 0;
+    uint32_t mx = 0;
+#pragma unroll 4
+    for (int it = 0; it < NB / 4; ++it) {
+        const uint4 v = im[it * 64 + lane];
+        const uint32_t left = __shfl_up(v.w, 1, 64);   // column 4 (l % 16) - 1 of the same row
+        const int64_t d0 = first ? 0 : (int64_t)v.x - (int64_t)left;
+        const int64_t d1 = (int64_t)v.y - (int64_t)v.x;
+        const int64_t d2 = (int64_t)v.z - (int64_t)v.y;
+        const int64_t d3 = (int64_t)v.w - (int64_t)v.z;
+        const uint64_t m01 = max((uint64_t)(d0 < 0 ? -d0 : d0), (uint64_t)(d1 < 0 ? -d1 : d1));
+        const uint64_t m23 = max((uint64_t)(d2 < 0 ? -d2 : d2), (uint64_t)(d3 < 0 ? -d3 : d3));
+        mx = (uint32_t)max((uint64_t)mx, min(max(m01, m23), (uint64_t)0xFFFFFFFEu));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    if (lane == 0) {
+        const uint32_t slot = mx <= kSmallD ? atomicAdd(counters, 1u) : nslots - 1 - atomicAdd(counters + 1, 1u);
+        maxabs_img[img] = mx;
+        perm[slot] = img;
+        maxabs[slot] = mx;
     }
 }
 
@@ -195,7 +244,8 @@ struct SearchArgs {
     const int8_t* a_planes; uint32_t a_groups; uint32_t nn;
     const int8_t* b_planes; uint32_t b_groups; uint32_t nh;
     const uint32_t* nmax;
-    const uint32_t* hmax;
+    const uint32_t* hmax;      // per haystack slot
+    const uint32_t* hperm;     // haystack slot -> image
     const int32_t* thr;
     const int64_t* sumsq;
     uint32_t* rank;
@@ -245,13 +295,16 @@ k_search(SearchArgs A)
     const uint32_t tn = (logical % in_group) / gsz;
     const uint32_t ga0 = tm * C::GA, gb0 = tn * C::GB;
 
-    // q phase needed iff some usable haystack image of the tile has 11 < |D| <= 127
-    int need_q = 0;
+    // q phase needed iff some usable haystack image of the tile has
+    // 11 < |D| <= 127; a tile without any usable haystack image is skipped
+    int flags = 0;
     for (int j = tid; j < C::BN; j += C::kThreads) {
         const uint32_t m = A.hmax[gb0 * 16 + j];
-        need_q |= (m > kSmallD && m <= kSlow) ? 1 : 0;
+        flags |= (m > kSmallD && m <= kSlow) ? 1 : 0;
+        flags |= (m <= kSlow) ? 2 : 0;
     }
-    const bool hq = __syncthreads_or(need_q) != 0;
+    const bool hq = __syncthreads_or(flags & 1) != 0;
+    if (!__syncthreads_or(flags & 2)) return;
     const int nstage = (hq ? 3 : 2) * NB;
 
     // Stage s = phase s / 64, image row s % 64.  Phase -> planes: needle planes
@@ -287,16 +340,29 @@ k_search(SearchArgs A)
 #pragma unroll
         for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = v4i{0, 0, 0, 0};
 
+    struct Frags { v4i a[C::kMB]; v4i b[C::kNBK]; };
+    auto read_frags = [&](int s, Frags& F) {
+        const int8_t* sA = lds + (s % C::kNS) * C::kStage + lane * 16;
+        const int8_t* sB = sA + C::GA * (int)kFragBytes;
 #pragma unroll
-    for (int s = 0; s < C::kNS - 1; ++s) issue(s);   // nstage >= 128 > kNS
-
-    for (int s = 0; s < nstage; ++s) {
-        // this wave's loads for stage s are done once at most the later ones
-        // (stages s+1 .. s+NS-2) are outstanding; then the barrier makes every
-        // wave's part of the stage visible and frees the slot of stage s-1
-        if (s + C::kNS - 2 < nstage) wait_vmcnt<(C::kNS - 2) * C::kLPW>();
-        else wait_vmcnt<0>();
-        stage_barrier();
+        for (int nb = 0; nb < C::kNBK; ++nb)
+            F.b[nb] = *reinterpret_cast<const v4i*>(sB + (wn * C::kNBK + nb) * (int)kFragBytes);
+#pragma unroll
+        for (int mb = 0; mb < C::kMB; ++mb)
+            F.a[mb] = *reinterpret_cast<const v4i*>(sA + (wm * C::kMB + mb) * (int)kFragBytes);
+    };
+    // One pipeline step: make stage s+1 visible, refill the slot of stage s-1
+    // with stage s+NS-1, fetch stage s+1's fragments into registers, and run
+    // stage s's MFMAs from the fragments fetched one step earlier, so the LDS
+    // reads of one stage overlap the matrix work of the previous one.
+    auto step = [&](int s, const Frags& cur, Frags& nxt) {
+        if (s + 1 < nstage) {
+            if (s + 2 < nstage) wait_vmcnt<C::kLPW>();
+            else wait_vmcnt<0>();
+            stage_barrier();
+            if (s + C::kNS - 1 < nstage) issue(s + C::kNS - 1);
+            read_frags(s + 1, nxt);
+        }
         if (s > 0 && s % NB == 0) {
             // end of a phase: scale the partial sum (x64 after q, x2 after -D.D)
             const int sh = (hq && s == NB) ? 6 : 1;
@@ -305,21 +371,23 @@ k_search(SearchArgs A)
 #pragma unroll
                 for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << sh;
         }
-        const int8_t* sA = lds + (s % C::kNS) * C::kStage + lane * 16;
-        const int8_t* sB = sA + C::GA * (int)kFragBytes;
-        v4i fb[C::kNBK], fa[C::kMB];
-#pragma unroll
-        for (int nb = 0; nb < C::kNBK; ++nb)
-            fb[nb] = *reinterpret_cast<const v4i*>(sB + (wn * C::kNBK + nb) * (int)kFragBytes);
-#pragma unroll
-        for (int mb = 0; mb < C::kMB; ++mb)
-            fa[mb] = *reinterpret_cast<const v4i*>(sA + (wm * C::kMB + mb) * (int)kFragBytes);
-        if (s + C::kNS - 1 < nstage) issue(s + C::kNS - 1);
 #pragma unroll
         for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < C::kNBK; ++nb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[mb], fb[nb], acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur.a[mb], cur.b[nb], acc[mb][nb], 0, 0, 0);
+    };
+
+    static_assert(C::kNS == 4, "the wait counts below assume a 4-deep ring");
+#pragma unroll
+    for (int s = 0; s < C::kNS - 1; ++s) issue(s);   // nstage >= 128 > kNS
+    wait_vmcnt<2 * C::kLPW>();
+    stage_barrier();
+    Frags fr0, fr1;
+    read_frags(0, fr0);
+    for (int s = 0; s < nstage; s += 2) {   // nstage is even
+        step(s, fr0, fr1);
+        step(s + 1, fr1, fr0);
     }
 
     // Epilogue.  16x16 accumulator layout: lane l holds column l % 16 and
@@ -329,8 +397,9 @@ k_search(SearchArgs A)
     uint32_t col[C::kNBK];
 #pragma unroll
     for (int nb = 0; nb < C::kNBK; ++nb) {
-        col[nb] = (gb0 + wn * C::kNBK + nb) * 16 + cl;
-        colok[nb] = col[nb] < A.nh && A.hmax[col[nb]] <= kSlow;
+        const uint32_t slot = (gb0 + wn * C::kNBK + nb) * 16 + cl;
+        colok[nb] = A.hmax[slot] <= kSlow;            // padding and |D| > 127 excluded
+        col[nb] = colok[nb] ? A.hperm[slot] : 0u;     // original haystack index
     }
 #pragma unroll
     for (int mb = 0; mb < C::kMB; ++mb) {
@@ -419,12 +488,31 @@ size_t search_groups(uint32_t n)
     return ((g + t - 1) / t) * t;
 }
 
+size_t haystack_slots(uint32_t nh)
+{
+    const size_t t = Cfg::BN;
+    return ((size_t)nh + t - 1) / t * t + t;   // + one tile: a tile boundary inside the gap
+}
+
 hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side, const SearchPrep& p,
                              hipStream_t s)
 {
     if (p.ngroups == 0) return hipSuccess;
+    if (p.perm) {
+        const uint32_t nslots = p.ngroups * kGroup;
+        hipLaunchKernelGGL(k_hay_init, dim3((nslots + 255) / 256), dim3(256), 0, s, p.perm, p.maxabs, nslots,
+                           p.counters);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (n > 0) {
+            hipLaunchKernelGGL(k_hay_classify, dim3((n + 3) / 4), dim3(256), 0, s, images, n, nslots, p.maxabs_img,
+                               p.perm, p.maxabs, p.counters);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
     hipLaunchKernelGGL(k_delta_prep, dim3(p.ngroups), dim3(256), 0, s, images, n, needle_side, p.planes, p.ngroups,
-                       p.sumsq, p.maxabs);
+                       p.sumsq, p.maxabs, p.perm);
     return hipGetLastError();
 }
 
@@ -445,10 +533,10 @@ hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp
     SearchArgs A;
     A.a_planes = np.planes; A.a_groups = np.ngroups; A.nn = nn;
     A.b_planes = hp.planes; A.b_groups = hp.ngroups; A.nh = nh;
-    A.nmax = np.maxabs; A.hmax = hp.maxabs;
+    A.nmax = np.maxabs; A.hmax = hp.maxabs; A.hperm = hp.perm;
     A.thr = thr; A.sumsq = sumsq; A.rank = rank; A.matrix = matrix;
     A.tiles_m = (nn + Cfg::BM - 1) / Cfg::BM;
-    A.tiles_n = (nh + Cfg::BN - 1) / Cfg::BN;
+    A.tiles_n = hp.ngroups * kGroup / Cfg::BN;   // every haystack slot, padding included
     const uint32_t total = A.tiles_m * A.tiles_n;
     A.per_xcd = (total + 7) / 8;
     const size_t lds = (size_t)Cfg::kLds;
