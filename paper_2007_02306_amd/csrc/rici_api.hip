@@ -266,11 +266,10 @@ int search_scratch(rici_ctx* h, uint32_t nn, uint32_t nh, bool want_dstar, Searc
     const size_t hmax = align256(hslots * sizeof(uint32_t));
     const size_t hmax_img = align256((size_t)nh * sizeof(uint32_t));
     const size_t hperm = align256(hslots * sizeof(uint32_t));
-    const size_t counters = 256;
     const size_t thr = align256((size_t)nn * sizeof(int32_t));
     const size_t dstar = want_dstar ? align256((size_t)nn * sizeof(int64_t)) : 0;
     const size_t lists = align256((2 + (size_t)nn + nh) * sizeof(uint32_t));
-    const size_t total = a_planes + b_planes + sumsq + nmax + hmax + hmax_img + hperm + counters + thr + dstar + lists;
+    const size_t total = a_planes + b_planes + sumsq + nmax + hmax + hmax_img + hperm + thr + dstar + lists;
     int rc = ensure_ws(h, total);
     if (rc) return rc;
     char* p = (char*)h->ws;
@@ -281,11 +280,9 @@ int search_scratch(rici_ctx* h, uint32_t nn, uint32_t nh, bool want_dstar, Searc
     S.np.maxabs = (uint32_t*)p; p += nmax;
     S.np.maxabs_img = S.np.maxabs;
     S.np.perm = nullptr;
-    S.np.counters = nullptr;
     S.hp.maxabs = (uint32_t*)p; p += hmax;
     S.hp.maxabs_img = (uint32_t*)p; p += hmax_img;
     S.hp.perm = (uint32_t*)p; p += hperm;
-    S.hp.counters = (uint32_t*)p; p += counters;
     S.thr = (int32_t*)p; p += thr;
     S.dstar = want_dstar ? (int64_t*)p : nullptr; p += dstar;
     S.lists = (uint32_t*)p;

@@ -44,7 +44,6 @@ struct SearchPrep {
     uint32_t* maxabs;      // max |D| per slot (saturating; padding = 0xFFFFFFFF)
     uint32_t* maxabs_img;  // max |D| per original image (== maxabs for needles)
     uint32_t* perm;        // haystack: slot -> image (0xFFFFFFFF = padding); needles: nullptr
-    uint32_t* counters;    // haystack: two slot counters
     uint32_t ngroups;      // slots / 16
 };
 

@@ -107,7 +107,7 @@ k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
         if (!needle_side)
             *reinterpret_cast<uint4*>(planes + 2 * plane_stride + frag) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
     }
-    if (perm) return;   // the haystack's statistics come from k_hay_classify
+    if (perm) return;   // the haystack's statistics come from k_hay_stats
     // per-image reductions: 4 lanes (q) per wave and 4 waves share image i
 #pragma unroll
     for (int o = 16; o < 64; o <<= 1) {
@@ -125,25 +125,22 @@ k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
     }
 }
 
-// Haystack slot assignment.  k_hay_init marks every slot as padding and clears
-// the two counters; k_hay_classify (one wavefront per image) finds max |D| and
-// takes a slot from the front (|D| <= 11 everywhere) or from the back.
+// Haystack slot assignment.  k_hay_init marks every slot as padding;
+// k_hay_stats (one wavefront per image) finds max |D|; k_hay_assign (one
+// workgroup, prefix sums) gives images with |D| <= 11 the front slots and the
+// others the back slots, both in image order, so the layout is deterministic.
 __global__ void __launch_bounds__(256)
-k_hay_init(uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs, uint32_t nslots,
-           uint32_t* __restrict__ counters)
+k_hay_init(uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs, uint32_t nslots)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < nslots) { perm[s] = kPad; maxabs[s] = kPad; }
-    if (s < 2) counters[s] = 0;
 }
 
 __global__ void __launch_bounds__(256)
-k_hay_classify(const uint32_t* __restrict__ images, uint32_t n, uint32_t nslots,
-               uint32_t* __restrict__ maxabs_img, uint32_t* __restrict__ perm,
-               uint32_t* __restrict__ maxabs, uint32_t* __restrict__ counters)
+k_hay_stats(const uint32_t* __restrict__ images, uint32_t n, uint32_t* __restrict__ maxabs_img)
 {
-    // one wavefront per image; each load instruction covers four rows: lane l
-    // holds columns 4 (l % 16) .. 4 (l % 16) + 3 of row 4 it + l / 16
+    // each load instruction covers four rows: lane l holds columns
+    // 4 (l % 16) .. 4 (l % 16) + 3 of row 4 it + l / 16
     const int lane = threadIdx.x & 63;
     const uint32_t img = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (img >= n) return;
@@ -164,11 +161,38 @@ k_hay_classify(const uint32_t* __restrict__ images, uint32_t n, uint32_t nslots,
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
-    if (lane == 0) {
-        const uint32_t slot = mx <= kSmallD ? atomicAdd(counters, 1u) : nslots - 1 - atomicAdd(counters + 1, 1u);
-        maxabs_img[img] = mx;
-        perm[slot] = img;
-        maxabs[slot] = mx;
+    if (lane == 0) maxabs_img[img] = mx;
+}
+
+__global__ void __launch_bounds__(1024)
+k_hay_assign(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslots,
+             uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs)
+{
+    __shared__ uint32_t wsum[16][2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t chunk = (n + 1023) / 1024;
+    const uint32_t lo = min((uint32_t)tid * chunk, n), hi = min(lo + chunk, n);
+    uint32_t cs = 0, co = 0;
+    for (uint32_t i = lo; i < hi; ++i) {
+        if (maxabs_img[i] <= kSmallD) ++cs; else ++co;
+    }
+    // exclusive prefix over threads: wavefront scans, then the 16 wave totals
+    uint32_t is = cs, io = co;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t a = __shfl_up(is, o, 64), b = __shfl_up(io, o, 64);
+        if (lane >= o) { is += a; io += b; }
+    }
+    if (lane == 63) { wsum[wave][0] = is; wsum[wave][1] = io; }
+    __syncthreads();
+    uint32_t bs = 0, bo = 0;
+    for (int w = 0; w < wave; ++w) { bs += wsum[w][0]; bo += wsum[w][1]; }
+    uint32_t ps = bs + is - cs, po = bo + io - co;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t m = maxabs_img[i];
+        const uint32_t slot = m <= kSmallD ? ps++ : nslots - 1 - po++;
+        perm[slot] = i;
+        maxabs[slot] = m;
     }
 }
 
@@ -500,13 +524,14 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
     if (p.ngroups == 0) return hipSuccess;
     if (p.perm) {
         const uint32_t nslots = p.ngroups * kGroup;
-        hipLaunchKernelGGL(k_hay_init, dim3((nslots + 255) / 256), dim3(256), 0, s, p.perm, p.maxabs, nslots,
-                           p.counters);
+        hipLaunchKernelGGL(k_hay_init, dim3((nslots + 255) / 256), dim3(256), 0, s, p.perm, p.maxabs, nslots);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (n > 0) {
-            hipLaunchKernelGGL(k_hay_classify, dim3((n + 3) / 4), dim3(256), 0, s, images, n, nslots, p.maxabs_img,
-                               p.perm, p.maxabs, p.counters);
+            hipLaunchKernelGGL(k_hay_stats, dim3((n + 3) / 4), dim3(256), 0, s, images, n, p.maxabs_img);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_hay_assign, dim3(1), dim3(1024), 0, s, p.maxabs_img, n, nslots, p.perm, p.maxabs);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
