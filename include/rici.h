@@ -123,6 +123,42 @@ int rici_distance_matrix(rici_handle h,
                          int64_t* out, void* stream);
 
 /*
+ * Batched describe-and-rank over many meshes (one plan, replayed as a HIP graph).
+ *
+ * Each job is one mesh with its own oriented points; its RICIs are written to
+ * out_images and, when true_index is given, every one of them is ranked as a
+ * needle against the job's own RICIs as the haystack (rank of the true match,
+ * Sec. 4.1 step 6c, same arithmetic as rici_distance_rank).
+ * rici_batch_create validates the jobs, allocates the plan's scratch (freed by
+ * rici_batch_destroy), uploads the job tables and records the launch sequence
+ * -- triangle preparation, one persistent generation kernel over (mesh, image
+ * group) items, delta planes, one persistent search kernel over (mesh, tile)
+ * items, exact fallback -- into a HIP graph.  Work items are taken from device
+ * counters, largest meshes first.  rici_batch_run replays the graph on
+ * `stream`; the device pointers of the jobs must stay valid for the life of the
+ * plan.  A plan must not run concurrently with itself.
+ */
+typedef struct {
+    const float* positions; uint32_t num_vertices;    /* [V][3] fp32                     */
+    const uint32_t* triangles; uint32_t num_triangles;/* [T][3] uint32                   */
+    const float* op_positions;                        /* [N][3] fp32                     */
+    const float* op_normals; uint32_t num_points;     /* [N][3] fp32                     */
+    uint32_t* out_images;                             /* [N][64][64] uint32              */
+    const uint32_t* true_index;                       /* [N] or NULL (describe only)     */
+    uint32_t* out_rank;                               /* [N], required with true_index   */
+    int64_t* out_true_distance;                       /* [N] or NULL                     */
+} rici_mesh_job;
+
+typedef struct rici_batch_ctx* rici_batch;
+
+int rici_batch_create(rici_handle h, const rici_mesh_job* jobs /* host array */, uint32_t num_jobs,
+                      float support_radius, rici_batch* out);
+int rici_batch_run(rici_batch b, void* stream);
+void rici_batch_destroy(rici_batch b);
+/* Bytes of device scratch the plan holds. */
+uint64_t rici_batch_scratch_bytes(rici_batch b);
+
+/*
  * Kernel timing (measurement support).  When enabled, every kernel the handle
  * launches is bracketed by HIP events on its stream; rici_timing_get sums the
  * elapsed times of the completed launches of the named kernel ("gen",

@@ -14,11 +14,11 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import EXPORTS, LIB_PATH, RiciError, check, load  # noqa: F401
+from ._lib import EXPORTS, LIB_PATH, MeshJob, RiciError, check, load  # noqa: F401
 
 NBINS = 64
 
-__all__ = ["Context", "RiciError", "NBINS", "load", "EXPORTS", "LIB_PATH"]
+__all__ = ["Context", "Batch", "RiciError", "NBINS", "load", "EXPORTS", "LIB_PATH"]
 
 
 def _torch():
@@ -147,6 +147,10 @@ class Context:
     def device_errors(self) -> int:
         return int(self._lib.rici_device_errors(self._h))
 
+    def batch(self, jobs, support_radius: float):
+        """Plan a batched describe-and-rank (see Batch)."""
+        return Batch(self, jobs, support_radius)
+
     # --------------------------------------------------------------- timing
     def timing(self, on: bool = True):
         check(self._lib.rici_timing_enable(self._h, int(bool(on))))
@@ -159,3 +163,64 @@ class Context:
         n = ctypes.c_uint64()
         check(self._lib.rici_timing_get(self._h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class Batch:
+    """A recorded describe-and-rank plan over many meshes (rici_batch_*).
+
+    jobs: list of dicts with device tensors
+        positions [V,3] f32, triangles [T,3] i32, op_positions [N,3] f32,
+        op_normals [N,3] f32, and optionally true_index [N] i32 (ranks each RICI
+        of the mesh against the mesh's own RICIs).
+    The plan allocates the outputs: images[k] ([N,64,64] i32), rank[k] and
+    true_distance[k] (None for describe-only jobs).  run() replays the plan.
+    """
+
+    def __init__(self, ctx: Context, jobs, support_radius: float):
+        torch = _torch()
+        dev = ctx.device
+        self._ctx = ctx
+        self._keep = []
+        self.images, self.rank, self.true_distance = [], [], []
+        arr = (MeshJob * max(len(jobs), 1))()
+        for k, j in enumerate(jobs):
+            pos = _dev(j["positions"], "positions", torch.float32, (3,), dev)
+            tri = _dev(j["triangles"], "triangles", torch.int32, (3,), dev)
+            opp = _dev(j["op_positions"], "op_positions", torch.float32, (3,), dev)
+            opn = _dev(j["op_normals"], "op_normals", torch.float32, (3,), dev)
+            n = opp.shape[0]
+            img = torch.empty((n, NBINS, NBINS), dtype=torch.int32, device=opp.device)
+            ti = j.get("true_index")
+            rk = ds = None
+            if ti is not None:
+                ti = _dev(ti, "true_index", torch.int32, None, dev)
+                rk = torch.empty(n, dtype=torch.int32, device=opp.device)
+                ds = torch.empty(n, dtype=torch.int64, device=opp.device)
+            self._keep += [pos, tri, opp, opn, img, ti, rk, ds]
+            self.images.append(img)
+            self.rank.append(rk)
+            self.true_distance.append(ds)
+            arr[k] = MeshJob(_ptr(pos).value, pos.shape[0], _ptr(tri).value, tri.shape[0], _ptr(opp).value,
+                             _ptr(opn).value, n, _ptr(img).value, _ptr(ti).value if ti is not None else None,
+                             _ptr(rk).value if rk is not None else None, _ptr(ds).value if ds is not None else None)
+        h = ctypes.c_void_p()
+        check(ctx._lib.rici_batch_create(ctx._h, arr, len(jobs), float(support_radius), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def scratch_bytes(self) -> int:
+        return int(self._ctx._lib.rici_batch_scratch_bytes(self._h))
+
+    def run(self, stream=None):
+        check(self._ctx._lib.rici_batch_run(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._ctx._lib.rici_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -18,7 +18,22 @@ EXPORTS = [
     "rici_create", "rici_destroy", "rici_last_error", "rici_sync", "rici_device_errors",
     "rici_generate", "rici_distance_rank", "rici_distance_matrix",
     "rici_timing_enable", "rici_timing_reset", "rici_timing_get",
+    "rici_batch_create", "rici_batch_run", "rici_batch_destroy", "rici_batch_scratch_bytes",
 ]
+
+
+class MeshJob(ctypes.Structure):
+    """rici_mesh_job of include/rici.h."""
+    _fields_ = [
+        ("positions", ctypes.c_void_p), ("num_vertices", ctypes.c_uint32),
+        ("triangles", ctypes.c_void_p), ("num_triangles", ctypes.c_uint32),
+        ("op_positions", ctypes.c_void_p),
+        ("op_normals", ctypes.c_void_p), ("num_points", ctypes.c_uint32),
+        ("out_images", ctypes.c_void_p),
+        ("true_index", ctypes.c_void_p),
+        ("out_rank", ctypes.c_void_p),
+        ("out_true_distance", ctypes.c_void_p),
+    ]
 
 RICI_OK = 0
 STATUS = {0: "RICI_OK", -1: "RICI_ERR_INVALID", -2: "RICI_ERR_OOM", -3: "RICI_ERR_HIP",
@@ -68,6 +83,14 @@ def load(path: str = LIB_PATH):
         lib.rici_timing_get.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_uint64)]
         lib.rici_timing_get.restype = I32
+        lib.rici_batch_create.argtypes = [P, ctypes.POINTER(MeshJob), U32, F32, ctypes.POINTER(P)]
+        lib.rici_batch_create.restype = I32
+        lib.rici_batch_run.argtypes = [P, P]
+        lib.rici_batch_run.restype = I32
+        lib.rici_batch_destroy.argtypes = [P]
+        lib.rici_batch_destroy.restype = None
+        lib.rici_batch_scratch_bytes.argtypes = [P]
+        lib.rici_batch_scratch_bytes.restype = ctypes.c_uint64
         _lib = lib
     return _lib
 

@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -229,18 +230,22 @@ int rici_generate(rici_handle h, const float* positions, uint32_t num_vertices, 
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     const size_t cull_bytes = align256((size_t)num_triangles * rici::kTriCullBytes);
+    const size_t clus_bytes = align256(((size_t)num_triangles + 63) / 64 * rici::kTriCullBytes);
     const size_t vert_bytes = align256((size_t)num_triangles * rici::kTriVertBytes);
-    int rc = ensure_ws(h, cull_bytes + vert_bytes + 256);
+    int rc = ensure_ws(h, cull_bytes + clus_bytes + vert_bytes + 256);
     if (rc) return rc;
     float4* cull = (float4*)h->ws;
-    float4* verts = (float4*)((char*)h->ws + cull_bytes);
+    float4* clusters = (float4*)((char*)h->ws + cull_bytes);
+    float4* verts = (float4*)((char*)h->ws + cull_bytes + clus_bytes);
     hipError_t e = timed(h, "gen_prep", s, [&] {
-        return rici::launch_gen_prep(positions, num_vertices, triangles, num_triangles, cull, verts, h->d_err, s);
+        hipError_t e1 = rici::launch_gen_prep(positions, num_vertices, triangles, num_triangles, cull, verts,
+                                              h->d_err, s);
+        return e1 != hipSuccess ? e1 : rici::launch_gen_clusters(cull, num_triangles, clusters, s);
     });
     if (e != hipSuccess) return hip_fail(e, "gen_prep launch");
     e = timed(h, "gen", s, [&] {
-        return rici::launch_gen(cull, verts, num_triangles, op_positions, op_normals, num_points, support_radius,
-                                out_images, h->d_err, s);
+        return rici::launch_gen(cull, clusters, verts, num_triangles, op_positions, op_normals, num_points,
+                                support_radius, out_images, h->d_err, s);
     });
     if (e != hipSuccess) return hip_fail(e, "gen launch");
     return RICI_OK;
@@ -429,5 +434,252 @@ int rici_timing_get(rici_handle h, const char* kernel, double* total_ms, uint64_
     *launches = n;
     return RICI_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched plans
+
+struct rici_batch_ctx {
+    rici_ctx* h = nullptr;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+bool job_ok(const rici_mesh_job& j, uint32_t k)
+{
+    if (j.num_points == 0) return true;
+    if (!j.op_positions || !j.op_normals || !j.out_images) {
+        fail(RICI_ERR_INVALID, "rici_batch_create: job %u has a NULL oriented-point or image pointer", k);
+        return false;
+    }
+    if (j.num_triangles > 0 && (!j.triangles || !j.positions || j.num_vertices == 0)) {
+        fail(RICI_ERR_INVALID, "rici_batch_create: job %u has a NULL mesh pointer", k);
+        return false;
+    }
+    if (j.num_triangles >= (1u << 29) || j.num_points >= (1u << 31)) {
+        fail(RICI_ERR_UNSUPPORTED, "rici_batch_create: job %u is beyond the size limits", k);
+        return false;
+    }
+    if (j.true_index && !j.out_rank) {
+        fail(RICI_ERR_INVALID, "rici_batch_create: job %u has true_index but no out_rank", k);
+        return false;
+    }
+    return true;
+}
+
+void destroy_plan(rici_batch_ctx* b)
+{
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->scratch) (void)hipFree(b->scratch);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_jobs, float support_radius,
+                      rici_batch* out)
+{
+    if (!out) return fail(RICI_ERR_INVALID, "rici_batch_create: out is NULL");
+    *out = nullptr;
+    if (!h) return fail(RICI_ERR_INVALID, "rici_batch_create: NULL handle");
+    if (num_jobs > 0 && !jobs) return fail(RICI_ERR_INVALID, "rici_batch_create: NULL jobs");
+    if (!(isfinite(support_radius) && support_radius > 0.0f))
+        return fail(RICI_ERR_INVALID, "rici_batch_create: support_radius must be finite and > 0");
+    for (uint32_t k = 0; k < num_jobs; ++k)
+        if (!job_ok(jobs[k], k)) return RICI_ERR_INVALID;
+
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    const uint32_t grid = (uint32_t)prop.multiProcessorCount;   // one resident workgroup per CU
+
+    // generation jobs, largest triangle count first (longest items start first)
+    std::vector<uint32_t> gorder;
+    for (uint32_t k = 0; k < num_jobs; ++k)
+        if (jobs[k].num_points > 0) gorder.push_back(k);
+    std::stable_sort(gorder.begin(), gorder.end(),
+                     [&](uint32_t a, uint32_t b2) { return jobs[a].num_triangles > jobs[b2].num_triangles; });
+    // ranking jobs, most tiles first
+    std::vector<uint32_t> sorder;
+    for (uint32_t k = 0; k < num_jobs; ++k)
+        if (jobs[k].num_points > 0 && jobs[k].true_index) sorder.push_back(k);
+    std::stable_sort(sorder.begin(), sorder.end(),
+                     [&](uint32_t a, uint32_t b2) { return jobs[a].num_points > jobs[b2].num_points; });
+
+    const uint32_t G = rici::gen_group_images();
+    const size_t tm = rici::search_tile_m(), tn = rici::search_tile_n();
+
+    // generation scratch (triangle soup); the search scratch reuses the same
+    // memory because it is only written after generation has finished
+    size_t gen_bytes = 0;
+    std::vector<size_t> goff(gorder.size());
+    for (size_t i = 0; i < gorder.size(); ++i) {
+        const rici_mesh_job& j = jobs[gorder[i]];
+        goff[i] = gen_bytes;
+        gen_bytes += align256((size_t)j.num_triangles * rici::kTriCullBytes) +
+                     align256(((size_t)j.num_triangles + 63) / 64 * rici::kTriCullBytes) +
+                     align256((size_t)j.num_triangles * rici::kTriVertBytes);
+    }
+    size_t srch_bytes = 0;
+    std::vector<size_t> soff(sorder.size());
+    for (size_t i = 0; i < sorder.size(); ++i) {
+        const uint32_t n = jobs[sorder[i]].num_points;
+        const size_t ga = rici::search_groups(n), hs = rici::haystack_slots(n), gb = hs / rici::kGroup;
+        soff[i] = srch_bytes;
+        srch_bytes += align256(2 * ga * rici::kPlaneGroupBytes) + align256(3 * gb * rici::kPlaneGroupBytes) +
+                      align256(ga * rici::kGroup * 8) + align256(ga * rici::kGroup * 4) + align256(hs * 4) +
+                      align256((size_t)n * 4) + align256(hs * 4) + align256((size_t)n * 4) +
+                      align256((size_t)n * 8) + align256((2 + 2 * (size_t)n) * 4);
+    }
+    const size_t tables = align256(gorder.size() * sizeof(rici::GenJob)) +
+                          align256(sorder.size() * sizeof(rici::SearchJob)) + 256;
+    const size_t total = tables + std::max(gen_bytes, srch_bytes);
+
+    rici_batch_ctx* b = new rici_batch_ctx();
+    b->h = h;
+    e = hipMalloc(&b->scratch, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b->scratch = nullptr;
+        destroy_plan(b);
+        return fail(RICI_ERR_OOM, "rici_batch_create: cannot allocate %zu bytes of scratch", total);
+    }
+    b->scratch_bytes = total;
+    char* base = (char*)b->scratch;
+    rici::GenJob* d_gjobs = (rici::GenJob*)base;
+    rici::SearchJob* d_sjobs = (rici::SearchJob*)(base + align256(gorder.size() * sizeof(rici::GenJob)));
+    uint32_t* d_counters = (uint32_t*)(base + tables - 256);
+    char* work = base + tables;
+
+    // ---- generation table
+    std::vector<rici::GenJob> gj(gorder.size());
+    uint64_t tri = 0, chunks = 0;
+    uint32_t items = 0;
+    for (size_t i = 0; i < gorder.size(); ++i) {
+        const rici_mesh_job& j = jobs[gorder[i]];
+        rici::GenJob& J = gj[i];
+        J.pos = j.positions; J.nv = j.num_vertices; J.tri = j.triangles; J.nt = j.num_triangles;
+        J.op_pos = j.op_positions; J.op_nrm = j.op_normals; J.n = j.num_points; J.out = j.out_images;
+        char* p = work + goff[i];
+        J.cull = (float4*)p; p += align256((size_t)j.num_triangles * rici::kTriCullBytes);
+        J.clusters = (float4*)p; p += align256(((size_t)j.num_triangles + 63) / 64 * rici::kTriCullBytes);
+        J.verts = (float4*)p;
+        J.tri_start = tri; J.chunk_start = chunks; J.item_start = items;
+        tri += j.num_triangles;
+        chunks += (j.num_triangles + 63) / 64;
+        items += (j.num_points + G - 1) / G;
+    }
+    // ---- search table
+    std::vector<rici::SearchJob> sj(sorder.size());
+    rici::SearchTotals T = {};
+    uint32_t tiles = 0;
+    for (size_t i = 0; i < sorder.size(); ++i) {
+        const rici_mesh_job& j = jobs[sorder[i]];
+        const uint32_t n = j.num_points;
+        const size_t ga = rici::search_groups(n), hs = rici::haystack_slots(n), gb = hs / rici::kGroup;
+        rici::SearchJob& S = sj[i];
+        char* p = work + soff[i];
+        S.np.planes = (int8_t*)p; p += align256(2 * ga * rici::kPlaneGroupBytes);
+        S.hp.planes = (int8_t*)p; p += align256(3 * gb * rici::kPlaneGroupBytes);
+        S.np.sumsq = (int64_t*)p; p += align256(ga * rici::kGroup * 8);
+        S.np.maxabs = (uint32_t*)p; p += align256(ga * rici::kGroup * 4);
+        S.hp.maxabs = (uint32_t*)p; p += align256(hs * 4);
+        S.hp.maxabs_img = (uint32_t*)p; p += align256((size_t)n * 4);
+        S.hp.perm = (uint32_t*)p; p += align256(hs * 4);
+        int32_t* thr = (int32_t*)p; p += align256((size_t)n * 4);
+        int64_t* dstar = (int64_t*)p; p += align256((size_t)n * 8);
+        S.lists = (uint32_t*)p;
+        S.np.maxabs_img = S.np.maxabs; S.np.perm = nullptr; S.hp.sumsq = nullptr;
+        S.np.ngroups = (uint32_t)ga; S.hp.ngroups = (uint32_t)gb;
+        S.needles = j.out_images; S.hay = j.out_images; S.true_idx = j.true_index;
+        S.dstar = j.out_true_distance ? j.out_true_distance : dstar;
+        rici::SearchArgs& A = S.A;
+        A = {};
+        A.a_planes = S.np.planes; A.a_groups = S.np.ngroups; A.nn = n;
+        A.b_planes = S.hp.planes; A.b_groups = S.hp.ngroups; A.nh = n;
+        A.nmax = S.np.maxabs; A.hmax = S.hp.maxabs; A.hperm = S.hp.perm;
+        A.thr = thr; A.sumsq = S.np.sumsq; A.rank = j.out_rank; A.matrix = nullptr;
+        A.tiles_m = (uint32_t)((n + tm - 1) / tm);
+        A.tiles_n = (uint32_t)(hs / tn);
+        A.per_xcd = 0;
+        S.ngrp_start = T.needle_groups; S.hslot_start = T.hay_slots; S.himg_start = T.hay_images;
+        S.hgrp_start = T.hay_groups; S.needle_start = T.needles; S.tile_start = tiles;
+        T.needle_groups += ga; T.hay_slots += hs; T.hay_images += n; T.hay_groups += gb; T.needles += n;
+        tiles += A.tiles_m * A.tiles_n;
+    }
+    T.tiles = tiles;
+    if (!gj.empty()) e = hipMemcpy(d_gjobs, gj.data(), gj.size() * sizeof(rici::GenJob), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !sj.empty())
+        e = hipMemcpy(d_sjobs, sj.data(), sj.size() * sizeof(rici::SearchJob), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        destroy_plan(b);
+        return hip_fail(e, "rici_batch_create: job table upload");
+    }
+    e = rici::prepare_search_kernels();
+    if (e != hipSuccess) {
+        destroy_plan(b);
+        return hip_fail(e, "rici_batch_create: kernel attributes");
+    }
+
+    // ---- record the launch sequence as a graph
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        destroy_plan(b);
+        return hip_fail(e, "hipStreamCreate");
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    hipError_t le = hipSuccess;
+    if (e == hipSuccess) {
+        le = rici::launch_gen_batched(d_gjobs, (uint32_t)gj.size(), tri, chunks, items, support_radius, d_counters,
+                                      h->d_err, grid, cs);
+        if (le == hipSuccess)
+            le = rici::launch_search_batched(d_sjobs, (uint32_t)sj.size(), T, d_counters + 1, grid, cs);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        b->graph = graph;
+    }
+    (void)hipStreamDestroy(cs);
+    if (e == hipSuccess && le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        destroy_plan(b);
+        return hip_fail(e, "rici_batch_create: graph capture");
+    }
+    *out = b;
+    return RICI_OK;
+}
+
+int rici_batch_run(rici_batch b, void* stream)
+{
+    if (!b || !b->exec) return fail(RICI_ERR_INVALID, "rici_batch_run: NULL plan");
+    DeviceGuard g(b->h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    rici_ctx* h = b->h;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = timed(h, "batch", s, [&] { return hipGraphLaunch(b->exec, s); });
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return RICI_OK;
+}
+
+void rici_batch_destroy(rici_batch b)
+{
+    if (!b) return;
+    DeviceGuard g(b->h->device);
+    (void)hipDeviceSynchronize();
+    destroy_plan(b);
+}
+
+uint64_t rici_batch_scratch_bytes(rici_batch b) { return b ? (uint64_t)b->scratch_bytes : 0u; }
 
 }  // extern "C"

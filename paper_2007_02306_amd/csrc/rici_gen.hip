@@ -38,12 +38,11 @@ __device__ __forceinline__ bool finite3(float a, float b, float c)
 
 // ------------------------------------------------------------- triangle prep
 
-__global__ void __launch_bounds__(256)
-k_gen_prep(const float* __restrict__ pos, uint32_t nv, const uint32_t* __restrict__ tri, uint32_t nt,
-           float4* __restrict__ cull, float4* __restrict__ verts, uint32_t* __restrict__ err)
+__device__ __forceinline__ void prep_triangle(const float* __restrict__ pos, uint32_t nv,
+                                              const uint32_t* __restrict__ tri, uint32_t t,
+                                              float4* __restrict__ cull, float4* __restrict__ verts,
+                                              uint32_t* __restrict__ err)
 {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nt) return;
     const uint32_t i0 = tri[3 * (size_t)t], i1 = tri[3 * (size_t)t + 1], i2 = tri[3 * (size_t)t + 2];
     float4 dead = make_float4(0.f, 0.f, 0.f, -INFINITY);   // never passes the cull
     if (i0 >= nv || i1 >= nv || i2 >= nv) {
@@ -76,6 +75,51 @@ k_gen_prep(const float* __restrict__ pos, uint32_t nv, const uint32_t* __restric
     float mag = fmaxf(fabsf(mx), fmaxf(fabsf(my), fabsf(mz)));
     r = r * 1.0001f + 1e-5f * (mag + r) + 1e-30f;
     cull[t] = make_float4(mx, my, mz, r);
+}
+
+__global__ void __launch_bounds__(256)
+k_gen_prep(const float* __restrict__ pos, uint32_t nv, const uint32_t* __restrict__ tri, uint32_t nt,
+           float4* __restrict__ cull, float4* __restrict__ verts, uint32_t* __restrict__ err)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nt) prep_triangle(pos, nv, tri, t, cull, verts, err);
+}
+
+// Bounding sphere of each run of 64 consecutive triangles (one wavefront's
+// chunk in k_gen): it contains every triangle sphere of the run, so a run whose
+// sphere misses an image's support volume can be skipped as a whole.
+__device__ __forceinline__ void cluster_sphere(const float4* __restrict__ cull, uint32_t nt, uint32_t c,
+                                               float4* __restrict__ clusters, int lane)
+{
+    const uint32_t t = c * 64 + lane;
+    const float4 s = t < nt ? cull[t] : make_float4(0.f, 0.f, 0.f, -INFINITY);
+    const bool live = s.w >= 0.f;
+    float lo[3] = { live ? s.x - s.w : INFINITY, live ? s.y - s.w : INFINITY, live ? s.z - s.w : INFINITY };
+    float hi[3] = { live ? s.x + s.w : -INFINITY, live ? s.y + s.w : -INFINITY, live ? s.z + s.w : -INFINITY };
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fminf(lo[k], __shfl_xor(lo[k], o, 64));
+            hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o, 64));
+        }
+    const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
+    float r = live ? sqrtf((s.x - cx) * (s.x - cx) + (s.y - cy) * (s.y - cy) + (s.z - cz) * (s.z - cz)) + s.w : -INFINITY;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) r = fmaxf(r, __shfl_xor(r, o, 64));
+    if (lane == 0) {
+        const float mag = fmaxf(fabsf(cx), fmaxf(fabsf(cy), fabsf(cz)));
+        const bool any = r >= 0.f;   // at least one live triangle
+        clusters[c] = any ? make_float4(cx, cy, cz, r * 1.0001f + 1e-5f * (mag + r) + 1e-30f)
+                          : make_float4(0.f, 0.f, 0.f, -INFINITY);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_gen_clusters(const float4* __restrict__ cull, uint32_t nt, float4* __restrict__ clusters, uint32_t nc)
+{
+    const uint32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c < nc) cluster_sphere(cull, nt, c, clusters, threadIdx.x & 63);
 }
 
 // ------------------------------------------------------------ exact pieces
@@ -264,14 +308,18 @@ __device__ void process_batch(GenLds& L, int wave, int lane, uint32_t head, uint
     }
 }
 
-__global__ void __launch_bounds__(kWaves * 64)
-k_gen(const float4* __restrict__ cull, const float4* __restrict__ verts, uint32_t nt,
-      const float* __restrict__ op_pos, const float* __restrict__ op_nrm, uint32_t n, float Rf,
-      uint32_t* __restrict__ out, uint32_t* __restrict__ err)
+// kG images (img0 .. img0 + kG - 1) of one job, by the whole workgroup.
+__device__ void gen_images(GenLds& L, const GenJob& J, uint32_t img0, float Rf, uint32_t* __restrict__ err)
 {
-    __shared__ GenLds L;
+    const float4* __restrict__ cull = J.cull;
+    const float4* __restrict__ clusters = J.clusters;
+    const float4* __restrict__ verts = J.verts;
+    const uint32_t nt = J.nt, n = J.n;
+    const float* __restrict__ op_pos = J.op_pos;
+    const float* __restrict__ op_nrm = J.op_nrm;
+    uint32_t* __restrict__ out = J.out;
+
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t img0 = blockIdx.x * kG;
 
     for (int i = tid; i < kG * NB * kDiffStride; i += kWaves * 64) (&L.diff[0][0])[i] = 0u;
     if (tid < kG) {
@@ -330,20 +378,32 @@ k_gen(const float4* __restrict__ cull, const float4* __restrict__ verts, uint32_
     uint32_t head = 0, tail = 0;   // wave-uniform ring counters
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-    for (uint32_t base = (uint32_t)wave * 64; base < nt; base += kWaves * 64) {
+    // Conservative FP32 sphere test against image g's support volume: the slab
+    // |beta| <= R/2 and the cylinder alpha <= R, both with margins.
+    auto reaches = [&](const float4& sp, int g) -> bool {
+        const float dx = sp.x - P[g][0], dy = sp.y - P[g][1], dz = sp.z - P[g][2];
+        const float h = P[g][3] * dx + P[g][4] * dy + P[g][5] * dz;
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        const float a2 = d2 - h * h;
+        const float la = P[g][7] + sp.w;
+        return (fabsf(h) <= P[g][6] + sp.w) & (a2 <= la * la);
+    };
+
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
+    for (uint32_t base = wv * 64; base < nt; base += kWaves * 64) {
+        // whole 64-triangle run first (same value in every lane)
+        const float4 cs = clusters[base / 64];
+        uint32_t cmask = 0;
+#pragma unroll
+        for (int g = 0; g < kG; ++g) cmask |= (reaches(cs, g) ? 1u : 0u) << g;
+        cmask = __builtin_amdgcn_readfirstlane(cmask);
+        if (cmask == 0) continue;
         const uint32_t t = base + lane;
         const float4 s = t < nt ? cull[t] : make_float4(0.f, 0.f, 0.f, -INFINITY);
         uint32_t mask = 0;
 #pragma unroll
-        for (int g = 0; g < kG; ++g) {
-            const float dx = s.x - P[g][0], dy = s.y - P[g][1], dz = s.z - P[g][2];
-            const float h = P[g][3] * dx + P[g][4] * dy + P[g][5] * dz;
-            const float d2 = dx * dx + dy * dy + dz * dz;
-            const float a2 = d2 - h * h;
-            const float la = P[g][7] + s.w;
-            const bool pass = (fabsf(h) <= P[g][6] + s.w) & (a2 <= la * la);
-            mask |= (pass ? 1u : 0u) << g;
-        }
+        for (int g = 0; g < kG; ++g)
+            if (cmask & (1u << g)) mask |= (reaches(s, g) ? 1u : 0u) << g;
         // append the pairs to the ring, one image bit per round
         while (__ballot(mask != 0)) {
             const bool has = mask != 0;
@@ -372,6 +432,74 @@ k_gen(const float4* __restrict__ cull, const float4* __restrict__ verts, uint32_
         const uint32_t v = wave_inclusive_scan(L.diff[g][r * kDiffStride + lane], lane);
         out[(size_t)img * NPIX + r * NB + lane] = v;
     }
+    __syncthreads();   // the LDS is reused by the workgroup's next group
+}
+
+__global__ void __launch_bounds__(kWaves * 64)
+k_gen(GenJob J, float Rf, uint32_t* __restrict__ err)
+{
+    __shared__ GenLds L;
+    gen_images(L, J, blockIdx.x * kG, Rf, err);
+}
+
+// Persistent form for many meshes: every workgroup takes (job, image group)
+// items from a device counter until none are left.  Jobs are stored largest
+// first, so the long items start early and the short ones fill the tail.
+__global__ void __launch_bounds__(kWaves * 64)
+k_gen_batched(const GenJob* __restrict__ jobs, uint32_t njobs, uint32_t total_items, float Rf,
+              uint32_t* __restrict__ counter, uint32_t* __restrict__ err)
+{
+    __shared__ GenLds L;
+    __shared__ uint32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= total_items) break;
+        uint32_t lo = 0, hi = njobs - 1;          // last job with item_start <= item
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            if (jobs[mid].item_start <= item) lo = mid; else hi = mid - 1;
+        }
+        const GenJob& J = jobs[lo];
+        gen_images(L, J, (item - J.item_start) * kG, Rf, err);
+    }
+}
+
+__device__ __forceinline__ uint32_t find_job(const GenJob* __restrict__ jobs, uint32_t njobs, uint64_t x, bool chunks)
+{
+    uint32_t lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        const uint64_t st = chunks ? jobs[mid].chunk_start : jobs[mid].tri_start;
+        if (st <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256)
+k_gen_prep_batched(const GenJob* __restrict__ jobs, uint32_t njobs, uint64_t total, uint32_t* __restrict__ err)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= total) return;
+    const GenJob& J = jobs[find_job(jobs, njobs, x, false)];
+    prep_triangle(J.pos, J.nv, J.tri, (uint32_t)(x - J.tri_start), J.cull, J.verts, err);
+}
+
+__global__ void __launch_bounds__(256)
+k_gen_clusters_batched(const GenJob* __restrict__ jobs, uint32_t njobs, uint64_t total)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (x >= total) return;
+    const GenJob& J = jobs[find_job(jobs, njobs, x, true)];
+    cluster_sphere(J.cull, J.nt, (uint32_t)(x - J.chunk_start), J.clusters, threadIdx.x & 63);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 }  // namespace
@@ -385,14 +513,49 @@ hipError_t launch_gen_prep(const float* pos, uint32_t nv, const uint32_t* tri, u
     return hipGetLastError();
 }
 
-hipError_t launch_gen(const float4* cull, const float4* verts, uint32_t nt,
+hipError_t launch_gen_clusters(const float4* cull, uint32_t nt, float4* clusters, hipStream_t s)
+{
+    const uint32_t nc = (nt + 63) / 64;
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gen_clusters, dim3((nc + 3) / 4), dim3(256), 0, s, cull, nt, clusters, nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen(const float4* cull, const float4* clusters, const float4* verts, uint32_t nt,
                       const float* op_pos, const float* op_nrm, uint32_t n, float R,
                       uint32_t* out, uint32_t* err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    GenJob J = {};
+    J.nt = nt; J.op_pos = op_pos; J.op_nrm = op_nrm; J.n = n; J.out = out;
+    J.cull = const_cast<float4*>(cull); J.clusters = const_cast<float4*>(clusters); J.verts = const_cast<float4*>(verts);
     const uint32_t blocks = (n + kG - 1) / kG;
-    hipLaunchKernelGGL(k_gen, dim3(blocks), dim3(kWaves * 64), 0, s, cull, verts, nt, op_pos, op_nrm, n, R,
-                       out, err);
+    hipLaunchKernelGGL(k_gen, dim3(blocks), dim3(kWaves * 64), 0, s, J, R, err);
+    return hipGetLastError();
+}
+
+uint32_t gen_group_images() { return kG; }
+
+hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total_tris, uint64_t total_chunks,
+                              uint32_t total_items, float R, uint32_t* counter, uint32_t* err, uint32_t grid,
+                              hipStream_t s)
+{
+    if (njobs == 0) return hipSuccess;
+    if (total_tris > 0) {
+        hipLaunchKernelGGL(k_gen_prep_batched, dim3((uint32_t)((total_tris + 255) / 256)), dim3(256), 0, s, jobs, njobs,
+                           total_tris, err);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gen_clusters_batched, dim3((uint32_t)((total_chunks + 3) / 4)), dim3(256), 0, s, jobs,
+                           njobs, total_chunks);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, counter, 1u, 0u);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (total_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gen_batched, dim3(grid), dim3(kWaves * 64), 0, s, jobs, njobs, total_items, R, counter, err);
     return hipGetLastError();
 }
 

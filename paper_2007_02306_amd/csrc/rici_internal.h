@@ -15,11 +15,31 @@ constexpr int NPIX = NB * NB;       // pixels per image
 constexpr size_t kTriCullBytes = 16;
 constexpr size_t kTriVertBytes = 48;
 
+// One mesh of a batched call (device copy).  cull / clusters / verts point at
+// this job's part of the scratch; tri_start / chunk_start / item_start are the
+// job's first triangle, 64-triangle chunk and image-group work item in the
+// flattened index spaces of the batched kernels.
+struct GenJob {
+    const float* pos; uint32_t nv;
+    const uint32_t* tri; uint32_t nt;
+    const float* op_pos; const float* op_nrm; uint32_t n;
+    uint32_t* out;
+    float4* cull; float4* clusters; float4* verts;
+    uint64_t tri_start, chunk_start;
+    uint32_t item_start;
+};
+
 hipError_t launch_gen_prep(const float* pos, uint32_t nv, const uint32_t* tri, uint32_t nt,
                            float4* cull, float4* verts, uint32_t* err, hipStream_t s);
-hipError_t launch_gen(const float4* cull, const float4* verts, uint32_t nt,
+hipError_t launch_gen_clusters(const float4* cull, uint32_t nt, float4* clusters, hipStream_t s);
+hipError_t launch_gen(const float4* cull, const float4* clusters, const float4* verts, uint32_t nt,
                       const float* op_pos, const float* op_nrm, uint32_t n, float R,
                       uint32_t* out, uint32_t* err, hipStream_t s);
+uint32_t gen_group_images();   // images per work item of the generation kernels
+// prep + clusters + persistent generation over `njobs` jobs stored largest first
+hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total_tris, uint64_t total_chunks,
+                              uint32_t total_items, float R, uint32_t* counter, uint32_t* err, uint32_t grid,
+                              hipStream_t s);
 
 // -------------------------------------------------------------------- search
 // Column-delta planes in "fragment-major" order: for every group of 16 images
@@ -47,8 +67,42 @@ struct SearchPrep {
     uint32_t ngroups;      // slots / 16
 };
 
+// Arguments of the MFMA search over one (needles, haystack) pair of sets.
+struct SearchArgs {
+    const int8_t* a_planes; uint32_t a_groups; uint32_t nn;
+    const int8_t* b_planes; uint32_t b_groups; uint32_t nh;
+    const uint32_t* nmax;
+    const uint32_t* hmax;      // per haystack slot
+    const uint32_t* hperm;     // haystack slot -> image
+    const int32_t* thr;
+    const int64_t* sumsq;
+    uint32_t* rank;
+    int64_t* matrix;
+    uint32_t tiles_m, tiles_n, per_xcd;
+};
+
+// One ranking job of a batched call (device copy): its arguments, its scratch
+// and its first index in each flattened index space of the batched kernels.
+struct SearchJob {
+    SearchArgs A;
+    const uint32_t* needles; const uint32_t* hay; const uint32_t* true_idx;
+    int64_t* dstar;
+    uint32_t* lists;
+    SearchPrep np, hp;
+    uint64_t ngrp_start, hslot_start, himg_start, hgrp_start, needle_start;
+    uint32_t tile_start;
+};
+
+struct SearchTotals {
+    uint64_t needle_groups, hay_slots, hay_images, hay_groups, needles, tiles;
+};
+
 hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side,
                              const SearchPrep& p, hipStream_t s);
+// every prep, rank and fallback step of `njobs` jobs (stored largest first),
+// with a persistent search kernel of `grid` workgroups
+hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,
+                                 uint32_t grid, hipStream_t s);
 size_t haystack_slots(uint32_t nh);   // slots allocated for a haystack of nh images
 hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                                 const uint32_t* true_idx, const int64_t* sumsq, const uint32_t* nmax,
@@ -63,6 +117,7 @@ hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t*
 
 size_t search_groups(uint32_t n);   // fragment groups allocated for n images
 size_t search_lds_bytes();          // dynamic LDS of the search kernel
+hipError_t prepare_search_kernels(); // raise the search kernels' LDS limit (before any graph capture)
 uint32_t search_tile_m();
 uint32_t search_tile_n();
 

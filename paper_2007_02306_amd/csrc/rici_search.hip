@@ -36,15 +36,13 @@ constexpr uint32_t kPad = 0xFFFFFFFFu;
 
 // One block per group of 16 images; thread (row-in-step, lane) with
 // lane = 16 * q + i writes columns 16 q .. 16 q + 15 of image i.
-__global__ void __launch_bounds__(256)
-k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
-             int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
-             uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm)
+__device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
+                            int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
+                            uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm, uint32_t grp)
 {
     __shared__ uint32_t smax[4][kGroup];
     __shared__ int64_t ssum[4][kGroup];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t grp = blockIdx.x;
     const int i = lane & 15, q = lane >> 4;
     const uint32_t slot = grp * kGroup + i;
     const uint32_t img = perm ? perm[slot] : slot;
@@ -125,6 +123,14 @@ k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
     }
 }
 
+__global__ void __launch_bounds__(256)
+k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
+             int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
+             uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm)
+{
+    delta_group(images, n, needle_side, planes, ngroups, sumsq, maxabs, perm, blockIdx.x);
+}
+
 // Haystack slot assignment.  k_hay_init marks every slot as padding;
 // k_hay_stats (one wavefront per image) finds max |D|; k_hay_assign (one
 // workgroup, prefix sums) gives images with |D| <= 11 the front slots and the
@@ -136,14 +142,11 @@ k_hay_init(uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs, uint32_t 
     if (s < nslots) { perm[s] = kPad; maxabs[s] = kPad; }
 }
 
-__global__ void __launch_bounds__(256)
-k_hay_stats(const uint32_t* __restrict__ images, uint32_t n, uint32_t* __restrict__ maxabs_img)
+__device__ void hay_stats_one(const uint32_t* __restrict__ images, uint32_t* __restrict__ maxabs_img,
+                              uint32_t img, int lane)
 {
     // each load instruction covers four rows: lane l holds columns
     // 4 (l % 16) .. 4 (l % 16) + 3 of row 4 it + l / 16
-    const int lane = threadIdx.x & 63;
-    const uint32_t img = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (img >= n) return;
     const uint4* im = reinterpret_cast<const uint4*>(images + (size_t)img * NPIX);
     const bool first = (lane & 15) == 0;
     uint32_t mx = 0;
@@ -164,9 +167,15 @@ k_hay_stats(const uint32_t* __restrict__ images, uint32_t n, uint32_t* __restric
     if (lane == 0) maxabs_img[img] = mx;
 }
 
-__global__ void __launch_bounds__(1024)
-k_hay_assign(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslots,
-             uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs)
+__global__ void __launch_bounds__(256)
+k_hay_stats(const uint32_t* __restrict__ images, uint32_t n, uint32_t* __restrict__ maxabs_img)
+{
+    const uint32_t img = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (img < n) hay_stats_one(images, maxabs_img, img, threadIdx.x & 63);
+}
+
+__device__ void hay_assign_block(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslots,
+                                 uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs)
 {
     __shared__ uint32_t wsum[16][2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -196,6 +205,13 @@ k_hay_assign(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslot
     }
 }
 
+__global__ void __launch_bounds__(1024)
+k_hay_assign(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslots,
+             uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs)
+{
+    hay_assign_block(maxabs_img, n, nslots, perm, maxabs);
+}
+
 // ------------------------------------------------------------ exact int64 CRD
 
 // CRD(n, h) by Eq. 7 for one pair, summed by one wavefront: lane = column.
@@ -219,15 +235,12 @@ __device__ __forceinline__ int64_t crd_wave(const uint32_t* __restrict__ nimg, c
 // d*_i = CRD(n_i, h_true(i)); MFMA threshold thr_i = d*_i - |D_n|^2 (clamped;
 // INT_MIN disables the MFMA count for needles outside the int8 range and for a
 // bad true index); rank zeroed.
-__global__ void __launch_bounds__(256)
-k_true_distance(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_t* __restrict__ hay, uint32_t nh,
-                const uint32_t* __restrict__ true_idx, const int64_t* __restrict__ sumsq,
-                const uint32_t* __restrict__ nmax, int64_t* __restrict__ dstar, int32_t* __restrict__ thr,
-                uint32_t* __restrict__ rank)
+__device__ void true_distance_one(const uint32_t* __restrict__ needles, const uint32_t* __restrict__ hay,
+                                  uint32_t nh, const uint32_t* __restrict__ true_idx,
+                                  const int64_t* __restrict__ sumsq, const uint32_t* __restrict__ nmax,
+                                  int64_t* __restrict__ dstar, int32_t* __restrict__ thr, uint32_t* __restrict__ rank,
+                                  uint32_t i, int lane)
 {
-    const int lane = threadIdx.x & 63;
-    const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= nn) return;
     const uint32_t t = true_idx[i];
     if (t >= nh) {
         if (lane == 0) { dstar[i] = -1; thr[i] = INT_MIN; rank[i] = nh; }
@@ -241,6 +254,16 @@ k_true_distance(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_
         thr[i] = nmax[i] <= kSlow ? (int32_t)th : INT_MIN;
         rank[i] = 0;
     }
+}
+
+__global__ void __launch_bounds__(256)
+k_true_distance(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_t* __restrict__ hay, uint32_t nh,
+                const uint32_t* __restrict__ true_idx, const int64_t* __restrict__ sumsq,
+                const uint32_t* __restrict__ nmax, int64_t* __restrict__ dstar, int32_t* __restrict__ thr,
+                uint32_t* __restrict__ rank)
+{
+    const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i < nn) true_distance_one(needles, hay, nh, true_idx, sumsq, nmax, dstar, thr, rank, i, threadIdx.x & 63);
 }
 
 // ----------------------------------------------------------------- MFMA search
@@ -264,19 +287,6 @@ struct SearchCfg {
 // one-row stages filled by direct global -> LDS loads
 using Cfg = SearchCfg<2, 4, 8, 4, 4>;
 
-struct SearchArgs {
-    const int8_t* a_planes; uint32_t a_groups; uint32_t nn;
-    const int8_t* b_planes; uint32_t b_groups; uint32_t nh;
-    const uint32_t* nmax;
-    const uint32_t* hmax;      // per haystack slot
-    const uint32_t* hperm;     // haystack slot -> image
-    const int32_t* thr;
-    const int64_t* sumsq;
-    uint32_t* rank;
-    int64_t* matrix;
-    uint32_t tiles_m, tiles_n, per_xcd;
-};
-
 // s_waitcnt with only the vector-memory counter constrained (gfx9 encoding)
 template <int V>
 __device__ __forceinline__ void wait_vmcnt()
@@ -296,27 +306,25 @@ __device__ __forceinline__ void stage_barrier()
     asm volatile("" ::: "memory");
 }
 
-template <class C>
-__global__ void __launch_bounds__(C::kThreads)
-k_search(SearchArgs A)
+// Tile `logical` of a tiles_m x tiles_n grid in an L2-friendly order: groups
+// of 8 needle tiles are walked haystack tile by haystack tile.
+__device__ __forceinline__ void tile_coords(uint32_t logical, uint32_t tiles_m, uint32_t tiles_n,
+                                            uint32_t& tm, uint32_t& tn)
 {
-    extern __shared__ __align__(16) int8_t lds[];
+    constexpr uint32_t GM = 8;
+    const uint32_t in_group = GM * tiles_n;
+    const uint32_t first_m = (logical / in_group) * GM;
+    const uint32_t gsz = min(tiles_m - first_m, GM);
+    tm = first_m + (logical % in_group) % gsz;
+    tn = (logical % in_group) / gsz;
+}
+
+// One 256 x 256 (needle x haystack) tile: every workgroup thread takes part.
+template <class C>
+__device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_t* lds)
+{
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / C::kWN, wn = wave % C::kWN;
-
-    // Tile order: consecutive workgroup ids land on different XCDs (round
-    // robin), so first gather each XCD's ids into one contiguous range, then
-    // walk that range in groups of 8 needle tiles so the tiles resident on one
-    // XCD share needle and haystack fragments in its L2.
-    const uint32_t b = blockIdx.x;
-    const uint32_t logical = (b & 7u) * A.per_xcd + (b >> 3);
-    if (logical >= A.tiles_m * A.tiles_n) return;
-    constexpr uint32_t GM = 8;
-    const uint32_t in_group = GM * A.tiles_n;
-    const uint32_t first_m = (logical / in_group) * GM;
-    const uint32_t gsz = min(A.tiles_m - first_m, GM);
-    const uint32_t tm = first_m + (logical % in_group) % gsz;
-    const uint32_t tn = (logical % in_group) / gsz;
     const uint32_t ga0 = tm * C::GA, gb0 = tn * C::GB;
 
     // q phase needed iff some usable haystack image of the tile has
@@ -453,13 +461,54 @@ k_search(SearchArgs A)
     }
 }
 
+template <class C>
+__global__ void __launch_bounds__(C::kThreads)
+k_search(SearchArgs A)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    // consecutive workgroup ids land on different XCDs (round robin): gather
+    // each XCD's ids into one contiguous range of the tile order so the tiles
+    // resident on one XCD share fragments in its L2
+    const uint32_t b = blockIdx.x;
+    const uint32_t logical = (b & 7u) * A.per_xcd + (b >> 3);
+    if (logical >= A.tiles_m * A.tiles_n) return;
+    uint32_t tm, tn;
+    tile_coords(logical, A.tiles_m, A.tiles_n, tm, tn);
+    search_tile<C>(A, tm, tn, lds);
+}
+
+// Persistent form for many searches: workgroups take (job, tile) items from a
+// device counter until none are left; jobs are stored largest first.
+template <class C>
+__global__ void __launch_bounds__(C::kThreads)
+k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t total, uint32_t* __restrict__ counter)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    __shared__ uint32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        uint32_t lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            if (jobs[mid].tile_start <= item) lo = mid; else hi = mid - 1;
+        }
+        const SearchArgs& A = jobs[lo].A;
+        uint32_t tm, tn;
+        tile_coords(item - jobs[lo].tile_start, A.tiles_m, A.tiles_n, tm, tn);
+        search_tile<C>(A, tm, tn, lds);
+    }
+}
+
 // ------------------------------------------------------- out-of-range images
 
 // lists[0] = #needles with |D| > 127, lists[1] = #haystack images with
 // |D| > 127, then the needle ids (nn slots) and the haystack ids (nh slots).
-__global__ void __launch_bounds__(1024)
-k_slow_lists(const uint32_t* __restrict__ nmax, uint32_t nn, const uint32_t* __restrict__ hmax, uint32_t nh,
-             uint32_t* __restrict__ lists)
+__device__ void slow_lists_block(const uint32_t* __restrict__ nmax, uint32_t nn, const uint32_t* __restrict__ hmax,
+                                 uint32_t nh, uint32_t* __restrict__ lists)
 {
     __shared__ uint32_t cn, ch;
     if (threadIdx.x == 0) { cn = 0; ch = 0; }
@@ -470,21 +519,28 @@ k_slow_lists(const uint32_t* __restrict__ nmax, uint32_t nn, const uint32_t* __r
         if (hmax[j] > kSlow) lists[2 + (size_t)nn + atomicAdd(&ch, 1u)] = j;
     __syncthreads();
     if (threadIdx.x == 0) { lists[0] = cn; lists[1] = ch; }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024)
+k_slow_lists(const uint32_t* __restrict__ nmax, uint32_t nn, const uint32_t* __restrict__ hmax, uint32_t nh,
+             uint32_t* __restrict__ lists)
+{
+    slow_lists_block(nmax, nn, hmax, nh, lists);
 }
 
 // Every (needle, haystack) pair with an out-of-range image, by Eq. 7 in int64.
 // A fixed grid of wavefronts walks the pair list; the list length is bounded
 // by nn * nh, so every wave reaches the end.
-__global__ void __launch_bounds__(256)
-k_fallback(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_t* __restrict__ hay, uint32_t nh,
-           const uint32_t* __restrict__ nmax, const uint32_t* __restrict__ lists,
-           const int64_t* __restrict__ dstar, uint32_t* __restrict__ rank, int64_t* __restrict__ matrix)
+__device__ void fallback_pairs(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_t* __restrict__ hay,
+                               uint32_t nh, const uint32_t* __restrict__ nmax, const uint32_t* __restrict__ lists,
+                               const int64_t* __restrict__ dstar, uint32_t* __restrict__ rank,
+                               int64_t* __restrict__ matrix, uint64_t wave_id, uint64_t nwaves)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t ns = lists[0], nhs = lists[1];
     const uint64_t part_a = ns * nh, total = part_a + nhs * nn;
-    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t w = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < total; w += nwaves) {
+    for (uint64_t w = wave_id; w < total; w += nwaves) {
         uint32_t i, j;
         if (w < part_a) {
             i = lists[2 + w / nh];
@@ -502,6 +558,107 @@ k_fallback(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_t* __
         }
     }
 }
+
+__global__ void __launch_bounds__(256)
+k_fallback(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_t* __restrict__ hay, uint32_t nh,
+           const uint32_t* __restrict__ nmax, const uint32_t* __restrict__ lists,
+           const int64_t* __restrict__ dstar, uint32_t* __restrict__ rank, int64_t* __restrict__ matrix)
+{
+    fallback_pairs(needles, nn, hay, nh, nmax, lists, dstar, rank, matrix,
+                   (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6),
+                   (uint64_t)gridDim.x * (blockDim.x >> 6));
+}
+
+// ------------------------------------------------------------ batched prep
+
+// job owning flat index x, given a per-job start offset selected by `which`
+template <int which>
+__device__ __forceinline__ uint32_t job_of(const SearchJob* __restrict__ jobs, uint32_t njobs, uint64_t x)
+{
+    uint32_t lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        const uint64_t st = which == 0 ? jobs[mid].ngrp_start : which == 1 ? jobs[mid].hslot_start
+                          : which == 2 ? jobs[mid].himg_start : which == 3 ? jobs[mid].hgrp_start
+                          : jobs[mid].needle_start;
+        if (st <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256)
+k_needle_prep_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
+{
+    const SearchJob& J = jobs[job_of<0>(jobs, njobs, blockIdx.x)];
+    delta_group(J.needles, J.A.nn, 1, J.np.planes, J.np.ngroups, J.np.sumsq, J.np.maxabs, nullptr,
+                (uint32_t)(blockIdx.x - J.ngrp_start));
+}
+
+__global__ void __launch_bounds__(256)
+k_hay_init_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint64_t total)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= total) return;
+    const SearchJob& J = jobs[job_of<1>(jobs, njobs, x)];
+    const uint64_t s = x - J.hslot_start;
+    J.hp.perm[s] = kPad;
+    J.hp.maxabs[s] = kPad;
+}
+
+__global__ void __launch_bounds__(256)
+k_hay_stats_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint64_t total)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (x >= total) return;
+    const SearchJob& J = jobs[job_of<2>(jobs, njobs, x)];
+    hay_stats_one(J.hay, J.hp.maxabs_img, (uint32_t)(x - J.himg_start), threadIdx.x & 63);
+}
+
+__global__ void __launch_bounds__(1024)
+k_hay_assign_batched(const SearchJob* __restrict__ jobs)
+{
+    const SearchJob& J = jobs[blockIdx.x];
+    hay_assign_block(J.hp.maxabs_img, J.A.nh, J.hp.ngroups * kGroup, J.hp.perm, J.hp.maxabs);
+}
+
+__global__ void __launch_bounds__(256)
+k_hay_prep_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
+{
+    const SearchJob& J = jobs[job_of<3>(jobs, njobs, blockIdx.x)];
+    delta_group(J.hay, J.A.nh, 0, J.hp.planes, J.hp.ngroups, nullptr, J.hp.maxabs, J.hp.perm,
+                (uint32_t)(blockIdx.x - J.hgrp_start));
+}
+
+__global__ void __launch_bounds__(256)
+k_true_distance_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint64_t total)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (x >= total) return;
+    const SearchJob& J = jobs[job_of<4>(jobs, njobs, x)];
+    true_distance_one(J.needles, J.hay, J.A.nh, J.true_idx, J.np.sumsq, J.np.maxabs, J.dstar,
+                      const_cast<int32_t*>(J.A.thr), J.A.rank, (uint32_t)(x - J.needle_start), threadIdx.x & 63);
+}
+
+__global__ void __launch_bounds__(1024)
+k_slow_lists_batched(const SearchJob* __restrict__ jobs)
+{
+    const SearchJob& J = jobs[blockIdx.x];
+    slow_lists_block(J.np.maxabs, J.A.nn, J.hp.maxabs_img, J.A.nh, J.lists);
+}
+
+__global__ void __launch_bounds__(256)
+k_fallback_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
+{
+    const uint64_t wave_id = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint32_t j = 0; j < njobs; ++j) {
+        const SearchJob& J = jobs[j];
+        fallback_pairs(J.needles, J.A.nn, J.hay, J.A.nh, J.np.maxabs, J.lists, J.dstar, J.A.rank, nullptr,
+                       wave_id, nwaves);
+    }
+}
+
+__global__ void k_zero_counter(uint32_t* __restrict__ c) { if (threadIdx.x == 0) *c = 0u; }
 
 }  // namespace
 
@@ -589,7 +746,48 @@ hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t*
     return hipGetLastError();
 }
 
+hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,
+                                 uint32_t grid, hipStream_t s)
+{
+    if (njobs == 0) return hipSuccess;
+#define RICI_LAUNCH(...)                                   \
+    do {                                                   \
+        hipLaunchKernelGGL(__VA_ARGS__);                   \
+        hipError_t e_ = hipGetLastError();                 \
+        if (e_ != hipSuccess) return e_;                   \
+    } while (0)
+    if (T.needle_groups) RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(256), 0, s, jobs, njobs);
+    if (T.hay_slots)
+        RICI_LAUNCH(k_hay_init_batched, dim3((uint32_t)((T.hay_slots + 255) / 256)), dim3(256), 0, s, jobs, njobs,
+                    T.hay_slots);
+    if (T.hay_images)
+        RICI_LAUNCH(k_hay_stats_batched, dim3((uint32_t)((T.hay_images + 3) / 4)), dim3(256), 0, s, jobs, njobs,
+                    T.hay_images);
+    RICI_LAUNCH(k_hay_assign_batched, dim3(njobs), dim3(1024), 0, s, jobs);
+    if (T.hay_groups) RICI_LAUNCH(k_hay_prep_batched, dim3((uint32_t)T.hay_groups), dim3(256), 0, s, jobs, njobs);
+    if (T.needles)
+        RICI_LAUNCH(k_true_distance_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
+                    T.needles);
+    RICI_LAUNCH(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
+    if (T.tiles)
+        RICI_LAUNCH(k_search_batched<Cfg>, dim3(grid), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, jobs, njobs,
+                    (uint32_t)T.tiles, counter);
+    RICI_LAUNCH(k_slow_lists_batched, dim3(njobs), dim3(1024), 0, s, jobs);
+    RICI_LAUNCH(k_fallback_batched, dim3(512), dim3(256), 0, s, jobs, njobs);
+#undef RICI_LAUNCH
+    return hipSuccess;
+}
+
 size_t search_lds_bytes() { return (size_t)Cfg::kLds; }
+
+hipError_t prepare_search_kernels()
+{
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<Cfg>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::kLds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_batched<Cfg>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::kLds);
+}
 uint32_t search_tile_m() { return Cfg::BM; }
 uint32_t search_tile_n() { return Cfg::BN; }
 

@@ -1,0 +1,99 @@
+"""GPU parity of the batched describe-and-rank plan (rici_batch_*): a batch of
+meshes of uneven size, replayed as a graph, must give exactly the plain
+per-mesh results (which the other GPU tests tie to the oracle), and sampled
+images must equal the oracle's outside flagged pixels."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev_f32, dev_u32, host_u32, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2007_02306_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _meshes(seed, count, lo, hi):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        t = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        m, _ = synth.configs.random_object(rng, t)
+        pos = m.positions.astype(np.float32)
+        nrm = synth.vertex_normals(pos, m.triangles)
+        ti = rng.permutation(pos.shape[0]).astype(np.uint32)
+        out.append((pos, m.triangles, nrm, ti))
+    return out
+
+
+def test_batch_matches_plain_path_and_oracle(ctx):
+    import torch
+    meshes = _meshes(4, 12, 60, 6000)
+    jobs = []
+    for k, (pos, tri, nrm, ti) in enumerate(meshes):
+        j = dict(positions=dev_f32(pos), triangles=dev_u32(tri), op_positions=dev_f32(pos), op_normals=dev_f32(nrm))
+        if k != 3:                      # one describe-only job
+            j["true_index"] = dev_u32(ti)
+        jobs.append(j)
+    say(f"  batch of {len(jobs)} meshes, triangles {[len(m[1]) for m in meshes]}")
+    b = ctx.batch(jobs, 0.3)
+    # plain path, mesh by mesh
+    plain = []
+    for k, (pos, tri, nrm, ti) in enumerate(meshes):
+        img = ctx.generate(jobs[k]["positions"], jobs[k]["triangles"], jobs[k]["op_positions"],
+                           jobs[k]["op_normals"], 0.3)
+        rk = ds = None
+        if k != 3:
+            rk, ds = ctx.distance_rank(img, img, jobs[k]["true_index"])
+        ctx.sync()
+        plain.append((host_u32(img), None if rk is None else host_u32(rk), None if ds is None else ds.cpu().numpy()))
+    for rep in range(3):
+        b.run()
+        ctx.sync()
+        # eager work between replays
+        scratch = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        for k in range(len(meshes)):
+            assert np.array_equal(host_u32(b.images[k]), plain[k][0]), f"replay {rep} mesh {k} images"
+            if k != 3:
+                assert np.array_equal(host_u32(b.rank[k]), plain[k][1]), f"replay {rep} mesh {k} ranks"
+                assert np.array_equal(b.true_distance[k].cpu().numpy(), plain[k][2])
+            else:
+                assert b.rank[k] is None
+        del scratch
+    # oracle on a sample of images of three meshes
+    for k in (0, 5, 11):
+        pos, tri, nrm, ti = meshes[k]
+        sel = np.unique(np.linspace(0, len(pos) - 1, 12).astype(int))
+        o, fl, _ = oracle.rici_rowrange(pos, tri, pos[sel], nrm[sel], 0.3)
+        g = host_u32(b.images[k])[sel]
+        assert not ((g != o) & ~fl).any(), f"mesh {k} differs from the oracle"
+    assert max(int(host_u32(r).max()) for r in b.rank if r is not None) > 0
+    b.close()
+
+
+def test_batch_empty_and_bad_jobs(ctx):
+    import torch
+    from paper_2007_02306_amd import RiciError
+    b = ctx.batch([], 0.3)
+    b.run()
+    ctx.sync()
+    b.close()
+    z = torch.zeros((0, 3), device="cuda")
+    b = ctx.batch([dict(positions=z, triangles=torch.zeros((0, 3), dtype=torch.int32, device="cuda"),
+                        op_positions=z, op_normals=z)], 0.3)
+    b.run()
+    ctx.sync()
+    b.close()
+    with pytest.raises(RiciError):
+        ctx.batch([], -1.0)
