@@ -159,6 +159,53 @@ void rici_batch_destroy(rici_batch b);
 uint64_t rici_batch_scratch_bytes(rici_batch b);
 
 /*
+ * Device-resident descriptor database and incremental queries (serving).
+ *
+ * rici_db_create prepares a haystack once: delta planes (partitioned by delta
+ * range), per-image statistics and the list of images outside the int8 range.
+ * The caller's images must stay valid while the database exists (true-match
+ * distances and exact out-of-range counts read them).  The database's tiles
+ * (rici_db_tiles, 256 haystack slots each) can then be scanned in any order and
+ * in any number of slices.
+ *
+ * rici_query_create prepares a set of needles against a database: delta planes,
+ * true-match distances d*_i = CRD(n_i, h_true[i]) (Eq. 7), out_rank zeroed, and
+ * the exact counts of every pair that involves an image outside the int8 range
+ * added to out_rank.  rici_db_scan adds, for each query, the counts
+ * #{h in tiles : CRD(n_i, h) < d*_i} of `tile_count` database tiles starting at
+ * `tile_begin` (wrapping around).  After every tile has been scanned exactly
+ * once for a query, its out_rank holds the rank of Sec. 4.1 step 6c -- whatever
+ * the order of the slices and whichever other queries shared them (integer
+ * counts, no rounding).  out_rank / out_true_distance are caller device buffers
+ * of num_needles entries.  A query's scratch is its own; queries and databases
+ * may be used from several handles on several streams, but a query must not be
+ * scanned by two calls at once.  At most RICI_SCAN_MAX_QUERIES queries per scan.
+ */
+#define RICI_SCAN_MAX_QUERIES 24
+
+typedef struct rici_db_ctx* rici_db;
+typedef struct rici_query_ctx* rici_query;
+
+int rici_db_create(rici_handle h, const uint32_t* images, uint32_t num_images, void* stream, rici_db* out);
+uint32_t rici_db_tiles(rici_db db);
+uint64_t rici_db_scratch_bytes(rici_db db);
+void rici_db_destroy(rici_db db);
+
+/* workspace: NULL (the query allocates and rici_query_destroy frees, after
+ * waiting for the device) or caller device memory of at least
+ * rici_query_footprint bytes that outlives the query (then rici_query_destroy
+ * neither frees nor waits: the caller must know the query's work is done). */
+int rici_query_create(rici_handle h, rici_db db, const uint32_t* needles, uint32_t num_needles,
+                      const uint32_t* true_index, uint32_t* out_rank, int64_t* out_true_distance,
+                      void* workspace, uint64_t workspace_bytes, void* stream, rici_query* out);
+/* Device bytes a query of num_needles needles against db holds (its admission footprint). */
+uint64_t rici_query_footprint(rici_db db, uint32_t num_needles);
+void rici_query_destroy(rici_query q);
+
+int rici_db_scan(rici_handle h, rici_db db, const rici_query* queries, uint32_t num_queries,
+                 uint32_t tile_begin, uint32_t tile_count, void* stream);
+
+/*
  * Kernel timing (measurement support).  When enabled, every kernel the handle
  * launches is bracketed by HIP events on its stream; rici_timing_get sums the
  * elapsed times of the completed launches of the named kernel ("gen",

@@ -19,6 +19,8 @@ EXPORTS = [
     "rici_generate", "rici_distance_rank", "rici_distance_matrix",
     "rici_timing_enable", "rici_timing_reset", "rici_timing_get",
     "rici_batch_create", "rici_batch_run", "rici_batch_destroy", "rici_batch_scratch_bytes",
+    "rici_db_create", "rici_db_tiles", "rici_db_scratch_bytes", "rici_db_destroy",
+    "rici_query_create", "rici_query_footprint", "rici_query_destroy", "rici_db_scan",
 ]
 
 
@@ -91,6 +93,23 @@ def load(path: str = LIB_PATH):
         lib.rici_batch_destroy.restype = None
         lib.rici_batch_scratch_bytes.argtypes = [P]
         lib.rici_batch_scratch_bytes.restype = ctypes.c_uint64
+        U64 = ctypes.c_uint64
+        lib.rici_db_create.argtypes = [P, P, U32, P, ctypes.POINTER(P)]
+        lib.rici_db_create.restype = I32
+        lib.rici_db_tiles.argtypes = [P]
+        lib.rici_db_tiles.restype = U32
+        lib.rici_db_scratch_bytes.argtypes = [P]
+        lib.rici_db_scratch_bytes.restype = U64
+        lib.rici_db_destroy.argtypes = [P]
+        lib.rici_db_destroy.restype = None
+        lib.rici_query_create.argtypes = [P, P, P, U32, P, P, P, P, U64, P, ctypes.POINTER(P)]
+        lib.rici_query_create.restype = I32
+        lib.rici_query_footprint.argtypes = [P, U32]
+        lib.rici_query_footprint.restype = U64
+        lib.rici_query_destroy.argtypes = [P]
+        lib.rici_query_destroy.restype = None
+        lib.rici_db_scan.argtypes = [P, P, ctypes.POINTER(P), U32, U32, U32, P]
+        lib.rici_db_scan.restype = I32
         _lib = lib
     return _lib
 

@@ -683,3 +683,227 @@ void rici_batch_destroy(rici_batch b)
 uint64_t rici_batch_scratch_bytes(rici_batch b) { return b ? (uint64_t)b->scratch_bytes : 0u; }
 
 }  // extern "C"
+
+// ------------------------------------------------------- database and queries
+
+struct rici_db_ctx {
+    rici_ctx* h = nullptr;
+    void* scratch = nullptr;
+    size_t bytes = 0;
+    rici::SearchPrep hp = {};
+    const uint32_t* images = nullptr;
+    uint32_t n = 0, tiles = 0;
+};
+
+struct rici_query_ctx {
+    rici_db db = nullptr;
+    void* scratch = nullptr;
+    bool owns = false;
+    size_t bytes = 0;
+    rici::SearchPrep np = {};
+    int32_t* thr = nullptr;
+    int64_t* dstar = nullptr;
+    uint32_t* rank = nullptr;
+    uint32_t nn = 0, tiles_m = 0;
+};
+
+namespace {
+
+struct QueryLayout {
+    size_t planes, sumsq, nmax, thr, dstar, lists, total;
+};
+
+QueryLayout query_layout(uint32_t nn, uint32_t nh)
+{
+    QueryLayout L;
+    const size_t ga = rici::search_groups(nn);
+    L.planes = align256(2 * ga * rici::kPlaneGroupBytes);
+    L.sumsq = align256(ga * rici::kGroup * sizeof(int64_t));
+    L.nmax = align256(ga * rici::kGroup * sizeof(uint32_t));
+    L.thr = align256((size_t)nn * sizeof(int32_t));
+    L.dstar = align256((size_t)nn * sizeof(int64_t));
+    L.lists = align256((2 + (size_t)nn + nh) * sizeof(uint32_t));
+    L.total = L.planes + L.sumsq + L.nmax + L.thr + L.dstar + L.lists;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rici_db_create(rici_handle h, const uint32_t* images, uint32_t num_images, void* stream, rici_db* out)
+{
+    if (!out) return fail(RICI_ERR_INVALID, "rici_db_create: out is NULL");
+    *out = nullptr;
+    if (!h) return fail(RICI_ERR_INVALID, "rici_db_create: NULL handle");
+    if (num_images == 0 || !images) return fail(RICI_ERR_INVALID, "rici_db_create: empty database");
+    if (num_images >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "rici_db_create: more than 2^31 images");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = rici::prepare_search_kernels();
+    if (e != hipSuccess) return hip_fail(e, "kernel attributes");
+    const size_t hs = rici::haystack_slots(num_images), gb = hs / rici::kGroup;
+    const size_t planes = align256(3 * gb * rici::kPlaneGroupBytes), hmax = align256(hs * 4),
+                 himg = align256((size_t)num_images * 4), perm = align256(hs * 4);
+    rici_db_ctx* db = new rici_db_ctx();
+    db->h = h;
+    db->bytes = planes + hmax + himg + perm;
+    e = hipMalloc(&db->scratch, db->bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete db;
+        return fail(RICI_ERR_OOM, "rici_db_create: cannot allocate %zu bytes", planes + hmax + himg + perm);
+    }
+    char* p = (char*)db->scratch;
+    db->hp.planes = (int8_t*)p; p += planes;
+    db->hp.maxabs = (uint32_t*)p; p += hmax;
+    db->hp.maxabs_img = (uint32_t*)p; p += himg;
+    db->hp.perm = (uint32_t*)p;
+    db->hp.sumsq = nullptr;
+    db->hp.ngroups = (uint32_t)gb;
+    db->images = images;
+    db->n = num_images;
+    db->tiles = (uint32_t)(hs / rici::search_tile_n());
+    hipStream_t s = (hipStream_t)stream;
+    e = timed(h, "delta_haystack", s, [&] { return rici::launch_delta_prep(images, num_images, 0, db->hp, s); });
+    if (e != hipSuccess) {
+        (void)hipFree(db->scratch);
+        delete db;
+        return hip_fail(e, "rici_db_create: delta planes");
+    }
+    *out = db;
+    return RICI_OK;
+}
+
+uint32_t rici_db_tiles(rici_db db) { return db ? db->tiles : 0u; }
+uint64_t rici_db_scratch_bytes(rici_db db) { return db ? (uint64_t)db->bytes : 0u; }
+
+void rici_db_destroy(rici_db db)
+{
+    if (!db) return;
+    DeviceGuard g(db->h->device);
+    (void)hipDeviceSynchronize();
+    if (db->scratch) (void)hipFree(db->scratch);
+    delete db;
+}
+
+uint64_t rici_query_footprint(rici_db db, uint32_t num_needles)
+{
+    return db ? (uint64_t)query_layout(num_needles, db->n).total : 0u;
+}
+
+int rici_query_create(rici_handle h, rici_db db, const uint32_t* needles, uint32_t num_needles,
+                      const uint32_t* true_index, uint32_t* out_rank, int64_t* out_true_distance, void* workspace,
+                      uint64_t workspace_bytes, void* stream, rici_query* out)
+{
+    if (!out) return fail(RICI_ERR_INVALID, "rici_query_create: out is NULL");
+    *out = nullptr;
+    if (!h || !db) return fail(RICI_ERR_INVALID, "rici_query_create: NULL handle or database");
+    if (num_needles == 0 || !needles || !true_index || !out_rank)
+        return fail(RICI_ERR_INVALID, "rici_query_create: empty query or NULL pointer");
+    if (num_needles >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "rici_query_create: too many needles");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    const QueryLayout L = query_layout(num_needles, db->n);
+    if (workspace && workspace_bytes < L.total)
+        return fail(RICI_ERR_INVALID, "rici_query_create: workspace of %llu bytes, %zu needed",
+                    (unsigned long long)workspace_bytes, L.total);
+    rici_query_ctx* q = new rici_query_ctx();
+    q->db = db;
+    q->bytes = L.total;
+    hipError_t e = hipSuccess;
+    if (workspace) {
+        q->scratch = workspace;
+    } else {
+        e = hipMalloc(&q->scratch, L.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete q;
+            return fail(RICI_ERR_OOM, "rici_query_create: cannot allocate %zu bytes", L.total);
+        }
+        q->owns = true;
+    }
+    char* p = (char*)q->scratch;
+    q->np.planes = (int8_t*)p; p += L.planes;
+    q->np.sumsq = (int64_t*)p; p += L.sumsq;
+    q->np.maxabs = (uint32_t*)p; p += L.nmax;
+    q->np.maxabs_img = q->np.maxabs;
+    q->np.perm = nullptr;
+    q->np.ngroups = (uint32_t)rici::search_groups(num_needles);
+    q->thr = (int32_t*)p; p += L.thr;
+    int64_t* own_dstar = (int64_t*)p; p += L.dstar;
+    uint32_t* lists = (uint32_t*)p;
+    q->dstar = out_true_distance ? out_true_distance : own_dstar;
+    q->rank = out_rank;
+    q->nn = num_needles;
+    q->tiles_m = (num_needles + rici::search_tile_m() - 1) / rici::search_tile_m();
+    hipStream_t s = (hipStream_t)stream;
+    e = timed(h, "delta_needle", s, [&] { return rici::launch_delta_prep(needles, num_needles, 1, q->np, s); });
+    if (e == hipSuccess)
+        e = timed(h, "true_distance", s, [&] {
+            return rici::launch_true_distance(needles, num_needles, db->images, db->n, true_index, q->np.sumsq,
+                                              q->np.maxabs, q->dstar, q->thr, out_rank, s);
+        });
+    if (e == hipSuccess)
+        e = timed(h, "fallback", s, [&] {
+            return rici::launch_fallback(needles, num_needles, db->images, db->n, q->np.maxabs, db->hp.maxabs_img,
+                                         q->dstar, out_rank, nullptr, lists, s);
+        });
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        if (q->owns) (void)hipFree(q->scratch);
+        delete q;
+        return hip_fail(e, "rici_query_create: launch");
+    }
+    *out = q;
+    return RICI_OK;
+}
+
+void rici_query_destroy(rici_query q)
+{
+    if (!q) return;
+    if (q->owns) {
+        DeviceGuard g(q->db->h->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(q->scratch);
+    }
+    delete q;
+}
+
+int rici_db_scan(rici_handle h, rici_db db, const rici_query* queries, uint32_t num_queries, uint32_t tile_begin,
+                 uint32_t tile_count, void* stream)
+{
+    if (!h || !db) return fail(RICI_ERR_INVALID, "rici_db_scan: NULL handle or database");
+    if (num_queries > (uint32_t)rici::kMaxScanJobs)
+        return fail(RICI_ERR_INVALID, "rici_db_scan: more than %d queries", rici::kMaxScanJobs);
+    if (num_queries > 0 && !queries) return fail(RICI_ERR_INVALID, "rici_db_scan: NULL queries");
+    if (tile_count > db->tiles || tile_begin >= db->tiles)
+        return fail(RICI_ERR_INVALID, "rici_db_scan: tile range beyond the database");
+    rici::ScanTable T = {};
+    uint32_t m = 0;
+    for (uint32_t k = 0; k < num_queries; ++k) {
+        const rici_query_ctx* q = queries[k];
+        if (!q || q->db != db) return fail(RICI_ERR_INVALID, "rici_db_scan: query %u is not of this database", k);
+        rici::SearchArgs& A = T.A[k];
+        A.a_planes = q->np.planes; A.a_groups = q->np.ngroups; A.nn = q->nn;
+        A.b_planes = db->hp.planes; A.b_groups = db->hp.ngroups; A.nh = db->n;
+        A.nmax = q->np.maxabs; A.hmax = db->hp.maxabs; A.hperm = db->hp.perm;
+        A.thr = q->thr; A.sumsq = q->np.sumsq; A.rank = q->rank; A.matrix = nullptr;
+        A.tiles_m = q->tiles_m; A.tiles_n = db->tiles; A.per_xcd = 0;
+        T.m_start[k] = m;
+        m += q->tiles_m;
+    }
+    T.m_start[num_queries] = m;
+    T.njobs = num_queries;
+    T.tile_begin = tile_begin;
+    T.tile_count = tile_count;
+    T.db_tiles = db->tiles;
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = timed(h, "scan", s, [&] { return rici::launch_search_scan(T, s); });
+    if (e != hipSuccess) return hip_fail(e, "rici_db_scan: launch");
+    return RICI_OK;
+}
+
+}  // extern "C"

@@ -93,6 +93,16 @@ struct SearchJob {
     uint32_t tile_start;
 };
 
+// One slice of a database scan: every listed query against database tiles
+// tile_begin .. tile_begin + tile_count - 1 (mod db_tiles).  Passed by value.
+constexpr int kMaxScanJobs = 24;
+struct ScanTable {
+    SearchArgs A[kMaxScanJobs];
+    uint32_t m_start[kMaxScanJobs + 1];   // prefix of the queries' needle tiles
+    uint32_t njobs, tile_begin, tile_count, db_tiles;
+};
+hipError_t launch_search_scan(const ScanTable& T, hipStream_t s);
+
 struct SearchTotals {
     uint64_t needle_groups, hay_slots, hay_images, hay_groups, needles, tiles;
 };

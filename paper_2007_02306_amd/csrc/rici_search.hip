@@ -503,6 +503,24 @@ k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t to
     }
 }
 
+// One slice of a database scan (serving): item = (haystack tile of the slice,
+// query, needle tile), haystack-tile major so that the workgroups running at
+// the same time share the slice's haystack fragments in L2.
+template <class C>
+__global__ void __launch_bounds__(C::kThreads)
+k_search_scan(ScanTable T)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    const uint32_t M = T.m_start[T.njobs];
+    const uint32_t item = blockIdx.x;
+    const uint32_t tnl = item / M, r = item % M;
+    uint32_t k = 0;
+    while (k + 1 < T.njobs && T.m_start[k + 1] <= r) ++k;
+    const uint32_t tm = r - T.m_start[k];
+    const uint32_t tn = (T.tile_begin + tnl) % T.db_tiles;
+    search_tile<C>(T.A[k], tm, tn, lds);
+}
+
 // ------------------------------------------------------- out-of-range images
 
 // lists[0] = #needles with |D| > 127, lists[1] = #haystack images with
@@ -778,6 +796,15 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
     return hipSuccess;
 }
 
+hipError_t launch_search_scan(const ScanTable& T, hipStream_t s)
+{
+    if (T.njobs == 0 || T.tile_count == 0) return hipSuccess;
+    const uint32_t items = T.m_start[T.njobs] * T.tile_count;
+    if (items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_search_scan<Cfg>, dim3(items), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, T);
+    return hipGetLastError();
+}
+
 size_t search_lds_bytes() { return (size_t)Cfg::kLds; }
 
 hipError_t prepare_search_kernels()
@@ -785,7 +812,10 @@ hipError_t prepare_search_kernels()
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<Cfg>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::kLds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_batched<Cfg>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_batched<Cfg>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::kLds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_scan<Cfg>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::kLds);
 }
 uint32_t search_tile_m() { return Cfg::BM; }

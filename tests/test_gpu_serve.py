@@ -1,0 +1,139 @@
+"""GPU tests of the device-resident database, incremental queries and the
+continuous-batching server (rici_db_*, rici_query_*, rici_db_scan, serve.py).
+
+The database holds oracle images (so no expected value comes from the GPU);
+requests describe canonical objects on the GPU and are ranked against it.
+Ranks must equal the oracle's, and be the same for a request served alone and
+in a mix with other requests in flight."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev_u32, host_u32, say
+
+pytestmark = pytest.mark.gpu
+
+R = 0.3
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2007_02306_amd import Context
+    from paper_2007_02306_amd.serve import DescriptorDB
+    rng = np.random.default_rng(55)
+    db_imgs, objects, base = [], [], 0
+    for _ in range(2):
+        mesh, canon, offsets, _ = synth.configs.clutter_scene(rng, 3, 400, 1500)
+        pos = mesh.positions.astype(np.float32)
+        nrm = synth.vertex_normals(pos, mesh.triangles)
+        im, _, _ = oracle.rici_rowrange(pos, mesh.triangles, pos, nrm, R)
+        db_imgs.append(im)
+        for o, m in enumerate(canon):
+            objects.append((m, base + offsets[o]))
+        base += pos.shape[0]
+    db_host = np.concatenate(db_imgs)
+    say(f"  database of {len(db_host)} oracle images, {len(objects)} objects")
+    ctx = Context(0)
+    db = DescriptorDB(ctx, dev_u32(db_host))
+    yield ctx, db, db_host, objects
+    db.close()
+    ctx.close()
+
+
+def _request(rid, objects, rng, q=160):
+    from paper_2007_02306_amd.serve import Request
+    m, off = objects[rid % len(objects)]
+    pos = m.positions.astype(np.float32)
+    nrm = synth.vertex_normals(pos, m.triangles)
+    ids = np.sort(rng.choice(pos.shape[0], min(q, pos.shape[0]), replace=False))
+    return Request(rid, pos, m.triangles, nrm, ids, (off + ids).astype(np.uint32), support_radius=R)
+
+
+def _oracle_ranks(req, db_host):
+    im, fl, _ = oracle.rici_rowrange(req.positions, req.triangles, req.positions[req.needle_ids],
+                                     req.normals[req.needle_ids], R)
+    rk, ds = oracle.rank(im, db_host, req.true_index)
+    return im, fl, rk, ds
+
+
+def test_query_scan_in_slices_matches_oracle(setup):
+    import torch
+    ctx, db, db_host, objects = setup
+    rng = np.random.default_rng(1)
+    req = _request(0, objects, rng)
+    im_o, fl, rk_o, ds_o = _oracle_ranks(req, db_host)
+    assert not fl.any()
+    needles = dev_u32(im_o)
+    ti = dev_u32(req.true_index)
+    rank = torch.empty(len(im_o), dtype=torch.int32, device="cuda")
+    dist = torch.empty(len(im_o), dtype=torch.int64, device="cuda")
+    import ctypes
+    from paper_2007_02306_amd import _ptr, check
+    h = ctypes.c_void_p()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    check(ctx._lib.rici_query_create(ctx._h, db._h, _ptr(needles), len(im_o), _ptr(ti), _ptr(rank), _ptr(dist),
+                                     None, 0, s, ctypes.byref(h)))
+    # scan the tiles in three uneven slices, starting in the middle (wrap-around)
+    T = db.tiles
+    cuts = [T // 2, T // 2 + max(1, T // 5), T // 2 + T]
+    arr = (ctypes.c_void_p * 1)(h.value)
+    check(ctx._lib.rici_db_scan(ctx._h, db._h, arr, 1, cuts[0] % T, cuts[1] - cuts[0], s))
+    check(ctx._lib.rici_db_scan(ctx._h, db._h, arr, 1, cuts[1] % T, cuts[2] - cuts[1], s))
+    ctx.sync()
+    assert np.array_equal(dist.cpu().numpy(), ds_o)
+    assert np.array_equal(host_u32(rank), rk_o)
+    assert rk_o.max() > 0
+    ctx._lib.rici_query_destroy(h)
+
+
+def test_server_alone_and_in_mix(setup):
+    from paper_2007_02306_amd.serve import Server
+    ctx, db, db_host, objects = setup
+    alone = {}
+    for rid in range(4):
+        srv = Server(db, max_active=1, slices=5, keep_images=True)
+        srv.submit(_request(rid, objects, np.random.default_rng(100 + rid)))
+        srv.drain()
+        (req,) = srv.done
+        alone[rid] = req
+        im_o, fl, rk_o, ds_o = _oracle_ranks(req, db_host)
+        assert not ((req.images != im_o) & ~fl).any(), f"request {rid} images"
+        if not fl.any():
+            assert np.array_equal(req.rank, rk_o), f"request {rid} ranks"
+            assert np.array_equal(req.true_distance, ds_o)
+        srv.close()
+    srv = Server(db, max_active=3, slices=5)
+    for rid in range(4):
+        srv.submit(_request(rid, objects, np.random.default_rng(100 + rid)))
+    srv.drain()
+    assert len(srv.done) == 4 and srv.used == 0
+    for req in srv.done:
+        assert np.array_equal(req.rank, alone[req.rid].rank), f"request {req.rid} differs in the mix"
+        assert np.array_equal(req.true_distance, alone[req.rid].true_distance)
+    assert srv.steps < 4 * 5      # requests shared scan steps
+    srv.close()
+
+
+def test_server_admission_by_footprint(setup):
+    from paper_2007_02306_amd.serve import Server
+    ctx, db, db_host, objects = setup
+    reqs = [_request(rid, objects, np.random.default_rng(7 + rid)) for rid in range(3)]
+    probe = Server(db, slices=3)
+    need = max(probe.footprint(r) for r in reqs)
+    probe.close()
+    srv = Server(db, budget_bytes=need + need // 2, max_active=8, slices=3)   # room for one at a time
+    for r in reqs:
+        srv.submit(r)
+    peak = 0
+    while srv.poll():
+        peak = max(peak, len(srv.describing) + len(srv.scanning) + len(srv.finishing))
+        assert srv.used <= srv.budget
+    assert peak == 1 and len(srv.done) == 3
+    with pytest.raises(ValueError):
+        big = Server(db, budget_bytes=1024)
+        big.submit(reqs[0])
+    srv.close()
