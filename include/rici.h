@@ -216,6 +216,23 @@ int rici_timing_enable(rici_handle h, int on);
 int rici_timing_reset(rici_handle h);
 int rici_timing_get(rici_handle h, const char* kernel, double* total_ms, uint64_t* launches);
 
+/*
+ * Tuning knobs of a handle (launch shapes only: results never depend on them).
+ *
+ *   "search_tile_m"  needles per search workgroup tile: 256 (default) or 128.
+ *                    The smaller tile wastes less work on padding when a
+ *                    needle set is small or just above a multiple of 256.
+ *                    Read by rici_distance_rank, rici_distance_matrix,
+ *                    rici_batch_create (fixed into the plan) and
+ *                    rici_query_create (fixed into the query: queries scanned
+ *                    together by rici_db_scan must share it).
+ *
+ * rici_set_tuning returns RICI_ERR_INVALID for an unknown key or a value the
+ * key does not allow; rici_get_tuning writes the current value to *value.
+ */
+int rici_set_tuning(rici_handle h, const char* key, int value);
+int rici_get_tuning(rici_handle h, const char* key, int* value);
+
 #ifdef __cplusplus
 }
 #endif

@@ -151,6 +151,15 @@ class Context:
         """Plan a batched describe-and-rank (see Batch)."""
         return Batch(self, jobs, support_radius)
 
+    # --------------------------------------------------------------- tuning
+    def set_tuning(self, key: str, value: int):
+        check(self._lib.rici_set_tuning(self._h, key.encode(), int(value)))
+
+    def get_tuning(self, key: str) -> int:
+        v = ctypes.c_int()
+        check(self._lib.rici_get_tuning(self._h, key.encode(), ctypes.byref(v)))
+        return v.value
+
     # --------------------------------------------------------------- timing
     def timing(self, on: bool = True):
         check(self._lib.rici_timing_enable(self._h, int(bool(on))))

@@ -21,6 +21,7 @@ EXPORTS = [
     "rici_batch_create", "rici_batch_run", "rici_batch_destroy", "rici_batch_scratch_bytes",
     "rici_db_create", "rici_db_tiles", "rici_db_scratch_bytes", "rici_db_destroy",
     "rici_query_create", "rici_query_footprint", "rici_query_destroy", "rici_db_scan",
+    "rici_set_tuning", "rici_get_tuning",
 ]
 
 
@@ -110,6 +111,10 @@ def load(path: str = LIB_PATH):
         lib.rici_query_destroy.restype = None
         lib.rici_db_scan.argtypes = [P, P, ctypes.POINTER(P), U32, U32, U32, P]
         lib.rici_db_scan.restype = I32
+        lib.rici_set_tuning.argtypes = [P, ctypes.c_char_p, I32]
+        lib.rici_set_tuning.restype = I32
+        lib.rici_get_tuning.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I32)]
+        lib.rici_get_tuning.restype = I32
         _lib = lib
     return _lib
 

@@ -24,6 +24,7 @@ struct rici_ctx {
     void* ws = nullptr;             // scratch
     size_t ws_size = 0;
     bool timing = false;
+    int search_variant = 0;         // search tile: 0 = 256 x 256, 1 = 128 x 256
     std::vector<TimedLaunch> launches;
     std::vector<hipEvent_t> free_events;
 };
@@ -161,8 +162,6 @@ int rici_create(rici_handle* out, int device)
         delete h;
         return hip_fail(e, "hipMemset(error word)");
     }
-    // the search kernel needs more dynamic LDS than the default cap
-    // (set per function in launch_search; nothing to do here)
     *out = h;
     return RICI_OK;
 }
@@ -351,7 +350,8 @@ int rici_distance_rank(rici_handle h, const uint32_t* needles, uint32_t num_need
     });
     if (e != hipSuccess) return hip_fail(e, "true_distance launch");
     e = timed(h, "search", s, [&] {
-        return rici::launch_search(S.np, num_needles, S.hp, num_haystack, S.thr, S.np.sumsq, out_rank, nullptr, s);
+        return rici::launch_search(S.np, num_needles, S.hp, num_haystack, S.thr, S.np.sumsq, out_rank, nullptr,
+                                   h->search_variant, s);
     });
     if (e != hipSuccess) return hip_fail(e, "search launch");
     e = timed(h, "fallback", s, [&] {
@@ -383,7 +383,8 @@ int rici_distance_matrix(rici_handle h, const uint32_t* needles, uint32_t num_ne
     rc = prep_both(h, S, needles, num_needles, haystack, num_haystack, s);
     if (rc) return rc;
     hipError_t e = timed(h, "matrix", s, [&] {
-        return rici::launch_search(S.np, num_needles, S.hp, num_haystack, nullptr, S.np.sumsq, nullptr, out, s);
+        return rici::launch_search(S.np, num_needles, S.hp, num_haystack, nullptr, S.np.sumsq, nullptr, out,
+                                   h->search_variant, s);
     });
     if (e != hipSuccess) return hip_fail(e, "matrix launch");
     e = timed(h, "fallback", s, [&] {
@@ -392,6 +393,28 @@ int rici_distance_matrix(rici_handle h, const uint32_t* needles, uint32_t num_ne
     });
     if (e != hipSuccess) return hip_fail(e, "fallback launch");
     return RICI_OK;
+}
+
+int rici_set_tuning(rici_handle h, const char* key, int value)
+{
+    if (!h || !key) return fail(RICI_ERR_INVALID, "rici_set_tuning: NULL handle or key");
+    if (strcmp(key, "search_tile_m") == 0) {
+        if (value != 256 && value != 128)
+            return fail(RICI_ERR_INVALID, "rici_set_tuning: search_tile_m must be 256 or 128 (got %d)", value);
+        h->search_variant = value == 128 ? 1 : 0;
+        return RICI_OK;
+    }
+    return fail(RICI_ERR_INVALID, "rici_set_tuning: unknown key '%s'", key);
+}
+
+int rici_get_tuning(rici_handle h, const char* key, int* value)
+{
+    if (!h || !key || !value) return fail(RICI_ERR_INVALID, "rici_get_tuning: NULL argument");
+    if (strcmp(key, "search_tile_m") == 0) {
+        *value = (int)rici::search_tile_m(h->search_variant);
+        return RICI_OK;
+    }
+    return fail(RICI_ERR_INVALID, "rici_get_tuning: unknown key '%s'", key);
 }
 
 int rici_timing_enable(rici_handle h, int on)
@@ -445,6 +468,7 @@ struct rici_batch_ctx {
     size_t scratch_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int search_variant = 0;
 };
 
 namespace {
@@ -517,7 +541,8 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
                      [&](uint32_t a, uint32_t b2) { return jobs[a].num_points > jobs[b2].num_points; });
 
     const uint32_t G = rici::gen_group_images();
-    const size_t tm = rici::search_tile_m(), tn = rici::search_tile_n();
+    const int variant = h->search_variant;
+    const size_t tm = rici::search_tile_m(variant), tn = rici::search_tile_n();
 
     // generation scratch (triangle soup); the search scratch reuses the same
     // memory because it is only written after generation has finished
@@ -547,6 +572,7 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
 
     rici_batch_ctx* b = new rici_batch_ctx();
     b->h = h;
+    b->search_variant = variant;
     e = hipMalloc(&b->scratch, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -644,7 +670,7 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
         le = rici::launch_gen_batched(d_gjobs, (uint32_t)gj.size(), tri, chunks, items, support_radius, d_counters,
                                       h->d_err, grid, cs);
         if (le == hipSuccess)
-            le = rici::launch_search_batched(d_sjobs, (uint32_t)sj.size(), T, d_counters + 1, grid, cs);
+            le = rici::launch_search_batched(d_sjobs, (uint32_t)sj.size(), T, d_counters + 1, grid, variant, cs);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cs, &graph);
         b->graph = graph;
@@ -705,6 +731,7 @@ struct rici_query_ctx {
     int64_t* dstar = nullptr;
     uint32_t* rank = nullptr;
     uint32_t nn = 0, tiles_m = 0;
+    int variant = 0;                // search tile shape the needle tiles were counted for
 };
 
 namespace {
@@ -836,7 +863,8 @@ int rici_query_create(rici_handle h, rici_db db, const uint32_t* needles, uint32
     q->dstar = out_true_distance ? out_true_distance : own_dstar;
     q->rank = out_rank;
     q->nn = num_needles;
-    q->tiles_m = (num_needles + rici::search_tile_m() - 1) / rici::search_tile_m();
+    q->variant = h->search_variant;
+    q->tiles_m = (num_needles + rici::search_tile_m(q->variant) - 1) / rici::search_tile_m(q->variant);
     hipStream_t s = (hipStream_t)stream;
     e = timed(h, "delta_needle", s, [&] { return rici::launch_delta_prep(needles, num_needles, 1, q->np, s); });
     if (e == hipSuccess)
@@ -881,9 +909,12 @@ int rici_db_scan(rici_handle h, rici_db db, const rici_query* queries, uint32_t 
         return fail(RICI_ERR_INVALID, "rici_db_scan: tile range beyond the database");
     rici::ScanTable T = {};
     uint32_t m = 0;
+    const int variant = num_queries > 0 && queries[0] ? queries[0]->variant : 0;
     for (uint32_t k = 0; k < num_queries; ++k) {
         const rici_query_ctx* q = queries[k];
         if (!q || q->db != db) return fail(RICI_ERR_INVALID, "rici_db_scan: query %u is not of this database", k);
+        if (q->variant != variant)
+            return fail(RICI_ERR_INVALID, "rici_db_scan: queries %u and 0 were created with different search tiles", k);
         rici::SearchArgs& A = T.A[k];
         A.a_planes = q->np.planes; A.a_groups = q->np.ngroups; A.nn = q->nn;
         A.b_planes = db->hp.planes; A.b_groups = db->hp.ngroups; A.nh = db->n;
@@ -901,7 +932,7 @@ int rici_db_scan(rici_handle h, rici_db db, const rici_query* queries, uint32_t 
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = timed(h, "scan", s, [&] { return rici::launch_search_scan(T, s); });
+    hipError_t e = timed(h, "scan", s, [&] { return rici::launch_search_scan(T, variant, s); });
     if (e != hipSuccess) return hip_fail(e, "rici_db_scan: launch");
     return RICI_OK;
 }

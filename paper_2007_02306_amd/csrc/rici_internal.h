@@ -101,7 +101,8 @@ struct ScanTable {
     uint32_t m_start[kMaxScanJobs + 1];   // prefix of the queries' needle tiles
     uint32_t njobs, tile_begin, tile_count, db_tiles;
 };
-hipError_t launch_search_scan(const ScanTable& T, hipStream_t s);
+// variant: search tile shape (0: 256 x 256, 1: 128 x 256; see search_tile_m)
+hipError_t launch_search_scan(const ScanTable& T, int variant, hipStream_t s);
 
 struct SearchTotals {
     uint64_t needle_groups, hay_slots, hay_images, hay_groups, needles, tiles;
@@ -112,13 +113,13 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
 // every prep, rank and fallback step of `njobs` jobs (stored largest first),
 // with a persistent search kernel of `grid` workgroups
 hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,
-                                 uint32_t grid, hipStream_t s);
+                                 uint32_t grid, int variant, hipStream_t s);
 size_t haystack_slots(uint32_t nh);   // slots allocated for a haystack of nh images
 hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                                 const uint32_t* true_idx, const int64_t* sumsq, const uint32_t* nmax,
                                 int64_t* dstar, int32_t* thr, uint32_t* rank, hipStream_t s);
 hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
-                         const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix,
+                         const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix, int variant,
                          hipStream_t s);
 // `lists` scratch: 2 + nn + nh uint32
 hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
@@ -128,7 +129,7 @@ hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t*
 size_t search_groups(uint32_t n);   // fragment groups allocated for n images
 size_t search_lds_bytes();          // dynamic LDS of the search kernel
 hipError_t prepare_search_kernels(); // raise the search kernels' LDS limit (before any graph capture)
-uint32_t search_tile_m();
-uint32_t search_tile_n();
+uint32_t search_tile_m(int variant);  // needles per search tile
+uint32_t search_tile_n();             // haystack slots per search tile (same for every variant)
 
 }  // namespace rici

@@ -279,13 +279,17 @@ struct SearchCfg {
     static constexpr int kFrags = GA + GB;           // 1 KiB fragments per stage (one image row)
     static constexpr int kStage = kFrags * (int)kFragBytes;
     static constexpr int kLPW = kFrags / kWaves;     // fragment loads per wave per stage
-    static constexpr int kLds = NS * kStage + 4096;  // ring of NS stages (+ slack)
+    static constexpr int kLds = NS * kStage;         // ring of NS stages
     static_assert(kFrags % kWaves == 0, "fragments must split evenly over the waves");
 };
 
 // 256 x 256 (needle x haystack) tile, 8 waves of 128 x 64, a 4-deep ring of
-// one-row stages filled by direct global -> LDS loads
+// one-row stages (4 x 32 KiB) filled by direct global -> LDS loads two stages
+// ahead of their use (measured on MI355X: 3- and 5-deep rings are slower)
 using Cfg = SearchCfg<2, 4, 8, 4, 4>;
+// 128 x 256 tile (8 waves of 64 x 64, 4-deep ring of 24 KiB stages): less
+// padding for needle sets of at most 128 images
+using CfgS = SearchCfg<2, 4, 4, 4, 4>;
 
 // s_waitcnt with only the vector-memory counter constrained (gfx9 encoding)
 template <int V>
@@ -319,7 +323,7 @@ __device__ __forceinline__ void tile_coords(uint32_t logical, uint32_t tiles_m, 
     tn = (logical % in_group) / gsz;
 }
 
-// One 256 x 256 (needle x haystack) tile: every workgroup thread takes part.
+// One BM x BN (needle x haystack) tile: every workgroup thread takes part.
 template <class C>
 __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_t* lds)
 {
@@ -335,8 +339,21 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         flags |= (m > kSmallD && m <= kSlow) ? 1 : 0;
         flags |= (m <= kSlow) ? 2 : 0;
     }
-    const bool hq = __syncthreads_or(flags & 1) != 0;
-    if (!__syncthreads_or(flags & 2)) return;
+    // workgroup OR of the flags through the head of the (still idle) ring: the
+    // ring is all of the LDS, so no other shared array may be allocated
+    {
+        volatile uint32_t* red = reinterpret_cast<volatile uint32_t*>(lds);
+        const uint64_t b1 = __ballot(flags & 1), b2 = __ballot(flags & 2);
+        if (lane == 0) red[wave] = (b1 ? 1u : 0u) | (b2 ? 2u : 0u);
+        __syncthreads();
+        int all = 0;
+#pragma unroll
+        for (int w = 0; w < C::kWaves; ++w) all |= (int)red[w];
+        __syncthreads();   // every wave has read the flags before the ring fills
+        flags = __builtin_amdgcn_readfirstlane(all);   // uniform: scalar control flow below
+    }
+    const bool hq = (flags & 1) != 0;
+    if (!(flags & 2)) return;
     const int nstage = (hq ? 3 : 2) * NB;
 
     // Stage s = phase s / 64, image row s % 64.  Phase -> planes: needle planes
@@ -344,26 +361,29 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // Each wave moves kLPW whole fragments (1 KiB, one instruction each) from
     // global memory straight into the stage's LDS slot; every address but the
     // lane's 16-byte offset is wave-uniform.
-    static_assert(C::GA % C::kLPW == 0, "a wave loads fragments of one operand only");
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int f0 = wv * C::kLPW;                       // first fragment of this wave
-    const bool is_a = f0 < C::GA;
-    const int8_t* wbase = is_a ? A.a_planes + (size_t)(ga0 + f0) * kPlaneGroupBytes
-                               : A.b_planes + (size_t)(gb0 + f0 - C::GA) * kPlaneGroupBytes;
-    const size_t wps = is_a ? (size_t)A.a_groups * kPlaneGroupBytes : (size_t)A.b_groups * kPlaneGroupBytes;
+    const size_t a_ps = (size_t)A.a_groups * kPlaneGroupBytes, b_ps = (size_t)A.b_groups * kPlaneGroupBytes;
+    const int8_t* a_base = A.a_planes + (size_t)ga0 * kPlaneGroupBytes;
+    const int8_t* b_base = A.b_planes + (size_t)gb0 * kPlaneGroupBytes;
     const uint32_t lane_off = (uint32_t)lane * 16;
 
     auto issue = [&](int s) {
         const int p = s / NB, row = s % NB;
         const int pa = hq ? ((p == 1) ? 0 : 1) : p;
         const int pb = hq ? ((p == 0) ? 2 : (p == 1 ? 0 : 1)) : p;
-        const int8_t* src = wbase + (size_t)(is_a ? pa : pb) * wps + (size_t)row * kFragBytes;
-        int8_t* dst = lds + (s % C::kNS) * C::kStage + f0 * (int)kFragBytes;
+        const int8_t* srca = a_base + (size_t)pa * a_ps + (size_t)row * kFragBytes;
+        const int8_t* srcb = b_base + (size_t)pb * b_ps + (size_t)row * kFragBytes;
+        int8_t* dst = lds + (s % C::kNS) * C::kStage;
 #pragma unroll
-        for (int j = 0; j < C::kLPW; ++j)
+        for (int j = 0; j < C::kLPW; ++j) {
+            const int f = f0 + j;                      // wave-uniform: scalar branch
+            const int8_t* src = f < C::GA ? srca + (size_t)f * kPlaneGroupBytes
+                                          : srcb + (size_t)(f - C::GA) * kPlaneGroupBytes;
             __builtin_amdgcn_global_load_lds(
-                (const void __attribute__((address_space(1)))*)(src + (size_t)j * kPlaneGroupBytes + lane_off),
-                (void __attribute__((address_space(3)))*)(dst + j * (int)kFragBytes), 16, 0, 0);
+                (const void __attribute__((address_space(1)))*)(src + lane_off),
+                (void __attribute__((address_space(3)))*)(dst + f * (int)kFragBytes), 16, 0, 0);
+        }
     };
 
     v4i acc[C::kMB][C::kNBK];
@@ -389,7 +409,8 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // reads of one stage overlap the matrix work of the previous one.
     auto step = [&](int s, const Frags& cur, Frags& nxt) {
         if (s + 1 < nstage) {
-            if (s + 2 < nstage) wait_vmcnt<C::kLPW>();
+            // outstanding loads beyond stage s+1: stages s+2 .. s+NS-2
+            if (s + C::kNS - 2 < nstage) wait_vmcnt<(C::kNS - 3) * C::kLPW>();
             else wait_vmcnt<0>();
             stage_barrier();
             if (s + C::kNS - 1 < nstage) issue(s + C::kNS - 1);
@@ -410,10 +431,10 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
                 acc[mb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur.a[mb], cur.b[nb], acc[mb][nb], 0, 0, 0);
     };
 
-    static_assert(C::kNS == 4, "the wait counts below assume a 4-deep ring");
+    static_assert(C::kNS >= 3 && C::kNS < 2 * NB, "ring depth");
 #pragma unroll
     for (int s = 0; s < C::kNS - 1; ++s) issue(s);   // nstage >= 128 > kNS
-    wait_vmcnt<2 * C::kLPW>();
+    wait_vmcnt<(C::kNS - 2) * C::kLPW>();
     stage_barrier();
     Frags fr0, fr1;
     read_frags(0, fr0);
@@ -484,11 +505,15 @@ __global__ void __launch_bounds__(C::kThreads)
 k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t total, uint32_t* __restrict__ counter)
 {
     extern __shared__ __align__(16) int8_t lds[];
-    __shared__ uint32_t s_item;
+    // the ring takes all of the LDS: the item is broadcast through its first
+    // word, which no wave reads or fills between two tiles
+    volatile uint32_t* s_item = reinterpret_cast<volatile uint32_t*>(lds);
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1u);
         __syncthreads();
-        const uint32_t item = s_item;
+        // the item is the same in every lane: keep it (and the job's
+        // arguments loaded through it) in scalar registers
+        const uint32_t item = __builtin_amdgcn_readfirstlane(*s_item);
         __syncthreads();
         if (item >= total) break;
         uint32_t lo = 0, hi = njobs - 1;
@@ -496,10 +521,11 @@ k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t to
             const uint32_t mid = (lo + hi + 1) / 2;
             if (jobs[mid].tile_start <= item) lo = mid; else hi = mid - 1;
         }
-        const SearchArgs& A = jobs[lo].A;
+        const SearchArgs A = jobs[lo].A;
         uint32_t tm, tn;
         tile_coords(item - jobs[lo].tile_start, A.tiles_m, A.tiles_n, tm, tn);
         search_tile<C>(A, tm, tn, lds);
+        __syncthreads();   // every wave is done with the ring before its first word is reused
     }
 }
 
@@ -726,29 +752,33 @@ hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
-                         const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix, hipStream_t s)
+template <class C>
+static hipError_t launch_search_t(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
+                                  const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix,
+                                  hipStream_t s)
 {
-    if (nn == 0 || nh == 0) return hipSuccess;
     SearchArgs A;
     A.a_planes = np.planes; A.a_groups = np.ngroups; A.nn = nn;
     A.b_planes = hp.planes; A.b_groups = hp.ngroups; A.nh = nh;
     A.nmax = np.maxabs; A.hmax = hp.maxabs; A.hperm = hp.perm;
     A.thr = thr; A.sumsq = sumsq; A.rank = rank; A.matrix = matrix;
-    A.tiles_m = (nn + Cfg::BM - 1) / Cfg::BM;
-    A.tiles_n = hp.ngroups * kGroup / Cfg::BN;   // every haystack slot, padding included
+    A.tiles_m = (nn + C::BM - 1) / C::BM;
+    A.tiles_n = hp.ngroups * kGroup / C::BN;   // every haystack slot, padding included
     const uint32_t total = A.tiles_m * A.tiles_n;
     A.per_xcd = (total + 7) / 8;
-    const size_t lds = (size_t)Cfg::kLds;
-    static bool lds_raised = false;   // per process; the attribute is per function
-    if (!lds_raised) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<Cfg>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        lds_raised = true;
-    }
-    hipLaunchKernelGGL(k_search<Cfg>, dim3(8 * A.per_xcd), dim3(Cfg::kThreads), lds, s, A);
+    hipLaunchKernelGGL(k_search<C>, dim3(8 * A.per_xcd), dim3(C::kThreads), (size_t)C::kLds, s, A);
     return hipGetLastError();
+}
+
+hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
+                         const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix, int variant,
+                         hipStream_t s)
+{
+    if (nn == 0 || nh == 0) return hipSuccess;
+    hipError_t e = prepare_search_kernels();
+    if (e != hipSuccess) return e;
+    return variant == 1 ? launch_search_t<CfgS>(np, nn, hp, nh, thr, sumsq, rank, matrix, s)
+                        : launch_search_t<Cfg>(np, nn, hp, nh, thr, sumsq, rank, matrix, s);
 }
 
 hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
@@ -765,7 +795,7 @@ hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t*
 }
 
 hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,
-                                 uint32_t grid, hipStream_t s)
+                                 uint32_t grid, int variant, hipStream_t s)
 {
     if (njobs == 0) return hipSuccess;
 #define RICI_LAUNCH(...)                                   \
@@ -787,7 +817,10 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
         RICI_LAUNCH(k_true_distance_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
                     T.needles);
     RICI_LAUNCH(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
-    if (T.tiles)
+    if (T.tiles && variant == 1)
+        RICI_LAUNCH(k_search_batched<CfgS>, dim3(grid), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, jobs, njobs,
+                    (uint32_t)T.tiles, counter);
+    else if (T.tiles)
         RICI_LAUNCH(k_search_batched<Cfg>, dim3(grid), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, jobs, njobs,
                     (uint32_t)T.tiles, counter);
     RICI_LAUNCH(k_slow_lists_batched, dim3(njobs), dim3(1024), 0, s, jobs);
@@ -796,29 +829,42 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
     return hipSuccess;
 }
 
-hipError_t launch_search_scan(const ScanTable& T, hipStream_t s)
+hipError_t launch_search_scan(const ScanTable& T, int variant, hipStream_t s)
 {
     if (T.njobs == 0 || T.tile_count == 0) return hipSuccess;
     const uint32_t items = T.m_start[T.njobs] * T.tile_count;
     if (items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_search_scan<Cfg>, dim3(items), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, T);
+    if (variant == 1)
+        hipLaunchKernelGGL(k_search_scan<CfgS>, dim3(items), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, T);
+    else
+        hipLaunchKernelGGL(k_search_scan<Cfg>, dim3(items), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, T);
     return hipGetLastError();
 }
 
-size_t search_lds_bytes() { return (size_t)Cfg::kLds; }
+template <class C>
+static hipError_t raise_lds()
+{
+    const int lds = (int)C::kLds;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<C>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_batched<C>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_scan<C>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
 
 hipError_t prepare_search_kernels()
 {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<Cfg>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::kLds);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_batched<Cfg>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::kLds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_scan<Cfg>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::kLds);
+    static hipError_t once = [] {
+        hipError_t e = raise_lds<Cfg>();
+        return e != hipSuccess ? e : raise_lds<CfgS>();
+    }();
+    return once;
 }
-uint32_t search_tile_m() { return Cfg::BM; }
+
+uint32_t search_tile_m(int variant) { return variant == 1 ? CfgS::BM : Cfg::BM; }
 uint32_t search_tile_n() { return Cfg::BN; }
 
 }  // namespace rici

@@ -82,6 +82,29 @@ def test_batch_matches_plain_path_and_oracle(ctx):
     b.close()
 
 
+def test_batch_small_search_tile(ctx):
+    """A plan recorded under the 128-needle search tile gives the plain path's
+    exact results."""
+    from paper_2007_02306_amd import Context
+    meshes = _meshes(8, 4, 100, 3000)
+    c128 = Context(0)
+    c128.set_tuning("search_tile_m", 128)
+    jobs = [dict(positions=dev_f32(p), triangles=dev_u32(t), op_positions=dev_f32(p), op_normals=dev_f32(n),
+                 true_index=dev_u32(ti)) for p, t, n, ti in meshes]
+    b = c128.batch(jobs, 0.3)
+    b.run()
+    c128.sync()
+    for k, j in enumerate(jobs):
+        img = ctx.generate(j["positions"], j["triangles"], j["op_positions"], j["op_normals"], 0.3)
+        rk, ds = ctx.distance_rank(img, img, j["true_index"])
+        ctx.sync()
+        assert np.array_equal(host_u32(b.images[k]), host_u32(img))
+        assert np.array_equal(host_u32(b.rank[k]), host_u32(rk))
+        assert np.array_equal(b.true_distance[k].cpu().numpy(), ds.cpu().numpy())
+    b.close()
+    c128.close()
+
+
 def test_batch_empty_and_bad_jobs(ctx):
     import torch
     from paper_2007_02306_amd import RiciError

@@ -153,3 +153,39 @@ def test_bad_true_index_and_empty(ctx):
     with pytest.raises(RiciError):
         ctx.distance_rank(dev_u32(h[:2]), torch.zeros((0, 64, 64), dtype=torch.int32, device="cuda"),
                           dev_u32(np.zeros(2, np.uint32)))
+
+
+@pytest.fixture()
+def ctx128():
+    from paper_2007_02306_amd import Context
+    c = Context(0)
+    c.set_tuning("search_tile_m", 128)
+    assert c.get_tuning("search_tile_m") == 128
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("nn,nh", [(1, 5), (127, 300), (129, 257), (385, 700)])
+def test_small_tile_matches_oracle(ctx128, nn, nh):
+    """The 128-needle search tile: same exact matrix and ranks (ragged needle
+    counts on both sides of a tile, every delta range)."""
+    rng = np.random.default_rng(nn + 31 * nh)
+    h = synth.step_images(rng, nh, delta_scale=3)
+    h[nh // 2] = synth.step_images(rng, 1, max_delta=90, density=0.05)[0]
+    h[nh - 1] = synth.step_images(rng, 1, max_delta=300, density=0.02)[0]
+    t = rng.integers(0, nh, nn).astype(np.uint32)
+    t[0] = nh // 2
+    n = synth.perturb(rng, h[t], frac=0.02)
+    assert np.array_equal(gpu_matrix(ctx128, n, h), oracle.distance_matrix(n, h))
+    rk, ds = gpu_rank(ctx128, n, h, t)
+    ork, ods = oracle.rank(n, h, t)
+    assert np.array_equal(ds, ods) and np.array_equal(rk, ork)
+
+
+def test_tuning_rejects_bad_values(ctx):
+    from paper_2007_02306_amd import RiciError
+    with pytest.raises(RiciError):
+        ctx.set_tuning("search_tile_m", 64)
+    with pytest.raises(RiciError):
+        ctx.set_tuning("no_such_knob", 1)
+    assert ctx.get_tuning("search_tile_m") == 256

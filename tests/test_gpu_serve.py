@@ -137,3 +137,40 @@ def test_server_admission_by_footprint(setup):
         big = Server(db, budget_bytes=1024)
         big.submit(reqs[0])
     srv.close()
+
+
+def test_scan_with_small_tile_and_mixed_tiles_rejected(setup):
+    """A query created under the 128-needle search tile scans to the oracle's
+    ranks; queries of different tile shapes are not scanned together."""
+    import ctypes
+    import torch
+    from paper_2007_02306_amd import Context, RiciError, _ptr, check
+    ctx, db, db_host, objects = setup
+    rng = np.random.default_rng(2)
+    req = _request(1, objects, rng, q=150)
+    im_o, fl, rk_o, ds_o = _oracle_ranks(req, db_host)
+    c128 = Context(0)
+    c128.set_tuning("search_tile_m", 128)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    needles, ti = dev_u32(im_o), dev_u32(req.true_index)
+    outs, hs = [], []
+    for c in (c128, ctx):
+        rank = torch.empty(len(im_o), dtype=torch.int32, device="cuda")
+        dist = torch.empty(len(im_o), dtype=torch.int64, device="cuda")
+        h = ctypes.c_void_p()
+        check(c._lib.rici_query_create(c._h, db._h, _ptr(needles), len(im_o), _ptr(ti), _ptr(rank), _ptr(dist),
+                                       None, 0, s, ctypes.byref(h)))
+        outs.append((rank, dist))
+        hs.append(h)
+    both = (ctypes.c_void_p * 2)(hs[0].value, hs[1].value)
+    with pytest.raises(RiciError):
+        check(ctx._lib.rici_db_scan(ctx._h, db._h, both, 2, 0, db.tiles, s))
+    one = (ctypes.c_void_p * 1)(hs[0].value)
+    check(ctx._lib.rici_db_scan(ctx._h, db._h, one, 1, 0, db.tiles, s))
+    ctx.sync()
+    rank, dist = outs[0]
+    assert np.array_equal(dist.cpu().numpy(), ds_o)
+    assert np.array_equal(host_u32(rank), rk_o)
+    for h in hs:
+        ctx._lib.rici_query_destroy(h)
+    c128.close()
