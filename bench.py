@@ -45,7 +45,51 @@ def parse():
                     help="meshes in the batched-vs-plain comparison (0 to skip)")
     ap.add_argument("--db-images", type=int, default=1_000_000, help="serving: database size")
     ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (scales the HBM byte counters)")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = {
+    "k_gen": ["paper_2007_02306_amd/csrc/rici_gen.hip", "paper_2007_02306_amd/csrc/rici_internal.h"],
+    "k_search": ["paper_2007_02306_amd/csrc/rici_search.hip", "paper_2007_02306_amd/csrc/rici_internal.h"],
+}
+
+
+def source_digest(kernel: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, launches_per_record: int = 1):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_union12_hbm_traffic.json: FETCH_SIZE and WRITE_SIZE per
+    dispatch, each scaled by what the counter reads for a plain copy of known
+    size), or None when the kernel's sources changed after the counters were
+    taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_union12_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != source_digest(kernel):
+        return None
+    return rec["hbm_bytes_per_dispatch"] * launches_per_record
+
+
+def copy_calibration():
+    import torch
+    n = 256 * 1024 * 1024                       # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4, "copies": 3}}), flush=True)
 
 
 def cpu_baseline(scene, n_img, n_needles):
@@ -224,6 +268,9 @@ def main():
     from paper_2007_02306_amd import Context
 
     assert torch.cuda.is_available(), "bench.py needs the MI355X"
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.workload == "serving":
         serving(args)
         return
@@ -272,7 +319,8 @@ def main():
     search_ops = float(N) * N * OPS_PER_PAIR
     search_achieved = search_ops / (search_ms * 1e-3) / 1e12
     roof_search = {"bound": "mfma", "achieved": search_achieved, "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
-                   "frac": search_achieved / PEAK_INT8_TOPS, "traffic": None, "kernel": "k_search",
+                   "frac": search_achieved / PEAK_INT8_TOPS, "traffic": measured_traffic("k_search"),
+                   "kernel": "k_search",
                    "ops_per_launch": search_ops}
 
     cpu = None
@@ -291,7 +339,8 @@ def main():
         gen_ops = per_img * N
         gen_achieved = gen_ops / (gen_ms * 1e-3) / 1e12
         roof_gen = {"bound": "alu", "achieved": gen_achieved, "peak": PEAK_ALU_TOPS, "unit": "TFLOP/s",
-                    "frac": gen_achieved / PEAK_ALU_TOPS, "kernel": "k_gen", "ops_per_launch": gen_ops,
+                    "frac": gen_achieved / PEAK_ALU_TOPS, "traffic": measured_traffic("k_gen"),
+                    "kernel": "k_gen", "ops_per_launch": gen_ops,
                     "ops_basis": "oracle work counters on the CPU-baseline sample"}
 
     batched = batched_vs_plain(ctx, args.batch_meshes) if args.batch_meshes > 0 else None
