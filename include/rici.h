@@ -219,6 +219,9 @@ int rici_timing_get(rici_handle h, const char* kernel, double* total_ms, uint64_
 /*
  * Tuning knobs of a handle (launch shapes only: results never depend on them).
  *
+ *   "gen_images_per_group"  images sharing one generation workgroup (and its
+ *                    triangle stream): 2 (default) or 4.  Read by
+ *                    rici_generate and rici_batch_create (fixed into the plan).
  *   "search_tile_m"  needles per search workgroup tile: 256 (default) or 128.
  *                    The smaller tile wastes less work on padding when a
  *                    needle set is small or just above a multiple of 256.

@@ -25,6 +25,7 @@ struct rici_ctx {
     size_t ws_size = 0;
     bool timing = false;
     int search_variant = 0;         // search tile: 0 = 256 x 256, 1 = 128 x 256
+    int gen_group = 2;              // images per generation workgroup: 2 or 4
     std::vector<TimedLaunch> launches;
     std::vector<hipEvent_t> free_events;
 };
@@ -244,7 +245,7 @@ int rici_generate(rici_handle h, const float* positions, uint32_t num_vertices, 
     if (e != hipSuccess) return hip_fail(e, "gen_prep launch");
     e = timed(h, "gen", s, [&] {
         return rici::launch_gen(cull, clusters, verts, num_triangles, op_positions, op_normals, num_points,
-                                support_radius, out_images, h->d_err, s);
+                                support_radius, out_images, h->d_err, h->gen_group, s);
     });
     if (e != hipSuccess) return hip_fail(e, "gen launch");
     return RICI_OK;
@@ -398,6 +399,12 @@ int rici_distance_matrix(rici_handle h, const uint32_t* needles, uint32_t num_ne
 int rici_set_tuning(rici_handle h, const char* key, int value)
 {
     if (!h || !key) return fail(RICI_ERR_INVALID, "rici_set_tuning: NULL handle or key");
+    if (strcmp(key, "gen_images_per_group") == 0) {
+        if (value != 4 && value != 2)
+            return fail(RICI_ERR_INVALID, "rici_set_tuning: gen_images_per_group must be 4 or 2 (got %d)", value);
+        h->gen_group = value;
+        return RICI_OK;
+    }
     if (strcmp(key, "search_tile_m") == 0) {
         if (value != 256 && value != 128)
             return fail(RICI_ERR_INVALID, "rici_set_tuning: search_tile_m must be 256 or 128 (got %d)", value);
@@ -410,6 +417,10 @@ int rici_set_tuning(rici_handle h, const char* key, int value)
 int rici_get_tuning(rici_handle h, const char* key, int* value)
 {
     if (!h || !key || !value) return fail(RICI_ERR_INVALID, "rici_get_tuning: NULL argument");
+    if (strcmp(key, "gen_images_per_group") == 0) {
+        *value = h->gen_group;
+        return RICI_OK;
+    }
     if (strcmp(key, "search_tile_m") == 0) {
         *value = (int)rici::search_tile_m(h->search_variant);
         return RICI_OK;
@@ -525,7 +536,11 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
     hipDeviceProp_t prop;
     hipError_t e = hipGetDeviceProperties(&prop, h->device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-    const uint32_t grid = (uint32_t)prop.multiProcessorCount;   // one resident workgroup per CU
+    const int gen_group = h->gen_group;
+    uint32_t gen_grid = 0;   // as many persistent generation workgroups as fit at once
+    e = rici::gen_batched_grid(gen_group, prop.multiProcessorCount, &gen_grid);
+    if (e != hipSuccess) return hip_fail(e, "rici_batch_create: occupancy");
+    const uint32_t grid = (uint32_t)prop.multiProcessorCount;   // search: one resident workgroup per CU
 
     // generation jobs, largest triangle count first (longest items start first)
     std::vector<uint32_t> gorder;
@@ -540,7 +555,7 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
     std::stable_sort(sorder.begin(), sorder.end(),
                      [&](uint32_t a, uint32_t b2) { return jobs[a].num_points > jobs[b2].num_points; });
 
-    const uint32_t G = rici::gen_group_images();
+    const uint32_t G = rici::gen_group_images(gen_group);
     const int variant = h->search_variant;
     const size_t tm = rici::search_tile_m(variant), tn = rici::search_tile_n();
 
@@ -668,7 +683,7 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
     hipError_t le = hipSuccess;
     if (e == hipSuccess) {
         le = rici::launch_gen_batched(d_gjobs, (uint32_t)gj.size(), tri, chunks, items, support_radius, d_counters,
-                                      h->d_err, grid, cs);
+                                      h->d_err, gen_grid, gen_group, cs);
         if (le == hipSuccess)
             le = rici::launch_search_batched(d_sjobs, (uint32_t)sj.size(), T, d_counters + 1, grid, variant, cs);
         hipGraph_t graph = nullptr;

@@ -6,17 +6,23 @@
 // counted into the image (Sec. 3.1.2).
 //
 // Mapping onto CDNA4
-//   * A workgroup owns G images.  Their FP64 frames (Eq. 1 coefficients) and
-//     per-row difference arrays live in LDS (G x 16 KiB of uint32).
+//   * A workgroup of 8 waves owns G images (G = 4 or 2, a tuning knob).  Their
+//     FP64 frames (Eq. 1 coefficients) and per-row difference arrays live in
+//     LDS (G x 16.6 KiB of uint32); with the per-wave rings and slice maps this
+//     is small enough for 2 (G = 4) or 3 (G = 2) workgroups per CU.
 //   * Lanes stream triangles (one per lane, coalesced float4 bounding spheres)
 //     and test each against the G images with a conservative FP32 cull: the
 //     bounding sphere must reach the support slab |beta| <= R/2 and the support
-//     cylinder alpha <= R, with margins far above FP32 rounding.  The cull only
-//     discards triangles that provably touch no bin, so counts are unchanged.
+//     cylinder alpha <= R, with margins far above FP32 rounding.  Whole runs of
+//     64 triangles are tested first through their common bounding sphere.  The
+//     cull only discards triangles that provably touch no bin, so counts are
+//     unchanged.
 //   * Survivors (image, triangle) are appended to a per-wave LDS ring with a
 //     ballot prefix; once 64 are queued every lane takes one and does the exact
-//     work in FP64: projection (Eq. 2-5), rows in the triangle's beta extent,
-//     the slice E0E1, single range (min|E|, max|E|), double range (|C|, min|E|),
+//     work in FP64: projection (Eq. 2-5) and edge slopes, kept in registers.
+//     The pairs' row slices are then spread evenly over the lanes, each lane
+//     reading its slice's pair record from the owning lane (ds_bpermute): the
+//     slice E0E1, single range (min|E|, max|E|), double range (|C|, min|E|),
 //     all as comparisons of squared radii (no sqrt in any decision).
 //   * Each slice adds +1 / -1 (single) and +2 / -2 (double) at its first and
 //     end columns of a row's difference array (3 LDS atomics per slice, O(1)
@@ -27,7 +33,6 @@
 namespace rici {
 namespace {
 
-constexpr int kG = 4;          // images per workgroup
 constexpr int kWaves = 8;      // wavefronts per workgroup
 constexpr int kRing = 128;     // per-wave survivor ring (entries)
 
@@ -135,16 +140,6 @@ struct Frame {
     double pad;
 };
 
-// One surviving (image, triangle) pair in bin units, vertices sorted by
-// height (a lowest, c highest), with the slopes d(x, y)/dz of its edges.
-struct __align__(16) Rec {
-    double xa, ya, za, zb;
-    double xb, yb;
-    double sxl, syl;          // along a -> c (crosses every row of the range)
-    double sx1, sy1;          // along a -> b (rows with beta <= z_b)
-    double sx2, sy2;          // along b -> c (rows with beta >  z_b)
-};
-
 // First column c in [0, 64] whose bin radius c + 1/2 exceeds sqrt(s), s >= 0,
 // decided by an exact FP64 comparison.  The FP32 square root is biased low so
 // the guess is the answer or one below it.
@@ -207,26 +202,54 @@ __device__ __forceinline__ void wave_sync_lds()
 constexpr int kDiffStride = 65;   // column 64 of each row is a sink for "past the image"
 constexpr int kMapCap = 1024;     // slices mapped per round
 
+// LDS of a workgroup owning G images: the difference arrays, the per-wave
+// survivor rings and slice maps, and the frames.  The per-pair records of the
+// exact stage stay in registers (see process_batch), which keeps this small
+// enough for two (G = 4) or three (G = 2) resident workgroups per CU.
+template <int G>
 struct GenLds {
-    uint32_t diff[kG][NB * kDiffStride];
+    uint32_t diff[G][NB * kDiffStride];
     uint32_t ring[kWaves][kRing];
-    Rec rec[kWaves][64];
-    uint32_t meta[kWaves][64];    // image | first row << 2
-    uint32_t pre[kWaves][64];     // exclusive prefix of row counts
     uint8_t map[kWaves][kMapCap]; // slice -> survivor lane
-    Frame frames[kG];
-    float cp[kG][8];              // FP32 cull parameters
+    Frame frames[G];
+    float cp[G][8];               // FP32 cull parameters
 };
 
+// v from lane src_x4 / 4 (every lane of the wave must be active)
+__device__ __forceinline__ double lane_fetch(double v, int src_x4)
+{
+    const int lo = __builtin_amdgcn_ds_bpermute(src_x4, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src_x4, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ uint32_t lane_fetch(uint32_t v, int src_x4)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src_x4, (int)v);
+}
+
 // Exact work for up to 64 queued (image, triangle) pairs of one wavefront.
-__device__ void process_batch(GenLds& L, int wave, int lane, uint32_t head, uint32_t cnt,
+//
+// Stage A: lane i projects pair i (Eq. 2-4 in FP64, bin units), sorts its
+// vertices by height and keeps, in registers, the edge slopes and the first
+// row of its beta extent.  Stage B: the slices of all pairs (one per row in
+// the extent) are spread evenly over the lanes; a lane reads the record of
+// its slice's pair from the owning lane with cross-lane permutes and adds the
+// slice's single / double ranges to the row's difference array.
+template <int G>
+__device__ void process_batch(GenLds<G>& L, int wave, int lane, uint32_t head, uint32_t cnt,
                               const float4* __restrict__ verts)
 {
     wave_sync_lds();
-    uint32_t nrows = 0;
+    uint32_t nrows = 0, key = 0;
+    double xa = 0.0, ya = 0.0, za = 0.0, zb = 0.0, xb = 0.0, yb = 0.0;
+    double sxl = 0.0, syl = 0.0, sx1 = 0.0, sy1 = 0.0, sx2 = 0.0, sy2 = 0.0;
+    int r0 = 0;
+    uint32_t g = 0;
     if ((uint32_t)lane < cnt) {
         const uint32_t e = L.ring[wave][(head + lane) & (kRing - 1)];
-        const uint32_t g = e & (kG - 1), t = e / kG;
+        g = e & (G - 1);
+        const uint32_t t = e / G;
         const Frame& F = L.frames[g];
         const float4 v0 = verts[3 * (size_t)t], v1 = verts[3 * (size_t)t + 1], v2 = verts[3 * (size_t)t + 2];
         double X[3], Y[3], Z[3];
@@ -241,50 +264,58 @@ __device__ void process_batch(GenLds& L, int wave, int lane, uint32_t head, uint
             X[k] = F.nbz_d * qx - F.nbx_d * pz;               // Eq. 4, bin units
             Z[k] = F.nbx_d * qx + F.nbz_d * pz;
         }
-        double xa = X[0], ya = Y[0], za = Z[0], xb = X[1], yb = Y[1], zb = Z[1], xc = X[2], yc = Y[2], zc = Z[2];
+        double xc = X[2], yc = Y[2], zc = Z[2];
+        xa = X[0]; ya = Y[0]; za = Z[0]; xb = X[1]; yb = Y[1]; zb = Z[1];
         csort(xa, ya, za, xb, yb, zb);
         csort(xb, yb, zb, xc, yc, zc);
         csort(xa, ya, za, xb, yb, zb);
         // rows r with r - 31.5 in (z_a, z_c]: a vertex is above iff z >= beta
         const double f0 = floor(fmin(fmax(za + 31.5, -2.0), 70.0)) + 1.0;
         const double f1 = floor(fmin(fmax(zc + 31.5, -2.0), 70.0));
-        const int r0 = max((int)f0, 0), r1 = min((int)f1, 63);
+        r0 = max((int)f0, 0);
+        const int r1 = min((int)f1, 63);
         const double il = recip(zc - za);
         const double i1 = recip(zb - za);
         const double i2 = recip(zc - zb);
         nrows = (r1 >= r0 && zc > za) ? (uint32_t)(r1 - r0 + 1) : 0u;
-        Rec& R = L.rec[wave][lane];
-        R.xa = xa; R.ya = ya; R.za = za; R.zb = zb; R.xb = xb; R.yb = yb;
-        R.sxl = (xc - xa) * il; R.syl = (yc - ya) * il;
-        R.sx1 = (xb - xa) * i1; R.sy1 = (yb - ya) * i1;
-        R.sx2 = (xc - xb) * i2; R.sy2 = (yc - yb) * i2;
-        L.meta[wave][lane] = g | ((uint32_t)max(r0, 0) << 2);
+        sxl = (xc - xa) * il; syl = (yc - ya) * il;
+        sx1 = (xb - xa) * i1; sy1 = (yb - ya) * i1;
+        sx2 = (xc - xb) * i2; sy2 = (yc - yb) * i2;
     }
     const uint32_t incl = wave_inclusive_scan(nrows, lane);
     const uint32_t pre = incl - nrows;
     const uint32_t total = __shfl(incl, 63, 64);
-    L.pre[wave][lane] = pre;
+    // row of slice k of this pair = r0 + (k - pre); stored with its image
+    key = ((uint32_t)(r0 - (int)pre + 8192) << 2) | g;
 
     for (uint32_t base = 0; base < total; base += kMapCap) {
         const uint32_t lo = max(pre, base), hi = min(pre + nrows, base + kMapCap);
         for (uint32_t k = lo; k < hi; ++k) L.map[wave][k - base] = (uint8_t)lane;
         wave_sync_lds();
         const uint32_t n_round = min(total - base, (uint32_t)kMapCap);
-        for (uint32_t k = lane; k < n_round; k += 64) {
-            const uint32_t sidx = L.map[wave][k];
-            const Rec R = L.rec[wave][sidx];
-            const uint32_t m = L.meta[wave][sidx];
-            const int r = (int)(m >> 2) + (int)(base + k - L.pre[wave][sidx]);
-            const uint32_t g = m & (kG - 1);
+        for (uint32_t k0 = 0; k0 < n_round; k0 += 64) {   // uniform trip count: permutes see every lane
+            const uint32_t k = k0 + (uint32_t)lane;
+            const bool valid = k < n_round;
+            const int src = valid ? (int)L.map[wave][k] * 4 : 0;
+            const uint32_t m = lane_fetch(key, src);
+            const double Ra = lane_fetch(za, src), Rb = lane_fetch(zb, src);
+            const double Rxa = lane_fetch(xa, src), Rya = lane_fetch(ya, src);
+            const double Rsxl = lane_fetch(sxl, src), Rsyl = lane_fetch(syl, src);
+            const double Rxb = lane_fetch(xb, src), Ryb = lane_fetch(yb, src);
+            const double Rsx1 = lane_fetch(sx1, src), Rsy1 = lane_fetch(sy1, src);
+            const double Rsx2 = lane_fetch(sx2, src), Rsy2 = lane_fetch(sy2, src);
+            if (!valid) continue;
+            const int r = (int)(m >> 2) - 8192 + (int)(base + k);
+            const uint32_t gi = m & (G - 1);
             const double beta = (double)r - 31.5;
             // Sec. 3.1.2 step 1: crossings on the long edge and on the short
             // edge whose z-range holds beta
-            const double hl = beta - R.za;
-            const double e0x = R.xa + hl * R.sxl, e0y = R.ya + hl * R.syl;
-            const bool low = beta <= R.zb;
-            const double h1 = low ? hl : beta - R.zb;
-            const double e1x = (low ? R.xa : R.xb) + h1 * (low ? R.sx1 : R.sx2);
-            const double e1y = (low ? R.ya : R.yb) + h1 * (low ? R.sy1 : R.sy2);
+            const double hl = beta - Ra;
+            const double e0x = Rxa + hl * Rsxl, e0y = Rya + hl * Rsyl;
+            const bool low = beta <= Rb;
+            const double h1 = low ? hl : beta - Rb;
+            const double e1x = (low ? Rxa : Rxb) + h1 * (low ? Rsx1 : Rsx2);
+            const double e1y = (low ? Rya : Ryb) + h1 * (low ? Rsy1 : Rsy2);
             // steps 3-4: squared distances from the axis; single range (lo, hi)
             const double d0 = e0x * e0x + e0y * e0y, d1 = e1x * e1x + e1y * e1y;
             const double lo2 = fmin(d0, d1), hi2 = fmax(d0, d1);
@@ -299,7 +330,7 @@ __device__ void process_batch(GenLds& L, int wave, int lane, uint32_t head, uint
             int c_c = between ? min(first_col_ratio(cr * cr, dd), c_lo) : c_lo;
             if (!ok) { c_lo = c_hi = c_c = 64; }
             // +2 on [c_c, c_lo), +1 on [c_lo, c_hi) as a difference row
-            uint32_t* row = L.diff[g] + r * kDiffStride;
+            uint32_t* row = L.diff[gi] + r * kDiffStride;
             atomicAdd(row + c_c, 2u);
             atomicAdd(row + c_lo, (uint32_t)-1);
             atomicAdd(row + c_hi, (uint32_t)-1);
@@ -308,8 +339,9 @@ __device__ void process_batch(GenLds& L, int wave, int lane, uint32_t head, uint
     }
 }
 
-// kG images (img0 .. img0 + kG - 1) of one job, by the whole workgroup.
-__device__ void gen_images(GenLds& L, const GenJob& J, uint32_t img0, float Rf, uint32_t* __restrict__ err)
+// G images (img0 .. img0 + G - 1) of one job, by the whole workgroup.
+template <int G>
+__device__ void gen_images(GenLds<G>& L, const GenJob& J, uint32_t img0, float Rf, uint32_t* __restrict__ err)
 {
     const float4* __restrict__ cull = J.cull;
     const float4* __restrict__ clusters = J.clusters;
@@ -321,8 +353,8 @@ __device__ void gen_images(GenLds& L, const GenJob& J, uint32_t img0, float Rf, 
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    for (int i = tid; i < kG * NB * kDiffStride; i += kWaves * 64) (&L.diff[0][0])[i] = 0u;
-    if (tid < kG) {
+    for (int i = tid; i < G * NB * kDiffStride; i += kWaves * 64) (&L.diff[0][0])[i] = 0u;
+    if (tid < G) {
         Frame f = {};
         float* c = L.cp[tid];
         const uint32_t img = img0 + tid;
@@ -368,9 +400,9 @@ __device__ void gen_images(GenLds& L, const GenJob& J, uint32_t img0, float Rf, 
     __syncthreads();
 
     // cull parameters of the G images, wave-uniform (scalar registers)
-    float P[kG][8];
+    float P[G][8];
 #pragma unroll
-    for (int g = 0; g < kG; ++g)
+    for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             P[g][k] = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(L.cp[g][k])));
@@ -395,37 +427,37 @@ __device__ void gen_images(GenLds& L, const GenJob& J, uint32_t img0, float Rf, 
         const float4 cs = clusters[base / 64];
         uint32_t cmask = 0;
 #pragma unroll
-        for (int g = 0; g < kG; ++g) cmask |= (reaches(cs, g) ? 1u : 0u) << g;
+        for (int g = 0; g < G; ++g) cmask |= (reaches(cs, g) ? 1u : 0u) << g;
         cmask = __builtin_amdgcn_readfirstlane(cmask);
         if (cmask == 0) continue;
         const uint32_t t = base + lane;
         const float4 s = t < nt ? cull[t] : make_float4(0.f, 0.f, 0.f, -INFINITY);
         uint32_t mask = 0;
 #pragma unroll
-        for (int g = 0; g < kG; ++g)
+        for (int g = 0; g < G; ++g)
             if (cmask & (1u << g)) mask |= (reaches(s, g) ? 1u : 0u) << g;
         // append the pairs to the ring, one image bit per round
         while (__ballot(mask != 0)) {
             const bool has = mask != 0;
-            const uint32_t g = (uint32_t)__builtin_ctz(mask | 0x10u);
+            const uint32_t g = (uint32_t)__builtin_ctz(mask | (1u << G));
             mask &= mask - 1;
             const uint64_t bal = __ballot(has);
             if (has) {
                 const uint32_t slot = tail + (uint32_t)__popcll(bal & lt_mask);
-                L.ring[wave][slot & (kRing - 1)] = t * kG + g;
+                L.ring[wave][slot & (kRing - 1)] = t * G + g;
             }
             tail += (uint32_t)__popcll(bal);
             if (tail - head >= 64) {
-                process_batch(L, wave, lane, head, 64, verts);
+                process_batch<G>(L, wave, lane, head, 64, verts);
                 head += 64;
             }
         }
     }
-    if (tail > head) process_batch(L, wave, lane, head, tail - head, verts);
+    if (tail > head) process_batch<G>(L, wave, lane, head, tail - head, verts);
     __syncthreads();
 
     // row prefix sums of the difference arrays -> counts; one row per wave step
-    for (int row = wave; row < kG * NB; row += kWaves) {
+    for (int row = wave; row < G * NB; row += kWaves) {
         const int g = row / NB, r = row % NB;
         const uint32_t img = img0 + g;
         if (img >= n) continue;
@@ -435,26 +467,31 @@ __device__ void gen_images(GenLds& L, const GenJob& J, uint32_t img0, float Rf, 
     __syncthreads();   // the LDS is reused by the workgroup's next group
 }
 
-__global__ void __launch_bounds__(kWaves * 64)
+// waves per SIMD to leave room for: 3 workgroups per CU (G = 2), 2 (G = 4)
+template <int G> constexpr int kGenWavesPerEU = G == 2 ? 6 : 4;
+
+template <int G>
+__global__ void __launch_bounds__(kWaves * 64, kGenWavesPerEU<G>)
 k_gen(GenJob J, float Rf, uint32_t* __restrict__ err)
 {
-    __shared__ GenLds L;
-    gen_images(L, J, blockIdx.x * kG, Rf, err);
+    __shared__ GenLds<G> L;
+    gen_images<G>(L, J, blockIdx.x * G, Rf, err);
 }
 
 // Persistent form for many meshes: every workgroup takes (job, image group)
 // items from a device counter until none are left.  Jobs are stored largest
 // first, so the long items start early and the short ones fill the tail.
-__global__ void __launch_bounds__(kWaves * 64)
+template <int G>
+__global__ void __launch_bounds__(kWaves * 64, 4)   // 6 would spill here
 k_gen_batched(const GenJob* __restrict__ jobs, uint32_t njobs, uint32_t total_items, float Rf,
               uint32_t* __restrict__ counter, uint32_t* __restrict__ err)
 {
-    __shared__ GenLds L;
+    __shared__ GenLds<G> L;
     __shared__ uint32_t s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
         __syncthreads();
-        const uint32_t item = s_item;
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (item >= total_items) break;
         uint32_t lo = 0, hi = njobs - 1;          // last job with item_start <= item
@@ -462,8 +499,8 @@ k_gen_batched(const GenJob* __restrict__ jobs, uint32_t njobs, uint32_t total_it
             const uint32_t mid = (lo + hi + 1) / 2;
             if (jobs[mid].item_start <= item) lo = mid; else hi = mid - 1;
         }
-        const GenJob& J = jobs[lo];
-        gen_images(L, J, (item - J.item_start) * kG, Rf, err);
+        const GenJob J = jobs[lo];
+        gen_images<G>(L, J, (item - J.item_start) * G, Rf, err);
     }
 }
 
@@ -523,22 +560,35 @@ hipError_t launch_gen_clusters(const float4* cull, uint32_t nt, float4* clusters
 
 hipError_t launch_gen(const float4* cull, const float4* clusters, const float4* verts, uint32_t nt,
                       const float* op_pos, const float* op_nrm, uint32_t n, float R,
-                      uint32_t* out, uint32_t* err, hipStream_t s)
+                      uint32_t* out, uint32_t* err, int group, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     GenJob J = {};
     J.nt = nt; J.op_pos = op_pos; J.op_nrm = op_nrm; J.n = n; J.out = out;
     J.cull = const_cast<float4*>(cull); J.clusters = const_cast<float4*>(clusters); J.verts = const_cast<float4*>(verts);
-    const uint32_t blocks = (n + kG - 1) / kG;
-    hipLaunchKernelGGL(k_gen, dim3(blocks), dim3(kWaves * 64), 0, s, J, R, err);
+    if (group == 2)
+        hipLaunchKernelGGL(k_gen<2>, dim3((n + 1) / 2), dim3(kWaves * 64), 0, s, J, R, err);
+    else
+        hipLaunchKernelGGL(k_gen<4>, dim3((n + 3) / 4), dim3(kWaves * 64), 0, s, J, R, err);
     return hipGetLastError();
 }
 
-uint32_t gen_group_images() { return kG; }
+uint32_t gen_group_images(int group) { return group == 2 ? 2u : 4u; }
+
+hipError_t gen_batched_grid(int group, int cus, uint32_t* grid)
+{
+    int per_cu = 0;
+    hipError_t e = group == 2
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gen_batched<2>, kWaves * 64, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gen_batched<4>, kWaves * 64, 0);
+    if (e != hipSuccess) return e;
+    *grid = (uint32_t)(max(per_cu, 1) * cus);
+    return hipSuccess;
+}
 
 hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total_tris, uint64_t total_chunks,
                               uint32_t total_items, float R, uint32_t* counter, uint32_t* err, uint32_t grid,
-                              hipStream_t s)
+                              int group, hipStream_t s)
 {
     if (njobs == 0) return hipSuccess;
     if (total_tris > 0) {
@@ -555,7 +605,12 @@ hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (total_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gen_batched, dim3(grid), dim3(kWaves * 64), 0, s, jobs, njobs, total_items, R, counter, err);
+    if (group == 2)
+        hipLaunchKernelGGL(k_gen_batched<2>, dim3(grid), dim3(kWaves * 64), 0, s, jobs, njobs, total_items, R, counter,
+                           err);
+    else
+        hipLaunchKernelGGL(k_gen_batched<4>, dim3(grid), dim3(kWaves * 64), 0, s, jobs, njobs, total_items, R, counter,
+                           err);
     return hipGetLastError();
 }
 

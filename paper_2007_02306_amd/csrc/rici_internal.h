@@ -34,12 +34,15 @@ hipError_t launch_gen_prep(const float* pos, uint32_t nv, const uint32_t* tri, u
 hipError_t launch_gen_clusters(const float4* cull, uint32_t nt, float4* clusters, hipStream_t s);
 hipError_t launch_gen(const float4* cull, const float4* clusters, const float4* verts, uint32_t nt,
                       const float* op_pos, const float* op_nrm, uint32_t n, float R,
-                      uint32_t* out, uint32_t* err, hipStream_t s);
-uint32_t gen_group_images();   // images per work item of the generation kernels
+                      uint32_t* out, uint32_t* err, int group, hipStream_t s);
+// images per workgroup (and per work item of the batched kernel): 2 or 4
+uint32_t gen_group_images(int group);
+// workgroups of the persistent generation kernel that fit the device at once
+hipError_t gen_batched_grid(int group, int cus, uint32_t* grid);
 // prep + clusters + persistent generation over `njobs` jobs stored largest first
 hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total_tris, uint64_t total_chunks,
                               uint32_t total_items, float R, uint32_t* counter, uint32_t* err, uint32_t grid,
-                              hipStream_t s);
+                              int group, hipStream_t s);
 
 // -------------------------------------------------------------------- search
 // Column-delta planes in "fragment-major" order: for every group of 16 images

@@ -83,12 +83,13 @@ def test_batch_matches_plain_path_and_oracle(ctx):
 
 
 def test_batch_small_search_tile(ctx):
-    """A plan recorded under the 128-needle search tile gives the plain path's
-    exact results."""
+    """A plan recorded under the 128-needle search tile and 4-image generation
+    workgroups gives the plain path's exact results."""
     from paper_2007_02306_amd import Context
     meshes = _meshes(8, 4, 100, 3000)
     c128 = Context(0)
     c128.set_tuning("search_tile_m", 128)
+    c128.set_tuning("gen_images_per_group", 4)
     jobs = [dict(positions=dev_f32(p), triangles=dev_u32(t), op_positions=dev_f32(p), op_normals=dev_f32(n),
                  true_index=dev_u32(ti)) for p, t, n, ti in meshes]
     b = c128.batch(jobs, 0.3)

@@ -164,3 +164,41 @@ def test_bad_inputs_are_reported(ctx):
     # the handle stays usable
     g = gpu_images(ctx, s.positions, s.triangles, s.op_positions[:3], s.op_normals[:3], 1.0)
     assert g.max() > 0
+
+
+@pytest.fixture()
+def ctx4():
+    from paper_2007_02306_amd import Context
+    c = Context(0)
+    c.set_tuning("gen_images_per_group", 4)
+    assert c.get_tuning("gen_images_per_group") == 4
+    yield c
+    c.close()
+
+
+def test_four_images_per_group_matches_oracle(ctx4):
+    """The 4-image workgroup form of the generation kernel: icosphere (every
+    image, odd count) and tiny random scenes against the oracle."""
+    s = synth.config1_icosphere()
+    g = gpu_images(ctx4, s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    o, fl, _ = oracle.rici_rowrange(s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    assert_images_match(g, o, fl, "icosphere, 4 per group")
+    for seed, n in [(7, 1), (8, 5)]:
+        rng = np.random.default_rng(900 + seed)
+        nt = int(rng.integers(1, 300))
+        pts = rng.uniform(-1, 1, size=(3 * nt, 3)).astype(np.float32)
+        tri = np.arange(3 * nt, dtype=np.uint32).reshape(nt, 3)
+        opp = rng.uniform(-0.5, 0.5, size=(n, 3)).astype(np.float32)
+        opn = rng.normal(size=(n, 3)).astype(np.float32)
+        g = gpu_images(ctx4, pts, tri, opp, opn, 0.8)
+        o, fl, _ = oracle.rici_rowrange(pts, tri, opp, opn, 0.8)
+        assert_images_match(g, o, fl, f"random scene {seed}, 4 per group")
+
+
+def test_group_sizes_agree_at_full_size(ctx, ctx4):
+    """Counts are integer sums, so both workgroup forms give identical images
+    on the benchmark workload."""
+    s = synth.config2_union12()
+    a = gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    b = gpu_images(ctx4, s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    assert np.array_equal(a, b)

@@ -188,4 +188,7 @@ def test_tuning_rejects_bad_values(ctx):
         ctx.set_tuning("search_tile_m", 64)
     with pytest.raises(RiciError):
         ctx.set_tuning("no_such_knob", 1)
+    with pytest.raises(RiciError):
+        ctx.set_tuning("gen_images_per_group", 3)
     assert ctx.get_tuning("search_tile_m") == 256
+    assert ctx.get_tuning("gen_images_per_group") == 2
