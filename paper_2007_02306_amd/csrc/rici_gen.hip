@@ -141,11 +141,12 @@ struct Frame {
 };
 
 // First column c in [0, 64] whose bin radius c + 1/2 exceeds sqrt(s), s >= 0,
-// decided by an exact FP64 comparison.  The FP32 square root is biased low so
-// the guess is the answer or one below it.
+// decided by an exact FP64 comparison.  The guess comes from the hardware FP32
+// square root (about 1 ulp, no refinement), biased low by 2e-5 so that it is
+// the answer or one below it.
 __device__ __forceinline__ int first_col(double s)
 {
-    float f = sqrtf(fminf((float)s, 1.0e4f) * 0.99998f);
+    float f = __builtin_amdgcn_sqrtf(fminf((float)s, 1.0e4f) * 0.99998f);
     int c = (int)floorf(f - 0.5f) + 1;
     c = min(c, 64);
     const double t = (double)c + 0.5;
@@ -157,7 +158,7 @@ __device__ __forceinline__ int first_col(double s)
 __device__ __forceinline__ int first_col_ratio(double cr2, double dd)
 {
     const double approx = cr2 * __builtin_amdgcn_rcp(dd);
-    float f = sqrtf(fminf((float)approx, 1.0e4f) * 0.99990f);
+    float f = __builtin_amdgcn_sqrtf(fminf((float)approx, 1.0e4f) * 0.99990f);
     int c = (int)floorf(f - 0.5f) + 1;
     c = min(max(c, 0), 64);
     const double t = (double)c + 0.5;
