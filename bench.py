@@ -144,13 +144,23 @@ def batched_vs_plain(ctx, meshes: int, seed: int = 4, reps: int = 3):
         jobs.append(dict(positions=f(pos), triangles=i(m.triangles), op_positions=f(pos), op_normals=f(nrm),
                          true_index=i(np.arange(pos.shape[0], dtype=np.uint32))))
         sizes.append((pos.shape[0], m.triangles.shape[0]))
-    plan = ctx.batch(jobs, 0.3)
+    # batched form: knobs picked by the autotuner on a subset of the meshes
+    # (not timed); plain form: a separate handle with the default knobs
+    from paper_2007_02306_amd import Context
+    from paper_2007_02306_amd.tune import Tuner
+    tuner = Tuner(ctx, cache_path=None)
+    t0 = time.perf_counter()
+    knobs = tuner.tune_batch(jobs, 0.3)
+    tune_s = time.perf_counter() - t0
+    plan = tuner.batch(jobs, 0.3)
+    plain_ctx = Context(0)
 
     def plain():
         for k, j in enumerate(jobs):
             img = plan.images[k]
-            ctx.generate(j["positions"], j["triangles"], j["op_positions"], j["op_normals"], 0.3, out=img)
-            ctx.distance_rank(img, img, j["true_index"], out_rank=plan.rank[k], out_true_distance=plan.true_distance[k])
+            plain_ctx.generate(j["positions"], j["triangles"], j["op_positions"], j["op_normals"], 0.3, out=img)
+            plain_ctx.distance_rank(img, img, j["true_index"], out_rank=plan.rank[k],
+                                    out_true_distance=plan.true_distance[k])
 
     def timeit(fn):
         fn()
@@ -167,13 +177,19 @@ def batched_vs_plain(ctx, meshes: int, seed: int = 4, reps: int = 3):
     t_plain = timeit(plain)
     t_batch = timeit(plan.run)
     ctx.sync()
+    plain_ctx.sync()
     n_img = sum(v for v, _ in sizes)
     pairs = sum(v * v for v, _ in sizes)
     out = {"meshes": meshes, "images": n_img, "triangles": sum(t for _, t in sizes), "distance_pairs": pairs,
            "plain_s": t_plain, "batched_s": t_batch, "speedup": t_plain / t_batch,
            "batched_rici_per_s": n_img / t_batch, "plain_rici_per_s": n_img / t_plain,
-           "plan_scratch_gb": plan.scratch_bytes / 1e9}
+           "plan_scratch_gb": plan.scratch_bytes / 1e9,
+           "autotuned": {"gen_images_per_group": knobs[0], "search_tile_m": knobs[1], "tune_s": tune_s,
+                         "candidates_ms": {f"{g}x{m}": ms for _, (g, m), ms in tuner.measurements}},
+           "plain_knobs": {"gen_images_per_group": plain_ctx.get_tuning("gen_images_per_group"),
+                           "search_tile_m": plain_ctx.get_tuning("search_tile_m")}}
     plan.close()
+    plain_ctx.close()
     return out
 
 

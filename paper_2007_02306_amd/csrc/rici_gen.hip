@@ -482,8 +482,10 @@ k_gen(GenJob J, float Rf, uint32_t* __restrict__ err)
 // Persistent form for many meshes: every workgroup takes (job, image group)
 // items from a device counter until none are left.  Jobs are stored largest
 // first, so the long items start early and the short ones fill the tail.
+// (G = 2 spills a few registers of the per-item loop here, none in the
+// triangle or slice loops)
 template <int G>
-__global__ void __launch_bounds__(kWaves * 64, 4)   // 6 would spill here
+__global__ void __launch_bounds__(kWaves * 64, kGenWavesPerEU<G>)
 k_gen_batched(const GenJob* __restrict__ jobs, uint32_t njobs, uint32_t total_items, float Rf,
               uint32_t* __restrict__ counter, uint32_t* __restrict__ err)
 {

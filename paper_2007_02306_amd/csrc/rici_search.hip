@@ -404,9 +404,12 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             F.a[mb] = *reinterpret_cast<const v4i*>(sA + (wm * C::kMB + mb) * (int)kFragBytes);
     };
     // One pipeline step: make stage s+1 visible, refill the slot of stage s-1
-    // with stage s+NS-1, fetch stage s+1's fragments into registers, and run
-    // stage s's MFMAs from the fragments fetched one step earlier, so the LDS
-    // reads of one stage overlap the matrix work of the previous one.
+    // with stage s+NS-1, then run stage s's MFMAs (fragments fetched one step
+    // earlier) interleaved with the LDS reads of stage s+1's fragments, so
+    // the reads of one stage overlap the matrix work of the previous one.  The
+    // reads are issued on every step (after the last stage they read a stale
+    // slot and are never used) and only after the first MFMAs, so that the
+    // wait in front of the MFMAs covers only the previous step's reads.
     auto step = [&](int s, const Frags& cur, Frags& nxt) {
         if (s + 1 < nstage) {
             // outstanding loads beyond stage s+1: stages s+2 .. s+NS-2
@@ -414,21 +417,31 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             else wait_vmcnt<0>();
             stage_barrier();
             if (s + C::kNS - 1 < nstage) issue(s + C::kNS - 1);
-            read_frags(s + 1, nxt);
         }
-        if (s > 0 && s % NB == 0) {
-            // end of a phase: scale the partial sum (x64 after q, x2 after -D.D)
-            const int sh = (hq && s == NB) ? 6 : 1;
-#pragma unroll
-            for (int mb = 0; mb < C::kMB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << sh;
-        }
+        read_frags(s + 1, nxt);
 #pragma unroll
         for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < C::kNBK; ++nb)
                 acc[mb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur.a[mb], cur.b[nb], acc[mb][nb], 0, 0, 0);
+        // schedule: 2 MFMAs, 1 fragment read, repeated; then the rest of the MFMAs
+        constexpr int kReads = C::kMB + C::kNBK;
+        static_assert(2 * kReads <= C::kMB * C::kNBK, "interleave pattern");
+#pragma unroll
+        for (int i = 0; i < kReads; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+        }
+        if constexpr (C::kMB * C::kNBK > 2 * kReads)
+            __builtin_amdgcn_sched_group_barrier(0x008, C::kMB * C::kNBK - 2 * kReads, 0);
+        if ((s + 1) % NB == 0 && s + 1 < nstage) {
+            // end of a phase: scale the partial sum (x64 after q, x2 after -D.D)
+            const int sh = (hq && s + 1 == NB) ? 6 : 1;
+#pragma unroll
+            for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << sh;
+        }
     };
 
     static_assert(C::kNS >= 3 && C::kNS < 2 * NB, "ring depth");
