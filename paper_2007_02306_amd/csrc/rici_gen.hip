@@ -422,17 +422,9 @@ __device__ void gen_images(GenLds<G>& L, const GenJob& J, uint32_t img0, float R
         return (fabsf(h) <= P[g][6] + sp.w) & (a2 <= la * la);
     };
 
-    const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
-    for (uint32_t base = wv * 64; base < nt; base += kWaves * 64) {
-        // whole 64-triangle run first (same value in every lane)
-        const float4 cs = clusters[base / 64];
-        uint32_t cmask = 0;
-#pragma unroll
-        for (int g = 0; g < G; ++g) cmask |= (reaches(cs, g) ? 1u : 0u) << g;
-        cmask = __builtin_amdgcn_readfirstlane(cmask);
-        if (cmask == 0) continue;
-        const uint32_t t = base + lane;
-        const float4 s = t < nt ? cull[t] : make_float4(0.f, 0.f, 0.f, -INFINITY);
+    // Test one run of 64 triangles (spheres s, triangle t = run * 64 + lane)
+    // against the images in cmask and append the survivors to the ring.
+    auto test_run = [&](const float4& s, uint32_t t, uint32_t cmask) {
         uint32_t mask = 0;
 #pragma unroll
         for (int g = 0; g < G; ++g)
@@ -452,6 +444,29 @@ __device__ void gen_images(GenLds<G>& L, const GenJob& J, uint32_t img0, float R
                 process_batch<G>(L, wave, lane, head, 64, verts);
                 head += 64;
             }
+        }
+    };
+
+    // Runs of this wave: wv, wv + 8, wv + 16, ...  Their bounding spheres are
+    // tested 64 at a time (one run per lane), then the passing runs are
+    // tested triangle by triangle.  (A sphere that never passes is built in
+    // place: a named local would turn the guarded loads into flat loads
+    // through a pointer select.)
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
+    const uint32_t nc = (nt + 63) / 64;
+    for (uint32_t c0 = wv; c0 < nc; c0 += kWaves * 64) {
+        const uint32_t cl = c0 + kWaves * (uint32_t)lane;
+        const float4 cs = cl < nc ? clusters[cl] : make_float4(0.f, 0.f, 0.f, -INFINITY);
+        uint32_t cm = 0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) cm |= (reaches(cs, g) ? 1u : 0u) << g;
+        for (uint64_t pend = __ballot(cm != 0); pend != 0; pend &= pend - 1) {
+            const int l = (int)__builtin_ctzll(pend);
+            const uint32_t run = c0 + kWaves * (uint32_t)l;
+            const uint32_t rmask = (uint32_t)__builtin_amdgcn_readlane((int)cm, l);
+            const uint32_t t = run * 64 + (uint32_t)lane;
+            const float4 s = t < nt ? cull[t] : make_float4(0.f, 0.f, 0.f, -INFINITY);
+            test_run(s, t, rmask);
         }
     }
     if (tail > head) process_batch<G>(L, wave, lane, head, tail - head, verts);
