@@ -330,11 +330,17 @@ __device__ void process_batch(GenLds<G>& L, int wave, int lane, uint32_t head, u
             int c_lo = first_col(lo2), c_hi = first_col(hi2);
             int c_c = between ? min(first_col_ratio(cr * cr, dd), c_lo) : c_lo;
             if (!ok) { c_lo = c_hi = c_c = 64; }
-            // +2 on [c_c, c_lo), +1 on [c_lo, c_hi) as a difference row
+            // +2 on [c_c, c_lo), +1 on [c_lo, c_hi) as a difference row: +2 at
+            // c_c, -1 at c_lo, -1 at c_hi, with coinciding columns merged and
+            // zero or past-the-image (column 64) updates dropped (LDS atomics
+            // are the slice stage's most expensive instructions)
+            uint32_t v0 = 2u, v1 = (uint32_t)-1, v2 = (uint32_t)-1;
+            if (c_c == c_lo) { v0 = 0u; v1 = 1u; }
+            if (c_lo == c_hi) { v1 -= 1u; v2 = 0u; }
             uint32_t* row = L.diff[gi] + r * kDiffStride;
-            atomicAdd(row + c_c, 2u);
-            atomicAdd(row + c_lo, (uint32_t)-1);
-            atomicAdd(row + c_hi, (uint32_t)-1);
+            if (v0 != 0u && c_c < 64) atomicAdd(row + c_c, v0);
+            if (v1 != 0u && c_lo < 64) atomicAdd(row + c_lo, v1);
+            if (v2 != 0u && c_hi < 64) atomicAdd(row + c_hi, v2);
         }
         wave_sync_lds();
     }
