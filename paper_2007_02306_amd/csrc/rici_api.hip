@@ -310,7 +310,9 @@ int prep_both(rici_ctx* h, SearchScratch& S, const uint32_t* needles, uint32_t n
 {
     hipError_t e = timed(h, "delta_needle", s, [&] { return rici::launch_delta_prep(needles, nn, 1, S.np, s); });
     if (e != hipSuccess) return hip_fail(e, "delta_needle launch");
-    e = timed(h, "delta_haystack", s, [&] { return rici::launch_delta_prep(hay, nh, 0, S.hp, s); });
+    // a set ranked against itself: the haystack's max |D| comes from the needle pass
+    const uint32_t* known = (hay == needles && nh == nn) ? S.np.maxabs : nullptr;
+    e = timed(h, "delta_haystack", s, [&] { return rici::launch_delta_prep(hay, nh, 0, S.hp, s, known); });
     if (e != hipSuccess) return hip_fail(e, "delta_haystack launch");
     return RICI_OK;
 }

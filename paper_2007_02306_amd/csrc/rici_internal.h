@@ -111,8 +111,10 @@ struct SearchTotals {
     uint64_t needle_groups, hay_slots, hay_images, hay_groups, needles, tiles;
 };
 
+// known_maxabs (haystack side, optional): per-image max |D| already computed
+// for the same images (by the needle pass when a set is ranked against itself)
 hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side,
-                             const SearchPrep& p, hipStream_t s);
+                             const SearchPrep& p, hipStream_t s, const uint32_t* known_maxabs = nullptr);
 // every prep, rank and fallback step of `njobs` jobs (stored largest first),
 // with a persistent search kernel of `grid` workgroups
 hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,

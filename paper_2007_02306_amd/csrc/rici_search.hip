@@ -174,6 +174,13 @@ k_hay_stats(const uint32_t* __restrict__ images, uint32_t n, uint32_t* __restric
     if (img < n) hay_stats_one(images, maxabs_img, img, threadIdx.x & 63);
 }
 
+__global__ void __launch_bounds__(256)
+k_copy_u32(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 __device__ void hay_assign_block(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslots,
                                  uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs)
 {
@@ -668,7 +675,13 @@ k_hay_stats_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint64_t
     const uint64_t x = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (x >= total) return;
     const SearchJob& J = jobs[job_of<2>(jobs, njobs, x)];
-    hay_stats_one(J.hay, J.hp.maxabs_img, (uint32_t)(x - J.himg_start), threadIdx.x & 63);
+    const uint32_t img = (uint32_t)(x - J.himg_start);
+    if (J.hay == J.needles) {
+        // ranking a set against itself: the needle pass already found max |D|
+        if ((threadIdx.x & 63) == 0) J.hp.maxabs_img[img] = J.np.maxabs[img];
+    } else {
+        hay_stats_one(J.hay, J.hp.maxabs_img, img, threadIdx.x & 63);
+    }
 }
 
 __global__ void __launch_bounds__(1024)
@@ -733,7 +746,7 @@ size_t haystack_slots(uint32_t nh)
 }
 
 hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side, const SearchPrep& p,
-                             hipStream_t s)
+                             hipStream_t s, const uint32_t* known_maxabs)
 {
     if (p.ngroups == 0) return hipSuccess;
     if (p.perm) {
@@ -742,7 +755,10 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (n > 0) {
-            hipLaunchKernelGGL(k_hay_stats, dim3((n + 3) / 4), dim3(256), 0, s, images, n, p.maxabs_img);
+            if (known_maxabs)
+                hipLaunchKernelGGL(k_copy_u32, dim3((n + 255) / 256), dim3(256), 0, s, known_maxabs, p.maxabs_img, n);
+            else
+                hipLaunchKernelGGL(k_hay_stats, dim3((n + 3) / 4), dim3(256), 0, s, images, n, p.maxabs_img);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_hay_assign, dim3(1), dim3(1024), 0, s, p.maxabs_img, n, nslots, p.perm, p.maxabs);
