@@ -45,6 +45,8 @@ def parse():
                     help="meshes in the batched-vs-plain comparison (0 to skip)")
     ap.add_argument("--db-images", type=int, default=1_000_000, help="serving: database size")
     ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
+    ap.add_argument("--no-other-configs", dest="other_configs", action="store_false",
+                    help="skip the icosphere and clutter-scene figures")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scales the HBM byte counters)")
     return ap.parse_args()
@@ -92,10 +94,12 @@ def copy_calibration():
     print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4, "copies": 3}}), flush=True)
 
 
-def cpu_baseline(scene, n_img, n_needles):
+def cpu_baseline(scene, n_img, n_needles, gpu_images=None, gpu_rank=None):
     """The oracle, as it stands, on a bounded sample of the benchmark workload:
     generation of `n_img` seeded images and ranking of `n_needles` needles over
-    a full-size haystack of oracle images; scaled to RICIs per second."""
+    a full-size haystack of oracle images; scaled to RICIs per second.  Also a
+    1-thread figure on a smaller sample, and the parity verdict of the GPU's
+    images (and ranks, against the GPU images as haystack) on the sample."""
     import numpy as np
     import oracle
 
@@ -104,8 +108,8 @@ def cpu_baseline(scene, n_img, n_needles):
     sel = np.sort(rng.choice(n, min(n_img, n), replace=False))
     cores = oracle.threads(0)
     t0 = time.perf_counter()
-    imgs, _, work = oracle.rici_rowrange(scene.positions, scene.triangles, scene.op_positions[sel],
-                                         scene.op_normals[sel], scene.support_radius, nthreads=cores)
+    imgs, flags, work = oracle.rici_rowrange(scene.positions, scene.triangles, scene.op_positions[sel],
+                                             scene.op_normals[sel], scene.support_radius, nthreads=cores)
     t_gen = (time.perf_counter() - t0) / len(sel)
     hay = np.resize(imgs, (n, 64, 64))          # full-size haystack of oracle images
     nsel = np.arange(min(n_needles, len(sel)))
@@ -113,14 +117,119 @@ def cpu_baseline(scene, n_img, n_needles):
     oracle.rank(imgs[nsel], hay, nsel.astype(np.uint32), nthreads=cores)
     t_rank = (time.perf_counter() - t0) / len(nsel)
     per_img = t_gen + t_rank
-    return {
+    # one thread, smaller sample
+    s1 = sel[:64]
+    t0 = time.perf_counter()
+    oracle.rici_rowrange(scene.positions, scene.triangles, scene.op_positions[s1], scene.op_normals[s1],
+                         scene.support_radius, nthreads=1)
+    t_gen1 = (time.perf_counter() - t0) / len(s1)
+    t0 = time.perf_counter()
+    oracle.rank(imgs[:4], hay, np.arange(4, dtype=np.uint32), nthreads=1)
+    t_rank1 = (time.perf_counter() - t0) / 4
+    out = {
         "value": 1.0 / per_img,
         "unit": "RICIs/s",
         "cores": cores,
         "kind": "oracle",
         "sample": f"generation of {len(sel)} of {n} images + rank of {len(nsel)} needles against {n} "
                   f"haystack images; {t_gen * 1e3:.2f} ms/image + {t_rank * 1e3:.2f} ms/needle on {cores} threads",
-    }, work, sel
+        "single_thread": {"value": 1.0 / (t_gen1 + t_rank1), "unit": "RICIs/s",
+                          "sample": f"generation of {len(s1)} images + rank of 4 needles on 1 thread"},
+    }
+    if gpu_images is not None:
+        # parity of the GPU's images on the sample: equal at every pixel the
+        # oracle does not flag; ranks of the sample needles against the GPU's
+        # full haystack, true match = themselves shuffled
+        g = gpu_images[sel]
+        diff = (g != imgs)
+        verdict = {"images": int(len(sel)), "pixels": int(diff.size), "flagged_pixels": int(flags.sum()),
+                   "mismatches_outside_flags": int((diff & ~flags.astype(bool)).sum())}
+        if gpu_rank is not None:
+            ranks_gpu, needles_idx, true_idx = gpu_rank
+            k = min(32, len(needles_idx))
+            ork, _ = oracle.rank(gpu_images[needles_idx[:k]], gpu_images, true_idx[:k], nthreads=cores)
+            verdict["ranks_checked"] = int(k)
+            verdict["rank_mismatches"] = int((ork != ranks_gpu[:k]).sum())
+        out["parity"] = verdict
+    return out, work, sel
+
+
+def value_distributions(images):
+    """Statistics of a device image set (torch int32 [N,64,64]) that set the
+    search's arithmetic paths: count histogram summary, needle-mask density
+    (fraction of D != 0), per-image max |D| classes."""
+    import torch
+    x = images.to(torch.int64)
+    d = x[:, :, 1:] - x[:, :, :-1]
+    mx = d.abs().amax(dim=(1, 2))
+    n = images.shape[0]
+    hist = torch.bincount(images.clamp(max=16).flatten().to(torch.int64), minlength=17).cpu().tolist()
+    return {
+        "count_histogram_0_to_16plus": hist,
+        "max_count": int(images.max()),
+        "mask_density": float((d != 0).float().mean()),
+        "max_abs_delta_share": {"le_11": float((mx <= 11).sum()) / n,
+                                "12_to_127": float(((mx > 11) & (mx <= 127)).sum()) / n,
+                                "gt_127": float((mx > 127).sum()) / n},
+    }
+
+
+def per_config(ctx, reps: int = 3):
+    """Describe-and-rank figures of the icosphere (every image, full matrix)
+    and of the clutter scene (haystack = every scene vertex, needles = object 0
+    alone): best of `reps` runs each, HIP events for the kernels."""
+    import numpy as np
+    import torch
+    import synth
+
+    dev = torch.device("cuda:0")
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+    i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(dev)
+    out = {}
+    for name, make in (("icosphere", synth.config1_icosphere), ("clutter", synth.config3_clutter)):
+        sc = make()
+        hp, ht = f32(sc.positions), i32(sc.triangles)
+        hop, hon = f32(sc.op_positions), f32(sc.op_normals)
+        npos, ntri = f32(sc.needle_positions), i32(sc.needle_triangles)
+        nop, non = f32(sc.needle_op_positions), f32(sc.needle_op_normals)
+        ti = i32(sc.true_index)
+        nh, nn = hop.shape[0], nop.shape[0]
+        himg = torch.empty((nh, 64, 64), dtype=torch.int32, device=dev)
+        nimg = himg if sc.needle_op_positions is sc.op_positions else torch.empty((nn, 64, 64), dtype=torch.int32,
+                                                                                 device=dev)
+        best = None
+        for _ in range(reps + 1):
+            ctx.timing(True)
+            ctx.timing_reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.generate(hp, ht, hop, hon, sc.support_radius, out=himg)
+            if nimg is not himg:
+                ctx.generate(npos, ntri, nop, non, sc.support_radius, out=nimg)
+            rank, dist = ctx.distance_rank(nimg, himg, ti)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            gen_ms = ctx.timing_get("gen")[0]
+            search_ms = ctx.timing_get("search")[0]
+            ctx.timing(False)
+            if best is None or wall < best[0]:
+                best = (wall, gen_ms, search_ms)
+        wall, gen_ms, search_ms = best
+        pairs_gen = nh * sc.triangles.shape[0] + (0 if nimg is himg else nn * sc.needle_triangles.shape[0])
+        out[name] = {"images": int(nh + (0 if nimg is himg else nn)), "needles": int(nn), "haystack": int(nh),
+                     "triangles": int(sc.triangles.shape[0]), "wall_ms": wall * 1e3, "gen_ms": gen_ms,
+                     "search_ms": search_ms,
+                     "rici_per_s": (nh + (0 if nimg is himg else nn)) / wall,
+                     "image_triangle_pairs_per_s": pairs_gen / (gen_ms * 1e-3),
+                     "distance_pairs_per_s": float(nn) * nh / (search_ms * 1e-3),
+                     "ranks_per_s": nn / wall,
+                     "max_rank": int(rank.max())}
+        if name == "icosphere":
+            m = ctx.distance_matrix(nimg, himg)
+            torch.cuda.synchronize()
+            out[name]["matrix_checked_diagonal_zero"] = bool((torch.diagonal(m) == 0).all())
+        del himg, nimg
+    return out
 
 
 def batched_vs_plain(ctx, meshes: int, seed: int = 4, reps: int = 3):
@@ -342,7 +451,18 @@ def main():
     cpu = None
     work = None
     if not args.no_cpu_baseline:
-        cpu, work, _ = cpu_baseline(scene, args.cpu_images, args.cpu_needles)
+        # ranks of a seeded sample of needles against the GPU images with a
+        # shuffled true-match map (non-trivial ranks) for the parity verdict
+        rs = np.random.default_rng(7)
+        nidx = np.sort(rs.choice(N, 32, replace=False))
+        tmap = rs.permutation(N)[:32].astype(np.uint32)
+        rk, _ = ctx.distance_rank(images[torch.from_numpy(nidx).to(dev)].contiguous(), images,
+                                  i32(tmap))
+        ctx.sync()
+        host_images = images.cpu().numpy().view(np.uint32)
+        cpu, work, _ = cpu_baseline(scene, args.cpu_images, args.cpu_needles, gpu_images=host_images,
+                                    gpu_rank=(rk.cpu().numpy().view(np.uint32), nidx, tmap))
+    dist = value_distributions(images)
 
     gen_ms = kernels["gen"]["avg_ms"]
     roof_gen = None
@@ -360,6 +480,7 @@ def main():
                     "ops_basis": "oracle work counters on the CPU-baseline sample"}
 
     batched = batched_vs_plain(ctx, args.batch_meshes) if args.batch_meshes > 0 else None
+    others = per_config(ctx) if args.other_configs else None
 
     dominant = "search" if (search_ms or 0) >= (gen_ms or 0) else "gen"
     roofline = roof_search if dominant == "search" or roof_gen is None else roof_gen
@@ -381,11 +502,16 @@ def main():
                                "R=0.3, 64x64 u32 RICIs, all-vs-all CRD rank (23352 x 23352)",
                    "images": N, "triangles": T, "distance_pairs": N * N},
         "rates": {"rici_per_s": value, "distance_pairs_per_s": float(N) * N / (ms_step * 1e-3),
-                  "gen_only_rici_per_s": N / (gen_ms * 1e-3) if gen_ms else None},
+                  "ranks_per_s": value,
+                  "gen_only_rici_per_s": N / (gen_ms * 1e-3) if gen_ms else None,
+                  "image_triangle_pairs_per_s": float(N) * T / (gen_ms * 1e-3) if gen_ms else None,
+                  "search_only_distance_pairs_per_s": float(N) * N / (search_ms * 1e-3) if search_ms else None},
+        "value_distributions": dist,
         "roofline": roofline,
         "roofline_other": roof_gen if roofline is roof_search else roof_search,
         "kernels": kernels,
         "batched_vs_plain": batched,
+        "other_configs": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
