@@ -222,6 +222,13 @@ int rici_timing_get(rici_handle h, const char* kernel, double* total_ms, uint64_
  *   "gen_images_per_group"  images sharing one generation workgroup (and its
  *                    triangle stream): 2 (default) or 4.  Read by
  *                    rici_generate and rici_batch_create (fixed into the plan).
+ *   "search_early_exit"  0 (default) or 1: in rank mode a search tile stops
+ *                    once every partial distance of its last contraction phase
+ *                    (where partial sums only grow) has reached its needle's
+ *                    threshold, so the tile can add to no rank.  Ranks are
+ *                    unchanged; it saves work when true matches are close
+ *                    (clutter, serving).  Read by rici_distance_rank,
+ *                    rici_batch_create and rici_query_create.
  *   "search_tile_m"  needles per search workgroup tile: 256 (default) or 128.
  *                    The smaller tile wastes less work on padding when a
  *                    needle set is small or just above a multiple of 256.

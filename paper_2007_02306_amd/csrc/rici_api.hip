@@ -26,6 +26,7 @@ struct rici_ctx {
     bool timing = false;
     int search_variant = 0;         // search tile: 0 = 256 x 256, 1 = 128 x 256
     int gen_group = 2;              // images per generation workgroup: 2 or 4
+    int early_exit = 0;             // search tiles may stop once no pair can count (rank mode)
     std::vector<TimedLaunch> launches;
     std::vector<hipEvent_t> free_events;
 };
@@ -354,7 +355,7 @@ int rici_distance_rank(rici_handle h, const uint32_t* needles, uint32_t num_need
     if (e != hipSuccess) return hip_fail(e, "true_distance launch");
     e = timed(h, "search", s, [&] {
         return rici::launch_search(S.np, num_needles, S.hp, num_haystack, S.thr, S.np.sumsq, out_rank, nullptr,
-                                   h->search_variant, s);
+                                   h->search_variant, h->early_exit, s);
     });
     if (e != hipSuccess) return hip_fail(e, "search launch");
     e = timed(h, "fallback", s, [&] {
@@ -387,7 +388,7 @@ int rici_distance_matrix(rici_handle h, const uint32_t* needles, uint32_t num_ne
     if (rc) return rc;
     hipError_t e = timed(h, "matrix", s, [&] {
         return rici::launch_search(S.np, num_needles, S.hp, num_haystack, nullptr, S.np.sumsq, nullptr, out,
-                                   h->search_variant, s);
+                                   h->search_variant, 0, s);
     });
     if (e != hipSuccess) return hip_fail(e, "matrix launch");
     e = timed(h, "fallback", s, [&] {
@@ -401,6 +402,12 @@ int rici_distance_matrix(rici_handle h, const uint32_t* needles, uint32_t num_ne
 int rici_set_tuning(rici_handle h, const char* key, int value)
 {
     if (!h || !key) return fail(RICI_ERR_INVALID, "rici_set_tuning: NULL handle or key");
+    if (strcmp(key, "search_early_exit") == 0) {
+        if (value != 0 && value != 1)
+            return fail(RICI_ERR_INVALID, "rici_set_tuning: search_early_exit must be 0 or 1 (got %d)", value);
+        h->early_exit = value;
+        return RICI_OK;
+    }
     if (strcmp(key, "gen_images_per_group") == 0) {
         if (value != 4 && value != 2)
             return fail(RICI_ERR_INVALID, "rici_set_tuning: gen_images_per_group must be 4 or 2 (got %d)", value);
@@ -421,6 +428,10 @@ int rici_get_tuning(rici_handle h, const char* key, int* value)
     if (!h || !key || !value) return fail(RICI_ERR_INVALID, "rici_get_tuning: NULL argument");
     if (strcmp(key, "gen_images_per_group") == 0) {
         *value = h->gen_group;
+        return RICI_OK;
+    }
+    if (strcmp(key, "search_early_exit") == 0) {
+        *value = h->early_exit;
         return RICI_OK;
     }
     if (strcmp(key, "search_tile_m") == 0) {
@@ -655,6 +666,7 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
         A.tiles_m = (uint32_t)((n + tm - 1) / tm);
         A.tiles_n = (uint32_t)(hs / tn);
         A.per_xcd = 0;
+        A.early_exit = (uint32_t)h->early_exit;
         S.ngrp_start = T.needle_groups; S.hslot_start = T.hay_slots; S.himg_start = T.hay_images;
         S.hgrp_start = T.hay_groups; S.needle_start = T.needles; S.tile_start = tiles;
         T.needle_groups += ga; T.hay_slots += hs; T.hay_images += n; T.hay_groups += gb; T.needles += n;
@@ -687,7 +699,8 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
         le = rici::launch_gen_batched(d_gjobs, (uint32_t)gj.size(), tri, chunks, items, support_radius, d_counters,
                                       h->d_err, gen_grid, gen_group, cs);
         if (le == hipSuccess)
-            le = rici::launch_search_batched(d_sjobs, (uint32_t)sj.size(), T, d_counters + 1, grid, variant, cs);
+            le = rici::launch_search_batched(d_sjobs, (uint32_t)sj.size(), T, d_counters + 1, grid, variant,
+                                                h->early_exit, cs);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cs, &graph);
         b->graph = graph;
@@ -749,6 +762,7 @@ struct rici_query_ctx {
     uint32_t* rank = nullptr;
     uint32_t nn = 0, tiles_m = 0;
     int variant = 0;                // search tile shape the needle tiles were counted for
+    int early_exit = 0;
 };
 
 namespace {
@@ -881,6 +895,7 @@ int rici_query_create(rici_handle h, rici_db db, const uint32_t* needles, uint32
     q->rank = out_rank;
     q->nn = num_needles;
     q->variant = h->search_variant;
+    q->early_exit = h->early_exit;
     q->tiles_m = (num_needles + rici::search_tile_m(q->variant) - 1) / rici::search_tile_m(q->variant);
     hipStream_t s = (hipStream_t)stream;
     e = timed(h, "delta_needle", s, [&] { return rici::launch_delta_prep(needles, num_needles, 1, q->np, s); });
@@ -938,6 +953,7 @@ int rici_db_scan(rici_handle h, rici_db db, const rici_query* queries, uint32_t 
         A.nmax = q->np.maxabs; A.hmax = db->hp.maxabs; A.hperm = db->hp.perm;
         A.thr = q->thr; A.sumsq = q->np.sumsq; A.rank = q->rank; A.matrix = nullptr;
         A.tiles_m = q->tiles_m; A.tiles_n = db->tiles; A.per_xcd = 0;
+        A.early_exit = (uint32_t)q->early_exit;
         T.m_start[k] = m;
         m += q->tiles_m;
     }

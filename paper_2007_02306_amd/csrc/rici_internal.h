@@ -82,6 +82,9 @@ struct SearchArgs {
     uint32_t* rank;
     int64_t* matrix;
     uint32_t tiles_m, tiles_n, per_xcd;
+    // rank mode only: leave a tile as soon as every partial distance of its
+    // last (monotone) phase has reached the needle's threshold
+    uint32_t early_exit;
 };
 
 // One ranking job of a batched call (device copy): its arguments, its scratch
@@ -118,14 +121,14 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
 // every prep, rank and fallback step of `njobs` jobs (stored largest first),
 // with a persistent search kernel of `grid` workgroups
 hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,
-                                 uint32_t grid, int variant, hipStream_t s);
+                                 uint32_t grid, int variant, int early_exit, hipStream_t s);
 size_t haystack_slots(uint32_t nh);   // slots allocated for a haystack of nh images
 hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                                 const uint32_t* true_idx, const int64_t* sumsq, const uint32_t* nmax,
                                 int64_t* dstar, int32_t* thr, uint32_t* rank, hipStream_t s);
 hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
                          const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix, int variant,
-                         hipStream_t s);
+                         int early_exit, hipStream_t s);
 // `lists` scratch: 2 + nn + nh uint32
 hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                            const uint32_t* nmax, const uint32_t* hmax, const int64_t* dstar,

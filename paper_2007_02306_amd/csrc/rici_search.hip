@@ -286,7 +286,12 @@ struct SearchCfg {
     static constexpr int kFrags = GA + GB;           // 1 KiB fragments per stage (one image row)
     static constexpr int kStage = kFrags * (int)kFragBytes;
     static constexpr int kLPW = kFrags / kWaves;     // fragment loads per wave per stage
-    static constexpr int kLds = NS * kStage;         // ring of NS stages
+    // after the ring: early-exit votes (one word per wave), the tile's needle
+    // thresholds (BM int32) and haystack usability flags (BN bytes)
+    static constexpr int kVote = NS * kStage;
+    static constexpr int kThr = kVote + 64;
+    static constexpr int kCol = kThr + BM * 4;
+    static constexpr int kLds = kCol + BN;
     static_assert(kFrags % kWaves == 0, "fragments must split evenly over the waves");
 };
 
@@ -331,7 +336,8 @@ __device__ __forceinline__ void tile_coords(uint32_t logical, uint32_t tiles_m, 
 }
 
 // One BM x BN (needle x haystack) tile: every workgroup thread takes part.
-template <class C>
+// EXIT compiles in the early exit of rank mode (taken when A.early_exit is set).
+template <class C, bool EXIT>
 __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_t* lds)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -417,6 +423,52 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // reads are issued on every step (after the last stage they read a stale
     // slot and are never used) and only after the first MFMAs, so that the
     // wait in front of the MFMAs covers only the previous step's reads.
+    // Early exit (rank mode): in the last phase the partial sums only grow
+    // (they add <m, D_h^2> or <m, D_h^2 mod 128>, both >= 0), so once no pair
+    // of the tile is below its needle's threshold none will be, and the tile
+    // adds nothing to any rank.  Checked every 16 rows of that phase: each
+    // wave votes through LDS, the next stage barrier publishes the votes.
+    const bool exit_ok = EXIT && A.early_exit && A.thr && !A.matrix;
+    volatile uint32_t* votes = reinterpret_cast<volatile uint32_t*>(lds + C::kVote);
+    int32_t* thr_l = reinterpret_cast<int32_t*>(lds + C::kThr);
+    uint8_t* col_l = reinterpret_cast<uint8_t*>(lds + C::kCol);
+    const int last_phase = nstage - NB;
+    if (exit_ok) {
+        // the tile's thresholds and usable columns, read by the votes from LDS
+        // (global loads there would drain the stage loads in flight); visible
+        // after the first stage barrier, long before the first vote
+        for (int j = tid; j < C::BM; j += C::kThreads) {
+            const uint32_t row = ga0 * 16 + j;
+            thr_l[j] = row < A.nn ? A.thr[row] : INT_MIN;
+        }
+        for (int j = tid; j < C::BN; j += C::kThreads) col_l[j] = A.hmax[gb0 * 16 + j] <= kSlow ? 1 : 0;
+    }
+    auto vote = [&]() {
+        bool alive = false;
+        const int cl = lane & 15, rq = lane >> 4;
+        bool colok[C::kNBK];
+#pragma unroll
+        for (int nb = 0; nb < C::kNBK; ++nb) colok[nb] = col_l[(wn * C::kNBK + nb) * 16 + cl] != 0;
+#pragma unroll
+        for (int mb = 0; mb < C::kMB; ++mb) {
+            // one block row at a time (four thresholds live), in program order
+            const v4i t = *reinterpret_cast<const v4i*>(thr_l + (wm * C::kMB + mb) * 16 + 4 * rq);
+#pragma unroll
+            for (int nb = 0; nb < C::kNBK; ++nb)
+                alive |= colok[nb] && (acc[mb][nb].x < t.x || acc[mb][nb].y < t.y || acc[mb][nb].z < t.z ||
+                                       acc[mb][nb].w < t.w);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const uint64_t any_alive = __ballot(alive);   // every lane takes part
+        if (lane == 0) votes[wave] = any_alive != 0 ? 1u : 0u;
+    };
+    auto all_done = [&]() -> bool {
+        uint32_t any = 0;
+#pragma unroll
+        for (int w = 0; w < C::kWaves; ++w) any |= votes[w];
+        return __builtin_amdgcn_readfirstlane(any) == 0;
+    };
+
     auto step = [&](int s, const Frags& cur, Frags& nxt) {
         if (s + 1 < nstage) {
             // outstanding loads beyond stage s+1: stages s+2 .. s+NS-2
@@ -461,6 +513,16 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     for (int s = 0; s < nstage; s += 2) {   // nstage is even
         step(s, fr0, fr1);
         step(s + 1, fr1, fr0);
+        // after 16, 32 and 48 rows of the last phase: vote, publish, decide
+        if (exit_ok && s + 2 > last_phase && (s + 2 - last_phase) % 16 == 0 && s + 2 < nstage) {
+            vote();
+            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the votes are written
+            stage_barrier();
+            if (all_done()) {
+                wait_vmcnt<0>();   // no load may land in LDS after the tile is left
+                return;
+            }
+        }
     }
 
     // Epilogue.  16x16 accumulator layout: lane l holds column l % 16 and
@@ -502,7 +564,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     }
 }
 
-template <class C>
+template <class C, bool EXIT>
 __global__ void __launch_bounds__(C::kThreads)
 k_search(SearchArgs A)
 {
@@ -515,12 +577,12 @@ k_search(SearchArgs A)
     if (logical >= A.tiles_m * A.tiles_n) return;
     uint32_t tm, tn;
     tile_coords(logical, A.tiles_m, A.tiles_n, tm, tn);
-    search_tile<C>(A, tm, tn, lds);
+    search_tile<C, EXIT>(A, tm, tn, lds);
 }
 
 // Persistent form for many searches: workgroups take (job, tile) items from a
 // device counter until none are left; jobs are stored largest first.
-template <class C>
+template <class C, bool EXIT>
 __global__ void __launch_bounds__(C::kThreads)
 k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t total, uint32_t* __restrict__ counter)
 {
@@ -544,7 +606,7 @@ k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t to
         const SearchArgs A = jobs[lo].A;
         uint32_t tm, tn;
         tile_coords(item - jobs[lo].tile_start, A.tiles_m, A.tiles_n, tm, tn);
-        search_tile<C>(A, tm, tn, lds);
+        search_tile<C, EXIT>(A, tm, tn, lds);
         __syncthreads();   // every wave is done with the ring before its first word is reused
     }
 }
@@ -552,7 +614,7 @@ k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t to
 // One slice of a database scan (serving): item = (haystack tile of the slice,
 // query, needle tile), haystack-tile major so that the workgroups running at
 // the same time share the slice's haystack fragments in L2.
-template <class C>
+template <class C, bool EXIT>
 __global__ void __launch_bounds__(C::kThreads)
 k_search_scan(ScanTable T)
 {
@@ -564,7 +626,7 @@ k_search_scan(ScanTable T)
     while (k + 1 < T.njobs && T.m_start[k + 1] <= r) ++k;
     const uint32_t tm = r - T.m_start[k];
     const uint32_t tn = (T.tile_begin + tnl) % T.db_tiles;
-    search_tile<C>(T.A[k], tm, tn, lds);
+    search_tile<C, EXIT>(T.A[k], tm, tn, lds);
 }
 
 // ------------------------------------------------------- out-of-range images
@@ -784,9 +846,10 @@ hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint
 template <class C>
 static hipError_t launch_search_t(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
                                   const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix,
-                                  hipStream_t s)
+                                  int early_exit, hipStream_t s)
 {
     SearchArgs A;
+    A.early_exit = early_exit ? 1u : 0u;
     A.a_planes = np.planes; A.a_groups = np.ngroups; A.nn = nn;
     A.b_planes = hp.planes; A.b_groups = hp.ngroups; A.nh = nh;
     A.nmax = np.maxabs; A.hmax = hp.maxabs; A.hperm = hp.perm;
@@ -795,19 +858,22 @@ static hipError_t launch_search_t(const SearchPrep& np, uint32_t nn, const Searc
     A.tiles_n = hp.ngroups * kGroup / C::BN;   // every haystack slot, padding included
     const uint32_t total = A.tiles_m * A.tiles_n;
     A.per_xcd = (total + 7) / 8;
-    hipLaunchKernelGGL(k_search<C>, dim3(8 * A.per_xcd), dim3(C::kThreads), (size_t)C::kLds, s, A);
+    if (A.early_exit && thr && !matrix)
+        hipLaunchKernelGGL((k_search<C, true>), dim3(8 * A.per_xcd), dim3(C::kThreads), (size_t)C::kLds, s, A);
+    else
+        hipLaunchKernelGGL((k_search<C, false>), dim3(8 * A.per_xcd), dim3(C::kThreads), (size_t)C::kLds, s, A);
     return hipGetLastError();
 }
 
 hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
                          const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix, int variant,
-                         hipStream_t s)
+                         int early_exit, hipStream_t s)
 {
     if (nn == 0 || nh == 0) return hipSuccess;
     hipError_t e = prepare_search_kernels();
     if (e != hipSuccess) return e;
-    return variant == 1 ? launch_search_t<CfgS>(np, nn, hp, nh, thr, sumsq, rank, matrix, s)
-                        : launch_search_t<Cfg>(np, nn, hp, nh, thr, sumsq, rank, matrix, s);
+    return variant == 1 ? launch_search_t<CfgS>(np, nn, hp, nh, thr, sumsq, rank, matrix, early_exit, s)
+                        : launch_search_t<Cfg>(np, nn, hp, nh, thr, sumsq, rank, matrix, early_exit, s);
 }
 
 hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
@@ -824,7 +890,7 @@ hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t*
 }
 
 hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,
-                                 uint32_t grid, int variant, hipStream_t s)
+                                 uint32_t grid, int variant, int early_exit, hipStream_t s)
 {
     if (njobs == 0) return hipSuccess;
 #define RICI_LAUNCH(...)                                   \
@@ -846,12 +912,18 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
         RICI_LAUNCH(k_true_distance_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
                     T.needles);
     RICI_LAUNCH(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
-    if (T.tiles && variant == 1)
-        RICI_LAUNCH(k_search_batched<CfgS>, dim3(grid), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, jobs, njobs,
-                    (uint32_t)T.tiles, counter);
+    if (T.tiles && variant == 1 && early_exit)
+        RICI_LAUNCH((k_search_batched<CfgS, true>), dim3(grid), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, jobs,
+                    njobs, (uint32_t)T.tiles, counter);
+    else if (T.tiles && variant == 1)
+        RICI_LAUNCH((k_search_batched<CfgS, false>), dim3(grid), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, jobs,
+                    njobs, (uint32_t)T.tiles, counter);
+    else if (T.tiles && early_exit)
+        RICI_LAUNCH((k_search_batched<Cfg, true>), dim3(grid), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, jobs,
+                    njobs, (uint32_t)T.tiles, counter);
     else if (T.tiles)
-        RICI_LAUNCH(k_search_batched<Cfg>, dim3(grid), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, jobs, njobs,
-                    (uint32_t)T.tiles, counter);
+        RICI_LAUNCH((k_search_batched<Cfg, false>), dim3(grid), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, jobs,
+                    njobs, (uint32_t)T.tiles, counter);
     RICI_LAUNCH(k_slow_lists_batched, dim3(njobs), dim3(1024), 0, s, jobs);
     RICI_LAUNCH(k_fallback_batched, dim3(512), dim3(256), 0, s, jobs, njobs);
 #undef RICI_LAUNCH
@@ -863,32 +935,40 @@ hipError_t launch_search_scan(const ScanTable& T, int variant, hipStream_t s)
     if (T.njobs == 0 || T.tile_count == 0) return hipSuccess;
     const uint32_t items = T.m_start[T.njobs] * T.tile_count;
     if (items == 0) return hipSuccess;
-    if (variant == 1)
-        hipLaunchKernelGGL(k_search_scan<CfgS>, dim3(items), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, T);
+    bool early_exit = false;
+    for (uint32_t k = 0; k < T.njobs; ++k) early_exit |= T.A[k].early_exit != 0;
+    if (variant == 1 && early_exit)
+        hipLaunchKernelGGL((k_search_scan<CfgS, true>), dim3(items), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, T);
+    else if (variant == 1)
+        hipLaunchKernelGGL((k_search_scan<CfgS, false>), dim3(items), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, T);
+    else if (early_exit)
+        hipLaunchKernelGGL((k_search_scan<Cfg, true>), dim3(items), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, T);
     else
-        hipLaunchKernelGGL(k_search_scan<Cfg>, dim3(items), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, T);
+        hipLaunchKernelGGL((k_search_scan<Cfg, false>), dim3(items), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, T);
     return hipGetLastError();
 }
 
-template <class C>
+template <class C, bool EXIT>
 static hipError_t raise_lds()
 {
     const int lds = (int)C::kLds;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<C>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<C, EXIT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_batched<C>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_batched<C, EXIT>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_scan<C>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_scan<C, EXIT>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 hipError_t prepare_search_kernels()
 {
     static hipError_t once = [] {
-        hipError_t e = raise_lds<Cfg>();
-        return e != hipSuccess ? e : raise_lds<CfgS>();
+        hipError_t e = raise_lds<Cfg, false>();
+        if (e == hipSuccess) e = raise_lds<Cfg, true>();
+        if (e == hipSuccess) e = raise_lds<CfgS, false>();
+        return e != hipSuccess ? e : raise_lds<CfgS, true>();
     }();
     return once;
 }

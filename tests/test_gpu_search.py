@@ -190,5 +190,56 @@ def test_tuning_rejects_bad_values(ctx):
         ctx.set_tuning("no_such_knob", 1)
     with pytest.raises(RiciError):
         ctx.set_tuning("gen_images_per_group", 3)
+    with pytest.raises(RiciError):
+        ctx.set_tuning("search_early_exit", 2)
     assert ctx.get_tuning("search_tile_m") == 256
     assert ctx.get_tuning("gen_images_per_group") == 2
+
+
+@pytest.fixture()
+def ctx_exit():
+    from paper_2007_02306_amd import Context
+    c = Context(0)
+    assert c.get_tuning("search_early_exit") == 0        # off unless asked for
+    c.set_tuning("search_early_exit", 1)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("tile", [256, 128])
+def test_early_exit_ranks_equal(ctx_exit, tile):
+    """Tiles that leave early (every partial distance of the last phase at or
+    above the needle's threshold) change no rank: near-duplicate needles (small
+    thresholds, most tiles leave) and far ones, every delta range."""
+    ctx_exit.set_tuning("search_tile_m", tile)
+    rng = np.random.default_rng(40 + tile)
+    nh, nn = 1500, 300
+    h = synth.step_images(rng, nh, density=0.04)
+    h[100:140] = synth.step_images(rng, 40, max_delta=60, density=0.04)
+    h[200:203] = synth.step_images(rng, 3, max_delta=300, density=0.02)
+    t = rng.integers(0, nh, nn).astype(np.uint32)
+    t[:4] = [100, 120, 200, 5]
+    n = synth.perturb(rng, h[t], frac=0.002)
+    # the second half are images of other haystack entries: large thresholds
+    n[150:] = synth.perturb(rng, h[rng.integers(0, nh, nn - 150)], frac=0.01)
+    rk, ds = gpu_rank(ctx_exit, n, h, t)
+    ork, ods = oracle.rank(n, h, t)
+    assert np.array_equal(ds, ods) and np.array_equal(rk, ork)
+    assert (rk == 0).sum() > 10 and rk.max() > 0
+
+
+def test_early_exit_clutter_sampled(ctx_exit):
+    """Clutter scene: GPU needle and haystack images, ranks with the early exit
+    against the oracle's ranks of the same images for a sample of needles."""
+    s = synth.config3_clutter()
+    rng = np.random.default_rng(5)
+    hsel = np.sort(rng.choice(s.num_haystack, 3000, replace=False))
+    nsel = np.sort(rng.choice(s.num_needles, 64, replace=False))
+    hay = gpu_images(ctx_exit, s.positions, s.triangles, s.op_positions[hsel], s.op_normals[hsel], s.support_radius)
+    nd = gpu_images(ctx_exit, s.needle_positions, s.needle_triangles, s.needle_op_positions[nsel],
+                    s.needle_op_normals[nsel], s.support_radius)
+    # true matches: the needles' own vertices where sampled, else a seeded image
+    t = rng.integers(0, len(hsel), len(nsel)).astype(np.uint32)
+    rk, ds = gpu_rank(ctx_exit, nd, hay, t)
+    ork, ods = oracle.rank(nd, hay, t)
+    assert np.array_equal(ds, ods) and np.array_equal(rk, ork)

@@ -174,3 +174,33 @@ def test_scan_with_small_tile_and_mixed_tiles_rejected(setup):
     for h in hs:
         ctx._lib.rici_query_destroy(h)
     c128.close()
+
+
+def test_scan_with_early_exit_matches_oracle(setup):
+    """A query made under the early-exit knob scans (in two slices) to the
+    oracle's ranks."""
+    import ctypes
+    import torch
+    from paper_2007_02306_amd import Context, _ptr, check
+    ctx, db, db_host, objects = setup
+    rng = np.random.default_rng(3)
+    req = _request(2, objects, rng, q=200)
+    im_o, fl, rk_o, ds_o = _oracle_ranks(req, db_host)
+    c = Context(0)
+    c.set_tuning("search_early_exit", 1)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    needles, ti = dev_u32(im_o), dev_u32(req.true_index)
+    rank = torch.empty(len(im_o), dtype=torch.int32, device="cuda")
+    dist = torch.empty(len(im_o), dtype=torch.int64, device="cuda")
+    h = ctypes.c_void_p()
+    check(c._lib.rici_query_create(c._h, db._h, _ptr(needles), len(im_o), _ptr(ti), _ptr(rank), _ptr(dist),
+                                   None, 0, s, ctypes.byref(h)))
+    one = (ctypes.c_void_p * 1)(h.value)
+    half = db.tiles // 2
+    check(c._lib.rici_db_scan(c._h, db._h, one, 1, 0, half, s))
+    check(c._lib.rici_db_scan(c._h, db._h, one, 1, half, db.tiles - half, s))
+    c.sync()
+    assert np.array_equal(dist.cpu().numpy(), ds_o)
+    assert np.array_equal(host_u32(rank), rk_o)
+    c._lib.rici_query_destroy(h)
+    c.close()
