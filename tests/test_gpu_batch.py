@@ -106,6 +106,29 @@ def test_batch_small_search_tile(ctx):
     c128.close()
 
 
+def test_batch_with_early_exit(ctx):
+    """A plan recorded with the search's early exit gives the plain path's
+    exact ranks (shuffled true matches: non-trivial thresholds)."""
+    from paper_2007_02306_amd import Context
+    meshes = _meshes(9, 5, 200, 4000)
+    ce = Context(0)
+    ce.set_tuning("search_early_exit", 1)
+    jobs = [dict(positions=dev_f32(p), triangles=dev_u32(t), op_positions=dev_f32(p), op_normals=dev_f32(n),
+                 true_index=dev_u32(ti)) for p, t, n, ti in meshes]
+    b = ce.batch(jobs, 0.3)
+    for _ in range(2):
+        b.run()
+        ce.sync()
+        for k, j in enumerate(jobs):
+            img = ctx.generate(j["positions"], j["triangles"], j["op_positions"], j["op_normals"], 0.3)
+            rk, ds = ctx.distance_rank(img, img, j["true_index"])
+            ctx.sync()
+            assert np.array_equal(host_u32(b.rank[k]), host_u32(rk)), f"mesh {k}"
+            assert np.array_equal(b.true_distance[k].cpu().numpy(), ds.cpu().numpy())
+    b.close()
+    ce.close()
+
+
 def test_batch_empty_and_bad_jobs(ctx):
     import torch
     from paper_2007_02306_amd import RiciError
