@@ -69,6 +69,28 @@ def source_digest(kernel: str) -> str:
     return h.hexdigest()
 
 
+def measured_record(kernel: str):
+    """The committed counter record of `kernel` (see measured_traffic), or None
+    when missing or taken from other sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_union12_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    return rec if rec.get("source_sha256") == source_digest(kernel) else None
+
+
+def measured_busy(kernel: str):
+    """Counter-derived VALU / MFMA busy fractions of `kernel` (rocprofv3 SQ
+    counters on the same workload), or None."""
+    rec = measured_record(kernel)
+    if not rec or not rec.get("busy"):
+        return None
+    b = rec["busy"]
+    return {"valu_busy": b["valu_busy"], "mfma_busy": b["mfma_busy"],
+            "source": "profiles/union12_hbm_counters.md"}
+
+
 def measured_traffic(kernel: str, launches_per_record: int = 1):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/<kernel>_union12_hbm_traffic.json: FETCH_SIZE and WRITE_SIZE per
@@ -496,7 +518,7 @@ def main():
     search_achieved = search_ops / (search_ms * 1e-3) / 1e12
     roof_search = {"bound": "mfma", "achieved": search_achieved, "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
                    "frac": search_achieved / PEAK_INT8_TOPS, "traffic": measured_traffic("k_search"),
-                   "kernel": "k_search",
+                   "counters": measured_busy("k_search"), "kernel": "k_search",
                    "ops_per_launch": search_ops}
 
     cpu = None
@@ -527,7 +549,7 @@ def main():
         gen_achieved = gen_ops / (gen_ms * 1e-3) / 1e12
         roof_gen = {"bound": "alu", "achieved": gen_achieved, "peak": PEAK_ALU_TOPS, "unit": "TFLOP/s",
                     "frac": gen_achieved / PEAK_ALU_TOPS, "traffic": measured_traffic("k_gen"),
-                    "kernel": "k_gen", "ops_per_launch": gen_ops,
+                    "counters": measured_busy("k_gen"), "kernel": "k_gen", "ops_per_launch": gen_ops,
                     "ops_basis": "oracle work counters on the CPU-baseline sample"}
 
     batched = batched_vs_plain(ctx, args.batch_meshes) if args.batch_meshes > 0 else None
