@@ -159,6 +159,7 @@ def cpu_baseline(scene, n_img, n_needles, gpu_images=None, gpu_rank=None):
                   f"haystack images; {t_gen * 1e3:.2f} ms/image + {t_rank * 1e3:.2f} ms/needle on {cores} threads",
         "single_thread": {"value": 1.0 / (t_gen1 + t_rank1), "unit": "RICIs/s",
                           "sample": f"generation of {len(s1)} images + rank of 4 needles on 1 thread"},
+        "host": host_cpu(),
     }
     if gpu_images is not None:
         # parity of the GPU's images on the sample: equal at every pixel the
@@ -176,6 +177,21 @@ def cpu_baseline(scene, n_img, n_needles, gpu_images=None, gpu_rank=None):
             verdict["rank_mismatches"] = int((ork != ranks_gpu[:k]).sum())
         out["parity"] = verdict
     return out, work, sel
+
+
+def host_cpu():
+    """CPU model and logical CPU count of this host (the oracle's threads are
+    capped separately by oracle.threads)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
 
 
 def value_distributions(images):
