@@ -87,8 +87,8 @@ def measured_busy(kernel: str):
     if not rec or not rec.get("busy"):
         return None
     b = rec["busy"]
-    return {"valu_busy": b["valu_busy"], "mfma_busy": b["mfma_busy"],
-            "source": "profiles/union12_hbm_counters.md"}
+    key = "mfma_busy" if kernel == "k_search" else "valu_busy"
+    return {key: b[key], "source": "profiles/union12_hbm_counters.md"}
 
 
 def measured_traffic(kernel: str, launches_per_record: int = 1):
