@@ -335,6 +335,34 @@ __device__ __forceinline__ void tile_coords(uint32_t logical, uint32_t tiles_m, 
     tn = (logical % in_group) / gsz;
 }
 
+// Row bases of the planes a tile streams in each phase (phase 2 reads the
+// needle plane of phase 0).
+struct StageSrc { const int8_t *a0, *a1, *b0, *b1, *b2; };
+
+// Direct global -> LDS loads of stage t into ring slot `slot`: this wave's
+// kLPW fragments, fragment j being fragment wv + j * kWaves of the stage (the
+// GA needle fragments first, then the GB haystack fragments); voff[j] is its
+// group offset plus the lane's 16 bytes.  Values only (no references into the
+// caller), so the selects below stay scalar.
+template <class C>
+__device__ __forceinline__ void issue_stage(int8_t* lds, int slot, int t, int wv, StageSrc src,
+                                            const uint32_t (&voff)[C::kLPW])
+{
+    constexpr int kJA = C::GA / C::kWaves;
+    const int p = t / NB;
+    const size_t roff = (size_t)(t % NB) * kFragBytes;
+    const int8_t* sa = (p == 1 ? src.a1 : src.a0) + roff;
+    const int8_t* sb = (p == 0 ? src.b0 : (p == 1 ? src.b1 : src.b2)) + roff;
+    int8_t* dst = lds + slot * C::kStage;
+#pragma unroll
+    for (int j = 0; j < C::kLPW; ++j) {
+        const int8_t* g = (j < kJA ? sa : sb) + voff[j];
+        __builtin_amdgcn_global_load_lds(
+            (const void __attribute__((address_space(1)))*)g,
+            (void __attribute__((address_space(3)))*)(dst + (wv + j * C::kWaves) * (int)kFragBytes), 16, 0, 0);
+    }
+}
+
 // One BM x BN (needle x haystack) tile: every workgroup thread takes part.
 // EXIT compiles in the early exit of rank mode (taken when A.early_exit is set).
 template <class C, bool EXIT>
@@ -372,32 +400,36 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // Stage s = phase s / 64, image row s % 64.  Phase -> planes: needle planes
     // 0 = -D, 1 = mask; haystack planes 0 = D, 1 = D^2 mod 128, 2 = D^2 div 128.
     // Each wave moves kLPW whole fragments (1 KiB, one instruction each) from
-    // global memory straight into the stage's LDS slot; every address but the
-    // lane's 16-byte offset is wave-uniform.
+    // global memory straight into the stage's LDS slot.  Fragment j of wave w
+    // is fragment w + j * kWaves of the stage (the GA needle groups, then the
+    // GB haystack groups), so whether it comes from the needle or the haystack
+    // planes is known at compile time; its group offset and the lane's 16
+    // bytes are a per-tile 32-bit offset, and per stage only the two
+    // wave-uniform plane-row bases change.
+    static_assert(C::GA % C::kWaves == 0, "needle fragments must split evenly over the waves");
+    constexpr int kJA = C::GA / C::kWaves;             // fragments per wave from the needle planes
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const int f0 = wv * C::kLPW;                       // first fragment of this wave
     const size_t a_ps = (size_t)A.a_groups * kPlaneGroupBytes, b_ps = (size_t)A.b_groups * kPlaneGroupBytes;
     const int8_t* a_base = A.a_planes + (size_t)ga0 * kPlaneGroupBytes;
     const int8_t* b_base = A.b_planes + (size_t)gb0 * kPlaneGroupBytes;
-    const uint32_t lane_off = (uint32_t)lane * 16;
-
-    auto issue = [&](int s) {
-        const int p = s / NB, row = s % NB;
-        const int pa = hq ? ((p == 1) ? 0 : 1) : p;
-        const int pb = hq ? ((p == 0) ? 2 : (p == 1 ? 0 : 1)) : p;
-        const int8_t* srca = a_base + (size_t)pa * a_ps + (size_t)row * kFragBytes;
-        const int8_t* srcb = b_base + (size_t)pb * b_ps + (size_t)row * kFragBytes;
-        int8_t* dst = lds + (s % C::kNS) * C::kStage;
+    uint32_t voff[C::kLPW];
 #pragma unroll
-        for (int j = 0; j < C::kLPW; ++j) {
-            const int f = f0 + j;                      // wave-uniform: scalar branch
-            const int8_t* src = f < C::GA ? srca + (size_t)f * kPlaneGroupBytes
-                                          : srcb + (size_t)(f - C::GA) * kPlaneGroupBytes;
-            __builtin_amdgcn_global_load_lds(
-                (const void __attribute__((address_space(1)))*)(src + lane_off),
-                (void __attribute__((address_space(3)))*)(dst + f * (int)kFragBytes), 16, 0, 0);
-        }
-    };
+    for (int j = 0; j < C::kLPW; ++j) {
+        const int g = wv + j * C::kWaves - (j < kJA ? 0 : C::GA);
+        voff[j] = (uint32_t)g * (uint32_t)kPlaneGroupBytes + (uint32_t)lane * 16;
+    }
+    // planes of phases 0, 1 (, 2): needles -D, mask; haystack D, D^2 mod 128.
+    // With the q phase first (hq): needles mask, -D, mask; haystack
+    // D^2 div 128, D, D^2 mod 128.
+    const int8_t* a_p0 = a_base + (hq ? a_ps : 0);
+    const int8_t* a_p1 = a_base + (hq ? 0 : a_ps);
+    const int8_t* b_p0 = b_base + (hq ? 2 * b_ps : 0);
+    const int8_t* b_p1 = b_base + (hq ? 0 : b_ps);
+    const int8_t* b_p2 = b_base + b_ps;
+    const int last = nstage - 1;
+
+    const StageSrc src{a_p0, a_p1, b_p0, b_p1, b_p2};
+    auto issue = [&](int slot, int t) { issue_stage<C>(lds, slot, min(t, last), wv, src, voff); };
 
     v4i acc[C::kMB][C::kNBK];
 #pragma unroll
@@ -406,8 +438,8 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = v4i{0, 0, 0, 0};
 
     struct Frags { v4i a[C::kMB]; v4i b[C::kNBK]; };
-    auto read_frags = [&](int s, Frags& F) {
-        const int8_t* sA = lds + (s % C::kNS) * C::kStage + lane * 16;
+    auto read_frags = [&](int slot, Frags& F) {
+        const int8_t* sA = lds + slot * C::kStage + lane * 16;
         const int8_t* sB = sA + C::GA * (int)kFragBytes;
 #pragma unroll
         for (int nb = 0; nb < C::kNBK; ++nb)
@@ -420,9 +452,13 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // with stage s+NS-1, then run stage s's MFMAs (fragments fetched one step
     // earlier) interleaved with the LDS reads of stage s+1's fragments, so
     // the reads of one stage overlap the matrix work of the previous one.  The
-    // reads are issued on every step (after the last stage they read a stale
-    // slot and are never used) and only after the first MFMAs, so that the
-    // wait in front of the MFMAs covers only the previous step's reads.
+    // loop is unrolled NS times, so every ring slot is a compile-time
+    // constant.  Loads and reads are issued on every step (past the last
+    // stage the loads repeat the last row into a dead slot and the reads take
+    // a stale slot that is never used), which keeps them in the MFMAs' basic
+    // block; the loads go out after the first MFMA and the reads after the
+    // next ones, so that the wait in front of the MFMAs covers only the
+    // previous step's reads.
     // Early exit (rank mode): in the last phase the partial sums only grow
     // (they add <m, D_h^2> or <m, D_h^2 mod 128>, both >= 0), so once no pair
     // of the tile is below its needle's threshold none will be, and the tile
@@ -469,31 +505,37 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         return __builtin_amdgcn_readfirstlane(any) == 0;
     };
 
-    auto step = [&](int s, const Frags& cur, Frags& nxt) {
-        if (s + 1 < nstage) {
-            // outstanding loads beyond stage s+1: stages s+2 .. s+NS-2
-            if (s + C::kNS - 2 < nstage) wait_vmcnt<(C::kNS - 3) * C::kLPW>();
-            else wait_vmcnt<0>();
-            stage_barrier();
-            if (s + C::kNS - 1 < nstage) issue(s + C::kNS - 1);
-        }
-        read_frags(s + 1, nxt);
+    auto step = [&](int k, int s, const Frags& cur, Frags& nxt) {   // k = s % NS, a literal
+        // outstanding loads beyond stage s+1: stages s+2 .. s+NS-2
+        wait_vmcnt<(C::kNS - 3) * C::kLPW>();
+        stage_barrier();
+        issue((k + C::kNS - 1) % C::kNS, s + C::kNS - 1);
+        read_frags((k + 1) % C::kNS, nxt);
 #pragma unroll
         for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < C::kNBK; ++nb)
                 acc[mb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur.a[mb], cur.b[nb], acc[mb][nb], 0, 0, 0);
-        // schedule: 2 MFMAs, 1 fragment read, repeated; then the rest of the MFMAs
-        constexpr int kReads = C::kMB + C::kNBK;
-        static_assert(2 * kReads <= C::kMB * C::kNBK, "interleave pattern");
+        // schedule: 1 MFMA, the stage loads, then 2 MFMAs : 1 fragment read,
+        // repeated (the first pair has one MFMA when there are only twice as
+        // many MFMAs as reads); then the rest of the MFMAs
+        constexpr int kReads = C::kMB + C::kNBK, kMfma = C::kMB * C::kNBK;
+        static_assert(2 * kReads <= kMfma, "interleave pattern");
+        constexpr bool kTight = 1 + 2 * kReads > kMfma;
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);          // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x020, C::kLPW, 0);    // global -> LDS loads
+        if constexpr (kTight) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
 #pragma unroll
-        for (int i = 0; i < kReads; ++i) {
+        for (int i = kTight ? 1 : 0; i < kReads; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
         }
-        if constexpr (C::kMB * C::kNBK > 2 * kReads)
-            __builtin_amdgcn_sched_group_barrier(0x008, C::kMB * C::kNBK - 2 * kReads, 0);
-        if ((s + 1) % NB == 0 && s + 1 < nstage) {
+        constexpr int kRest = kMfma - 1 - 2 * kReads + (kTight ? 1 : 0);
+        if constexpr (kRest > 0) __builtin_amdgcn_sched_group_barrier(0x008, kRest, 0);
+        if (k == C::kNS - 1 && (s + 1) % NB == 0 && s + 1 < nstage) {
             // end of a phase: scale the partial sum (x64 after q, x2 after -D.D)
             const int sh = (hq && s + 1 == NB) ? 6 : 1;
 #pragma unroll
@@ -503,18 +545,21 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         }
     };
 
-    static_assert(C::kNS >= 3 && C::kNS < 2 * NB, "ring depth");
-#pragma unroll
-    for (int s = 0; s < C::kNS - 1; ++s) issue(s);   // nstage >= 128 > kNS
+    static_assert(C::kNS == 4 && NB % 4 == 0, "the loop below is unrolled for a 4-deep ring");
+    issue(0, 0);
+    issue(1, 1);
+    issue(2, 2);                                     // nstage >= 128 > NS
     wait_vmcnt<(C::kNS - 2) * C::kLPW>();
     stage_barrier();
     Frags fr0, fr1;
     read_frags(0, fr0);
-    for (int s = 0; s < nstage; s += 2) {   // nstage is even
-        step(s, fr0, fr1);
-        step(s + 1, fr1, fr0);
+    for (int s = 0; s < nstage; s += 4) {   // nstage is a multiple of 64
+        step(0, s, fr0, fr1);
+        step(1, s + 1, fr1, fr0);
+        step(2, s + 2, fr0, fr1);
+        step(3, s + 3, fr1, fr0);
         // after 16, 32 and 48 rows of the last phase: vote, publish, decide
-        if (exit_ok && s + 2 > last_phase && (s + 2 - last_phase) % 16 == 0 && s + 2 < nstage) {
+        if (exit_ok && s + 4 > last_phase && (s + 4 - last_phase) % 16 == 0 && s + 4 < nstage) {
             vote();
             __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the votes are written
             stage_barrier();
@@ -524,6 +569,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             }
         }
     }
+    wait_vmcnt<0>();   // the repeated loads of the last steps have landed
 
     // Epilogue.  16x16 accumulator layout: lane l holds column l % 16 and
     // rows 4 * (l / 16) + v of its block, v = 0..3.
