@@ -22,7 +22,9 @@
  *     on demand; growing it synchronises the device.
  *   - Zero-sized work (num_points == 0, num_needles == 0) is a valid no-op.
  *
- * Image layout: uint32 [N][64][64], row-major.  Row r is the circle plane at
+ * Image layout: uint32 [N][64][64], row-major; every image array (generation
+ * output, needles, haystack, database) must start on a 16-byte boundary
+ * (RICI_ERR_INVALID otherwise).  Row r is the circle plane at
  * height beta_r = -R/2 + (r + 1/2) R/64 along the Central Axis, column c the
  * circle of radius rho_c = (c + 1/2) R/64, so pixel (r, c) counts the points
  * where that circle meets the scene's triangles (Sec. 3.1; the square support

@@ -122,6 +122,9 @@ int ensure_ws(rici_ctx* h, size_t bytes)
     return RICI_OK;
 }
 
+// image arrays are read and written with 16-byte vector accesses
+bool misaligned(const void* p) { return ((uintptr_t)p & 15u) != 0; }
+
 bool overlaps(const void* a, size_t na, const void* b, size_t nb)
 {
     if (!a || !b || na == 0 || nb == 0) return false;
@@ -220,6 +223,7 @@ int rici_generate(rici_handle h, const float* positions, uint32_t num_vertices, 
         return fail(RICI_ERR_INVALID, "rici_generate: NULL oriented-point or output pointer");
     if (num_triangles > 0 && (!triangles || !positions || num_vertices == 0))
         return fail(RICI_ERR_INVALID, "rici_generate: NULL mesh pointer or no vertices");
+    if (misaligned(out_images)) return fail(RICI_ERR_INVALID, "rici_generate: out_images is not 16-byte aligned");
     const size_t out_bytes = (size_t)num_points * rici::NPIX * sizeof(uint32_t);
     if (overlaps(out_images, out_bytes, positions, (size_t)num_vertices * 12) ||
         overlaps(out_images, out_bytes, triangles, (size_t)num_triangles * 12) ||
@@ -303,6 +307,8 @@ int check_search_args(const char* fn, const uint32_t* needles, uint32_t nn, cons
     if (nh == 0 && nn > 0) return fail(RICI_ERR_INVALID, "%s: empty haystack", fn);
     if (nh > 0 && !hay) return fail(RICI_ERR_INVALID, "%s: NULL haystack", fn);
     if (nn >= (1u << 31) || nh >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "%s: more than 2^31 images", fn);
+    if ((nn > 0 && misaligned(needles)) || (nh > 0 && misaligned(hay)))
+        return fail(RICI_ERR_INVALID, "%s: image arrays must be 16-byte aligned", fn);
     return RICI_OK;
 }
 
@@ -502,6 +508,10 @@ bool job_ok(const rici_mesh_job& j, uint32_t k)
     if (j.num_points == 0) return true;
     if (!j.op_positions || !j.op_normals || !j.out_images) {
         fail(RICI_ERR_INVALID, "rici_batch_create: job %u has a NULL oriented-point or image pointer", k);
+        return false;
+    }
+    if (misaligned(j.out_images)) {
+        fail(RICI_ERR_INVALID, "rici_batch_create: job %u: out_images is not 16-byte aligned", k);
         return false;
     }
     if (j.num_triangles > 0 && (!j.triangles || !j.positions || j.num_vertices == 0)) {
@@ -796,6 +806,7 @@ int rici_db_create(rici_handle h, const uint32_t* images, uint32_t num_images, v
     if (!h) return fail(RICI_ERR_INVALID, "rici_db_create: NULL handle");
     if (num_images == 0 || !images) return fail(RICI_ERR_INVALID, "rici_db_create: empty database");
     if (num_images >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "rici_db_create: more than 2^31 images");
+    if (misaligned(images)) return fail(RICI_ERR_INVALID, "rici_db_create: images are not 16-byte aligned");
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e = rici::prepare_search_kernels();
@@ -860,6 +871,7 @@ int rici_query_create(rici_handle h, rici_db db, const uint32_t* needles, uint32
     if (num_needles == 0 || !needles || !true_index || !out_rank)
         return fail(RICI_ERR_INVALID, "rici_query_create: empty query or NULL pointer");
     if (num_needles >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "rici_query_create: too many needles");
+    if (misaligned(needles)) return fail(RICI_ERR_INVALID, "rici_query_create: needles are not 16-byte aligned");
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     const QueryLayout L = query_layout(num_needles, db->n);

@@ -181,34 +181,44 @@ k_copy_u32(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, uint32_
     if (i < n) dst[i] = src[i];
 }
 
+// One workgroup of 1024 threads walks the images in rounds of 1024
+// consecutive ones (coalesced loads, the next round prefetched); a workgroup
+// scan of the small/other flags gives each image its slot in image order.
 __device__ void hay_assign_block(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslots,
                                  uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs)
 {
-    __shared__ uint32_t wsum[16][2];
+    __shared__ uint32_t wsum[2][16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t chunk = (n + 1023) / 1024;
-    const uint32_t lo = min((uint32_t)tid * chunk, n), hi = min(lo + chunk, n);
-    uint32_t cs = 0, co = 0;
-    for (uint32_t i = lo; i < hi; ++i) {
-        if (maxabs_img[i] <= kSmallD) ++cs; else ++co;
-    }
-    // exclusive prefix over threads: wavefront scans, then the 16 wave totals
-    uint32_t is = cs, io = co;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint32_t base_s = 0, base_o = 0;   // small / other images of the earlier rounds
+    uint32_t m_next = (uint32_t)tid < n ? maxabs_img[tid] : 0u;
+    int par = 0;
+    for (uint32_t r0 = 0; r0 < n; r0 += 1024, par ^= 1) {
+        const uint32_t i = r0 + (uint32_t)tid;
+        const bool live = i < n;
+        const uint32_t m = m_next;
+        if (i + 1024 < n) m_next = maxabs_img[i + 1024];
+        const bool small = live && m <= kSmallD;
+        const uint64_t bs = __ballot(small);
+        if (lane == 0) wsum[par][wave] = (uint32_t)__popcll(bs);
+        __syncthreads();   // one barrier a round: the two halves of wsum alternate
+        uint32_t ps = 0, tot = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t a = __shfl_up(is, o, 64), b = __shfl_up(io, o, 64);
-        if (lane >= o) { is += a; io += b; }
-    }
-    if (lane == 63) { wsum[wave][0] = is; wsum[wave][1] = io; }
-    __syncthreads();
-    uint32_t bs = 0, bo = 0;
-    for (int w = 0; w < wave; ++w) { bs += wsum[w][0]; bo += wsum[w][1]; }
-    uint32_t ps = bs + is - cs, po = bo + io - co;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t m = maxabs_img[i];
-        const uint32_t slot = m <= kSmallD ? ps++ : nslots - 1 - po++;
-        perm[slot] = i;
-        maxabs[slot] = m;
+        for (int w = 0; w < 16; ++w) {
+            const uint32_t x = wsum[par][w];
+            ps += w < wave ? x : 0u;
+            tot += x;
+        }
+        const uint32_t small_before = ps + (uint32_t)__popcll(bs & below);   // in this round
+        if (live) {
+            const uint32_t slot = small ? base_s + small_before
+                                        : nslots - 1 - (base_o + (uint32_t)tid - small_before);
+            perm[slot] = i;
+            maxabs[slot] = m;
+        }
+        const uint32_t cnt = min(1024u, n - r0);
+        base_s += tot;
+        base_o += cnt - tot;
     }
 }
 
@@ -221,27 +231,33 @@ k_hay_assign(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslot
 
 // ------------------------------------------------------------ exact int64 CRD
 
-// CRD(n, h) by Eq. 7 for one pair, summed by one wavefront: lane = column.
+// CRD(n, h) by Eq. 7 for one pair, summed by one wavefront in int64.  Each
+// load instruction covers four rows: lane l holds columns 4 (l % 16) ..
+// 4 (l % 16) + 3 of row 4 it + l / 16, and takes the column to their left from
+// lane l - 1 (column 0 of a row has no delta and no term).
 __device__ __forceinline__ int64_t crd_wave(const uint32_t* __restrict__ nimg, const uint32_t* __restrict__ himg,
                                             int lane)
 {
+    const uint4* a4 = reinterpret_cast<const uint4*>(nimg);
+    const uint4* b4 = reinterpret_cast<const uint4*>(himg);
+    const bool first = (lane & 15) == 0;
+    auto term = [](uint32_t n1, uint32_t n0, uint32_t h1, uint32_t h0) -> int64_t {
+        const int64_t dn = (int64_t)n1 - (int64_t)n0, dh = (int64_t)h1 - (int64_t)h0;
+        return dn != 0 ? (dn - dh) * (dn - dh) : 0;   // only the needle's non-zero deltas count
+    };
     int64_t s = 0;
-    for (int r = 0; r < NB; ++r) {
-        const int64_t a = nimg[r * NB + lane], b = himg[r * NB + lane];
-        const int64_t ap = __shfl_up(a, 1, 64), bp = __shfl_up(b, 1, 64);
-        if (lane > 0) {
-            const int64_t dn = a - ap, dh = b - bp;
-            if (dn != 0) s += (dn - dh) * (dn - dh);
-        }
+#pragma unroll 4
+    for (int it = 0; it < NB / 4; ++it) {
+        const uint4 a = a4[it * 64 + lane], b = b4[it * 64 + lane];
+        const uint32_t al = __shfl_up(a.w, 1, 64), bl = __shfl_up(b.w, 1, 64);
+        if (!first) s += term(a.x, al, b.x, bl);
+        s += term(a.y, a.x, b.y, b.x) + term(a.z, a.y, b.z, b.y) + term(a.w, a.z, b.w, b.z);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     return s;
 }
 
-// d*_i = CRD(n_i, h_true(i)); MFMA threshold thr_i = d*_i - |D_n|^2 (clamped;
-// INT_MIN disables the MFMA count for needles outside the int8 range and for a
-// bad true index); rank zeroed.
 __device__ void true_distance_one(const uint32_t* __restrict__ needles, const uint32_t* __restrict__ hay,
                                   uint32_t nh, const uint32_t* __restrict__ true_idx,
                                   const int64_t* __restrict__ sumsq, const uint32_t* __restrict__ nmax,
@@ -679,26 +695,43 @@ k_search_scan(ScanTable T)
 
 // lists[0] = #needles with |D| > 127, lists[1] = #haystack images with
 // |D| > 127, then the needle ids (nn slots) and the haystack ids (nh slots).
-__device__ void slow_lists_block(const uint32_t* __restrict__ nmax, uint32_t nn, const uint32_t* __restrict__ hmax,
-                                 uint32_t nh, uint32_t* __restrict__ lists)
+// Order within a list is free (each entry is one independent unit of work).
+// k_slow_reset clears the two counts; k_slow_lists takes one entry per thread
+// (needles first, then the haystack) and appends by one atomic per wave.
+__global__ void __launch_bounds__(64)
+k_slow_reset(uint32_t* __restrict__ lists)
 {
-    __shared__ uint32_t cn, ch;
-    if (threadIdx.x == 0) { cn = 0; ch = 0; }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nn; i += blockDim.x)
-        if (nmax[i] > kSlow) lists[2 + atomicAdd(&cn, 1u)] = i;
-    for (uint32_t j = threadIdx.x; j < nh; j += blockDim.x)
-        if (hmax[j] > kSlow) lists[2 + (size_t)nn + atomicAdd(&ch, 1u)] = j;
-    __syncthreads();
-    if (threadIdx.x == 0) { lists[0] = cn; lists[1] = ch; }
-    __syncthreads();
+    if (threadIdx.x < 2) lists[threadIdx.x] = 0u;
 }
 
-__global__ void __launch_bounds__(1024)
+__device__ __forceinline__ void slow_lists_entry(const uint32_t* __restrict__ nmax, uint32_t nn,
+                                                 const uint32_t* __restrict__ hmax, uint32_t nh,
+                                                 uint32_t* __restrict__ lists, uint64_t x)
+{
+    // x < nn: needle x; nn <= x < nn + nh: haystack image x - nn.  A wave may
+    // straddle the two lists: each side gets its own ballot.
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const bool is_n = x < nn, is_h = !is_n && x < (uint64_t)nn + nh;
+    const bool slow_n = is_n && nmax[x] > kSlow;
+    const bool slow_h = is_h && hmax[x - nn] > kSlow;
+    const uint64_t bn = __ballot(slow_n), bh = __ballot(slow_h);
+    uint32_t base_n = 0, base_h = 0;
+    if (lane == 0) {
+        if (bn) base_n = atomicAdd(lists + 0, (uint32_t)__popcll(bn));
+        if (bh) base_h = atomicAdd(lists + 1, (uint32_t)__popcll(bh));
+    }
+    base_n = __shfl(base_n, 0, 64);
+    base_h = __shfl(base_h, 0, 64);
+    if (slow_n) lists[2 + base_n + __popcll(bn & below)] = (uint32_t)x;
+    if (slow_h) lists[2 + (size_t)nn + base_h + __popcll(bh & below)] = (uint32_t)(x - nn);
+}
+
+__global__ void __launch_bounds__(256)
 k_slow_lists(const uint32_t* __restrict__ nmax, uint32_t nn, const uint32_t* __restrict__ hmax, uint32_t nh,
              uint32_t* __restrict__ lists)
 {
-    slow_lists_block(nmax, nn, hmax, nh, lists);
+    slow_lists_entry(nmax, nn, hmax, nh, lists, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Every (needle, haystack) pair with an out-of-range image, by Eq. 7 in int64.
@@ -821,7 +854,14 @@ __global__ void __launch_bounds__(1024)
 k_slow_lists_batched(const SearchJob* __restrict__ jobs)
 {
     const SearchJob& J = jobs[blockIdx.x];
-    slow_lists_block(J.np.maxabs, J.A.nn, J.hp.maxabs_img, J.A.nh, J.lists);
+    if (threadIdx.x < 2) {
+        atomicExch(J.lists + threadIdx.x, 0u);
+        __threadfence();   // the counts are zero before any wave of the block adds to them
+    }
+    __syncthreads();
+    const uint64_t total = (uint64_t)J.A.nn + J.A.nh;
+    for (uint64_t x0 = 0; x0 < total; x0 += blockDim.x)   // uniform bound: every lane takes part in the ballots
+        slow_lists_entry(J.np.maxabs, J.A.nn, J.hp.maxabs_img, J.A.nh, J.lists, x0 + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256)
@@ -927,8 +967,13 @@ hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t*
                            uint32_t* rank, int64_t* matrix, uint32_t* lists, hipStream_t s)
 {
     if (nn == 0 || nh == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_slow_lists, dim3(1), dim3(1024), 0, s, nmax, nn, hmax, nh, lists);
+    hipLaunchKernelGGL(k_slow_reset, dim3(1), dim3(64), 0, s, lists);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint64_t entries = (uint64_t)nn + nh;   // < 2^32
+    hipLaunchKernelGGL(k_slow_lists, dim3((uint32_t)((entries + 255) / 256)), dim3(256), 0, s, nmax, nn, hmax, nh,
+                       lists);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fallback, dim3(512), dim3(256), 0, s, needles, nn, hay, nh, nmax, lists, dstar, rank,
                        matrix);

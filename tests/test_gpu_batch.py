@@ -129,6 +129,49 @@ def test_batch_with_early_exit(ctx):
     ce.close()
 
 
+def _stacked_mesh(seed, copies):
+    """A small object with one of its triangles repeated `copies` times: the
+    images near that triangle step by more than 127 between neighbouring
+    radii, so their pairs take the exact int64 fallback."""
+    rng = np.random.default_rng(seed)
+    m, _ = synth.configs.random_object(rng, 200)
+    pos = m.positions.astype(np.float32)
+    tri = np.concatenate([m.triangles, np.repeat(m.triangles[:1], copies, axis=0)])
+    nrm = synth.vertex_normals(pos, tri)
+    ti = rng.permutation(pos.shape[0]).astype(np.uint32)
+    return pos, tri, nrm, ti
+
+
+def test_batch_out_of_range_deltas(ctx):
+    """Meshes whose images have |D| > 127: the batched plan's exact fallback
+    (its per-job lists of out-of-range images) gives the plain path's ranks
+    and distances, and the plain path's ranks equal the oracle's."""
+    meshes = [_stacked_mesh(21, 160), _meshes(22, 1, 300, 2000)[0], _stacked_mesh(23, 140)]
+    jobs = [dict(positions=dev_f32(p), triangles=dev_u32(t), op_positions=dev_f32(p), op_normals=dev_f32(n),
+                 true_index=dev_u32(ti)) for p, t, n, ti in meshes]
+    b = ctx.batch(jobs, 0.3)
+    slow_seen = 0
+    for rep in range(2):
+        b.run()
+        ctx.sync()
+        for k, (j, (pos, tri, nrm, ti)) in enumerate(zip(jobs, meshes)):
+            img = ctx.generate(j["positions"], j["triangles"], j["op_positions"], j["op_normals"], 0.3)
+            rk, ds = ctx.distance_rank(img, img, j["true_index"])
+            ctx.sync()
+            h = host_u32(img)
+            assert np.array_equal(host_u32(b.images[k]), h), f"mesh {k} images"
+            assert np.array_equal(host_u32(b.rank[k]), host_u32(rk)), f"replay {rep} mesh {k} ranks"
+            assert np.array_equal(b.true_distance[k].cpu().numpy(), ds.cpu().numpy())
+            if rep == 0:
+                d = np.diff(h.astype(np.int64), axis=2)
+                slow_seen += int((np.abs(d).max(axis=(1, 2)) > 127).sum())
+                ork, ods = oracle.rank(h, h, ti)
+                assert np.array_equal(host_u32(rk), ork) and np.array_equal(ds.cpu().numpy(), ods), f"mesh {k}"
+    say(f"  images with |D| > 127: {slow_seen}")
+    assert slow_seen > 0
+    b.close()
+
+
 def test_batch_empty_and_bad_jobs(ctx):
     import torch
     from paper_2007_02306_amd import RiciError

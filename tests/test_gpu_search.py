@@ -155,6 +155,27 @@ def test_bad_true_index_and_empty(ctx):
                           dev_u32(np.zeros(2, np.uint32)))
 
 
+def test_misaligned_images_rejected(ctx):
+    """Image arrays are read with 16-byte vector loads: a pointer off that
+    boundary is an argument error reported before any work is enqueued."""
+    import torch
+    from paper_2007_02306_amd import RiciError
+    rng = np.random.default_rng(5)
+    h = dev_u32(synth.step_images(rng, 4))
+    flat = torch.zeros(4 * 4096 + 1, dtype=torch.int32, device="cuda")
+    flat[1:].copy_(h.reshape(-1))
+    off = flat[1:].view(4, 64, 64)                 # 4 bytes past a 16-byte boundary
+    t = dev_u32(np.arange(4, dtype=np.uint32))
+    with pytest.raises(RiciError) as e:
+        ctx.distance_rank(off, h, t)
+    assert "16-byte" in str(e.value)
+    with pytest.raises(RiciError):
+        ctx.distance_rank(h, off, t)
+    rk, _ = ctx.distance_rank(h, h, t)             # the handle stays usable
+    ctx.sync()
+    assert rk.cpu().numpy().tolist() == [0, 0, 0, 0]
+
+
 @pytest.fixture()
 def ctx128():
     from paper_2007_02306_amd import Context
