@@ -532,25 +532,37 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
 #pragma unroll
             for (int nb = 0; nb < C::kNBK; ++nb)
                 acc[mb][nb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur.a[mb], cur.b[nb], acc[mb][nb], 0, 0, 0);
-        // schedule: 1 MFMA, the stage loads, then 2 MFMAs : 1 fragment read,
-        // repeated (the first pair has one MFMA when there are only twice as
-        // many MFMAs as reads); then the rest of the MFMAs
+        // schedule: 1 MFMA, the stage loads, then the fragment reads spread
+        // over the MFMAs: 3 reads after every 6 MFMAs when the counts allow
+        // (measured best for the 256 x 256 tile), else 1 read after every 2
+        // (the first pair has one MFMA when there are only twice as many
+        // MFMAs as reads); then the rest of the MFMAs
         constexpr int kReads = C::kMB + C::kNBK, kMfma = C::kMB * C::kNBK;
         static_assert(2 * kReads <= kMfma, "interleave pattern");
-        constexpr bool kTight = 1 + 2 * kReads > kMfma;
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);          // MFMA
         __builtin_amdgcn_sched_group_barrier(0x020, C::kLPW, 0);    // global -> LDS loads
-        if constexpr (kTight) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        }
+        if constexpr (kReads % 3 == 0 && 1 + 2 * kReads <= kMfma) {
 #pragma unroll
-        for (int i = kTight ? 1 : 0; i < kReads; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+            for (int i = 0; i < kReads / 3; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);   // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);   // LDS read
+            }
+            constexpr int kRest = kMfma - 1 - 2 * kReads;
+            if constexpr (kRest > 0) __builtin_amdgcn_sched_group_barrier(0x008, kRest, 0);
+        } else {
+            constexpr bool kTight = 1 + 2 * kReads > kMfma;
+            if constexpr (kTight) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+#pragma unroll
+            for (int i = kTight ? 1 : 0; i < kReads; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+            }
+            constexpr int kRest = kMfma - 1 - 2 * kReads + (kTight ? 1 : 0);
+            if constexpr (kRest > 0) __builtin_amdgcn_sched_group_barrier(0x008, kRest, 0);
         }
-        constexpr int kRest = kMfma - 1 - 2 * kReads + (kTight ? 1 : 0);
-        if constexpr (kRest > 0) __builtin_amdgcn_sched_group_barrier(0x008, kRest, 0);
         if (k == C::kNS - 1 && (s + 1) % NB == 0 && s + 1 < nstage) {
             // end of a phase: scale the partial sum (x64 after q, x2 after -D.D)
             const int sh = (hq && s + 1 == NB) ? 6 : 1;
@@ -642,18 +654,36 @@ k_search(SearchArgs A)
     search_tile<C, EXIT>(A, tm, tn, lds);
 }
 
-// Persistent form for many searches: workgroups take (job, tile) items from a
-// device counter until none are left; jobs are stored largest first.
+// Persistent form for many searches.  The (job, tile) items (jobs stored
+// largest first) are split into 8 contiguous ranges, one per XCD: workgroup
+// ids are dealt to the XCDs round robin, so the tiles that run at the same
+// time on one XCD are neighbours in the tile order and share fragments in its
+// L2.  A workgroup takes items from its own XCD's counter, then from the
+// others' once its range is used up.
 template <class C, bool EXIT>
 __global__ void __launch_bounds__(C::kThreads)
-k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t total, uint32_t* __restrict__ counter)
+k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t total, uint32_t* __restrict__ counters)
 {
     extern __shared__ __align__(16) int8_t lds[];
     // the ring takes all of the LDS: the item is broadcast through its first
     // word, which no wave reads or fills between two tiles
     volatile uint32_t* s_item = reinterpret_cast<volatile uint32_t*>(lds);
+    const uint32_t xcd = blockIdx.x & 7u, per = (total + 7) / 8;
+    uint32_t visited = 0;   // ranges used up (thread 0 only)
     for (;;) {
-        if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) {
+            uint32_t item = total;
+            while (visited < 8) {
+                const uint32_t x = (xcd + visited) & 7u;
+                const uint32_t k = atomicAdd(counters + x, 1u);
+                if (k < per && x * per + k < total) {
+                    item = x * per + k;
+                    break;
+                }
+                ++visited;
+            }
+            *s_item = item;
+        }
         __syncthreads();
         // the item is the same in every lane: keep it (and the job's
         // arguments loaded through it) in scalar registers
@@ -877,6 +907,7 @@ k_fallback_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
 }
 
 __global__ void k_zero_counter(uint32_t* __restrict__ c) { if (threadIdx.x == 0) *c = 0u; }
+__global__ void k_zero_counters8(uint32_t* __restrict__ c) { if (threadIdx.x < 8) c[threadIdx.x] = 0u; }
 
 }  // namespace
 
@@ -1002,7 +1033,7 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
     if (T.needles)
         RICI_LAUNCH(k_true_distance_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
                     T.needles);
-    RICI_LAUNCH(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
+    RICI_LAUNCH(k_zero_counters8, dim3(1), dim3(64), 0, s, counter);
     if (T.tiles && variant == 1 && early_exit)
         RICI_LAUNCH((k_search_batched<CfgS, true>), dim3(grid), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, jobs,
                     njobs, (uint32_t)T.tiles, counter);
