@@ -224,6 +224,13 @@ int rici_timing_get(rici_handle h, const char* kernel, double* total_ms, uint64_
  *   "gen_images_per_group"  images sharing one generation workgroup (and its
  *                    triangle stream): 2 (default) or 4.  Read by
  *                    rici_generate and rici_batch_create (fixed into the plan).
+ *   "gen_sort_triangles"  order in which the triangle preparation stores a
+ *                    mesh's triangles for the generation kernel's culls: 0 mesh
+ *                    order, 1 Morton order of their bounding-box centres within
+ *                    blocks of 4096 (compact runs of 64 whose bounding spheres
+ *                    miss more images), 2 (default) Morton order for meshes of
+ *                    at least 131072 triangles.  Read by rici_generate and
+ *                    rici_batch_create (per mesh, fixed into the plan).
  *   "search_early_exit"  0 (default) or 1: in rank mode a search tile stops
  *                    once every partial distance of its last contraction phase
  *                    (where partial sums only grow) has reached its needle's

@@ -26,6 +26,7 @@ struct rici_ctx {
     bool timing = false;
     int search_variant = 0;         // search tile: 0 = 256 x 256, 1 = 128 x 256
     int gen_group = 2;              // images per generation workgroup: 2 or 4
+    int gen_sort = 2;               // triangle order: 0 mesh, 1 Morton, 2 Morton for large meshes
     int early_exit = 0;             // search tiles may stop once no pair can count (rank mode)
     std::vector<TimedLaunch> launches;
     std::vector<hipEvent_t> free_events;
@@ -243,7 +244,7 @@ int rici_generate(rici_handle h, const float* positions, uint32_t num_vertices, 
     float4* clusters = (float4*)((char*)h->ws + cull_bytes);
     float4* verts = (float4*)((char*)h->ws + cull_bytes + clus_bytes);
     hipError_t e = timed(h, "gen_prep", s, [&] {
-        hipError_t e1 = rici::launch_gen_prep(positions, num_vertices, triangles, num_triangles, cull, verts,
+        hipError_t e1 = rici::launch_gen_prep(positions, num_vertices, triangles, num_triangles, h->gen_sort, cull, verts,
                                               h->d_err, s);
         return e1 != hipSuccess ? e1 : rici::launch_gen_clusters(cull, num_triangles, clusters, s);
     });
@@ -414,6 +415,12 @@ int rici_set_tuning(rici_handle h, const char* key, int value)
         h->early_exit = value;
         return RICI_OK;
     }
+    if (strcmp(key, "gen_sort_triangles") == 0) {
+        if (value < 0 || value > 2)
+            return fail(RICI_ERR_INVALID, "rici_set_tuning: gen_sort_triangles must be 0, 1 or 2 (got %d)", value);
+        h->gen_sort = value;
+        return RICI_OK;
+    }
     if (strcmp(key, "gen_images_per_group") == 0) {
         if (value != 4 && value != 2)
             return fail(RICI_ERR_INVALID, "rici_set_tuning: gen_images_per_group must be 4 or 2 (got %d)", value);
@@ -438,6 +445,10 @@ int rici_get_tuning(rici_handle h, const char* key, int* value)
     }
     if (strcmp(key, "search_early_exit") == 0) {
         *value = h->early_exit;
+        return RICI_OK;
+    }
+    if (strcmp(key, "gen_sort_triangles") == 0) {
+        *value = h->gen_sort;
         return RICI_OK;
     }
     if (strcmp(key, "search_tile_m") == 0) {
@@ -627,7 +638,7 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
 
     // ---- generation table
     std::vector<rici::GenJob> gj(gorder.size());
-    uint64_t tri = 0, chunks = 0;
+    uint64_t blocks = 0, chunks = 0;
     uint32_t items = 0;
     for (size_t i = 0; i < gorder.size(); ++i) {
         const rici_mesh_job& j = jobs[gorder[i]];
@@ -638,8 +649,9 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
         J.cull = (float4*)p; p += align256((size_t)j.num_triangles * rici::kTriCullBytes);
         J.clusters = (float4*)p; p += align256(((size_t)j.num_triangles + 63) / 64 * rici::kTriCullBytes);
         J.verts = (float4*)p;
-        J.tri_start = tri; J.chunk_start = chunks; J.item_start = items;
-        tri += j.num_triangles;
+        J.block_start = blocks; J.chunk_start = chunks; J.item_start = items;
+        J.sort = rici::gen_sort_wanted(h->gen_sort, j.num_triangles) ? 1 : 0;
+        blocks += (j.num_triangles + rici::kGenSortBlock - 1) / rici::kGenSortBlock;
         chunks += (j.num_triangles + 63) / 64;
         items += (j.num_points + G - 1) / G;
     }
@@ -706,7 +718,7 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     hipError_t le = hipSuccess;
     if (e == hipSuccess) {
-        le = rici::launch_gen_batched(d_gjobs, (uint32_t)gj.size(), tri, chunks, items, support_radius, d_counters,
+        le = rici::launch_gen_batched(d_gjobs, (uint32_t)gj.size(), blocks, chunks, items, support_radius, d_counters,
                                       h->d_err, gen_grid, gen_group, cs);
         if (le == hipSuccess)
             le = rici::launch_search_batched(d_sjobs, (uint32_t)sj.size(), T, d_counters + 1, grid, variant,

@@ -43,12 +43,13 @@ __device__ __forceinline__ bool finite3(float a, float b, float c)
 
 // ------------------------------------------------------------- triangle prep
 
+// Triangle `src` of the mesh, stored at slot `t` of the cull and vertex arrays.
 __device__ __forceinline__ void prep_triangle(const float* __restrict__ pos, uint32_t nv,
-                                              const uint32_t* __restrict__ tri, uint32_t t,
+                                              const uint32_t* __restrict__ tri, uint32_t src, uint32_t t,
                                               float4* __restrict__ cull, float4* __restrict__ verts,
                                               uint32_t* __restrict__ err)
 {
-    const uint32_t i0 = tri[3 * (size_t)t], i1 = tri[3 * (size_t)t + 1], i2 = tri[3 * (size_t)t + 2];
+    const uint32_t i0 = tri[3 * (size_t)src], i1 = tri[3 * (size_t)src + 1], i2 = tri[3 * (size_t)src + 2];
     float4 dead = make_float4(0.f, 0.f, 0.f, -INFINITY);   // never passes the cull
     if (i0 >= nv || i1 >= nv || i2 >= nv) {
         atomicOr(err, 1u);
@@ -82,12 +83,145 @@ __device__ __forceinline__ void prep_triangle(const float* __restrict__ pos, uin
     cull[t] = make_float4(mx, my, mz, r);
 }
 
+// 30-bit Morton code of a point quantised to 10 bits per axis
+__device__ __forceinline__ uint32_t spread10(uint32_t v)
+{
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// One workgroup (1024 threads) stores triangles b * 4096 .. b * 4096 + 4095 of
+// the mesh in Morton order of their bounding-box centres within the block's
+// box, so that the runs of 64 consecutive triangles tested together by k_gen
+// are compact patches with small bounding spheres (the order of the triangles
+// never changes a count: every triangle adds its crossings to the same
+// integer image).  Keys: Morton code, then 2^30 for triangles with a bad index
+// or a non-finite vertex (stored as never-passing spheres), then padding past
+// the end of the mesh; the block index in the low word makes them unique.
+// With sort false the block is stored in mesh order.
+__device__ __forceinline__ void prep_sorted_block(const float* __restrict__ pos, uint32_t nv, const uint32_t* __restrict__ tri,
+                                  uint32_t nt, uint32_t b, bool sort, float4* __restrict__ cull,
+                                  float4* __restrict__ verts, uint32_t* __restrict__ err)
+{
+    constexpr int kT = 1024, kPer = kGenSortBlock / kT;
+    __shared__ uint64_t key[kGenSortBlock];
+    __shared__ float box[2][16][3];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t base = b * kGenSortBlock;
+    const uint32_t n_in = min(nt - base, kGenSortBlock);
+    if (!sort) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const uint32_t j = (uint32_t)(q * kT + tid);
+            if (j < n_in) prep_triangle(pos, nv, tri, base + j, base + j, cull, verts, err);
+        }
+        return;
+    }
+
+    float cx[kPer], cy[kPer], cz[kPer];
+    int state[kPer];                        // 0 live, 1 bad or non-finite, 2 past the end
+    float lo[3] = { INFINITY, INFINITY, INFINITY }, hi[3] = { -INFINITY, -INFINITY, -INFINITY };
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const uint32_t j = (uint32_t)(q * kT + tid);
+        cx[q] = cy[q] = cz[q] = 0.f;
+        state[q] = 2;
+        if (j < n_in) {
+            const uint32_t t = base + j;
+            const uint32_t i0 = tri[3 * (size_t)t], i1 = tri[3 * (size_t)t + 1], i2 = tri[3 * (size_t)t + 2];
+            state[q] = 1;
+            if (i0 < nv && i1 < nv && i2 < nv) {
+                const float* a = pos + 3 * (size_t)i0;
+                const float* bb = pos + 3 * (size_t)i1;
+                const float* c = pos + 3 * (size_t)i2;
+                const float x = (fminf(a[0], fminf(bb[0], c[0])) + fmaxf(a[0], fmaxf(bb[0], c[0]))) * 0.5f;
+                const float y = (fminf(a[1], fminf(bb[1], c[1])) + fmaxf(a[1], fmaxf(bb[1], c[1]))) * 0.5f;
+                const float z = (fminf(a[2], fminf(bb[2], c[2])) + fmaxf(a[2], fmaxf(bb[2], c[2]))) * 0.5f;
+                if (finite3(x, y, z)) {
+                    cx[q] = x; cy[q] = y; cz[q] = z;
+                    state[q] = 0;
+                    lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
+                    hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
+                }
+            }
+        }
+    }
+    // the block's box of live centres
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fminf(lo[k], __shfl_xor(lo[k], o, 64));
+            hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o, 64));
+        }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { box[0][wave][k] = lo[k]; box[1][wave][k] = hi[k]; }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = box[0][0][k]; hi[k] = box[1][0][k];
+        for (int w = 1; w < kT / 64; ++w) { lo[k] = fminf(lo[k], box[0][w][k]); hi[k] = fmaxf(hi[k], box[1][w][k]); }
+    }
+    float sc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sc[k] = 1023.0f / fmaxf(hi[k] - lo[k], 1e-30f);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const uint32_t j = (uint32_t)(q * kT + tid);
+        uint32_t code;
+        if (state[q] == 0) {
+            const uint32_t qx = (uint32_t)fminf(fmaxf((cx[q] - lo[0]) * sc[0], 0.f), 1023.f);
+            const uint32_t qy = (uint32_t)fminf(fmaxf((cy[q] - lo[1]) * sc[1], 0.f), 1023.f);
+            const uint32_t qz = (uint32_t)fminf(fmaxf((cz[q] - lo[2]) * sc[2], 0.f), 1023.f);
+            code = spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
+        } else {
+            code = state[q] == 1 ? (1u << 30) : 0xFFFFFFFFu;
+        }
+        key[j] = ((uint64_t)code << 32) | j;
+    }
+    __syncthreads();
+    // bitonic sort of the 4096 keys, two compare-exchanges per thread and pass
+    for (uint32_t k = 2; k <= kGenSortBlock; k <<= 1) {
+        for (uint32_t h = k >> 1; h > 0; h >>= 1) {
+#pragma unroll
+            for (int q = 0; q < kPer / 2; ++q) {
+                const uint32_t i = (uint32_t)(q * kT + tid);           // pair index, < 2048
+                const uint32_t a = ((i & ~(h - 1)) << 1) | (i & (h - 1));
+                const uint32_t c = a | h;
+                const uint64_t ka = key[a], kc = key[c];
+                const bool up = (a & k) == 0;
+                if ((ka > kc) == up) { key[a] = kc; key[c] = ka; }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const uint32_t p = (uint32_t)(q * kT + tid);
+        if (p < n_in)
+            prep_triangle(pos, nv, tri, base + (uint32_t)(key[p] & 0xFFFFFFFFu), base + p, cull, verts, err);
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+k_gen_prep_sorted(const float* __restrict__ pos, uint32_t nv, const uint32_t* __restrict__ tri, uint32_t nt,
+                  float4* __restrict__ cull, float4* __restrict__ verts, uint32_t* __restrict__ err)
+{
+    prep_sorted_block(pos, nv, tri, nt, blockIdx.x, true, cull, verts, err);
+}
+
+// mesh order: one thread per triangle
 __global__ void __launch_bounds__(256)
 k_gen_prep(const float* __restrict__ pos, uint32_t nv, const uint32_t* __restrict__ tri, uint32_t nt,
            float4* __restrict__ cull, float4* __restrict__ verts, uint32_t* __restrict__ err)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nt) prep_triangle(pos, nv, tri, t, cull, verts, err);
+    if (t < nt) prep_triangle(pos, nv, tri, t, t, cull, verts, err);
 }
 
 // Bounding sphere of each run of 64 consecutive triangles (one wavefront's
@@ -533,19 +667,19 @@ __device__ __forceinline__ uint32_t find_job(const GenJob* __restrict__ jobs, ui
     uint32_t lo = 0, hi = njobs - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) / 2;
-        const uint64_t st = chunks ? jobs[mid].chunk_start : jobs[mid].tri_start;
+        const uint64_t st = chunks ? jobs[mid].chunk_start : jobs[mid].block_start;
         if (st <= x) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
-__global__ void __launch_bounds__(256)
-k_gen_prep_batched(const GenJob* __restrict__ jobs, uint32_t njobs, uint64_t total, uint32_t* __restrict__ err)
+__global__ void __launch_bounds__(1024)
+k_gen_prep_batched(const GenJob* __restrict__ jobs, uint32_t njobs, uint32_t* __restrict__ err)
 {
-    const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= total) return;
+    // one workgroup per sort block of every mesh (block_start: the mesh's first)
+    const uint64_t x = blockIdx.x;
     const GenJob& J = jobs[find_job(jobs, njobs, x, false)];
-    prep_triangle(J.pos, J.nv, J.tri, (uint32_t)(x - J.tri_start), J.cull, J.verts, err);
+    prep_sorted_block(J.pos, J.nv, J.tri, J.nt, (uint32_t)(x - J.block_start), J.sort != 0, J.cull, J.verts, err);
 }
 
 __global__ void __launch_bounds__(256)
@@ -565,12 +699,20 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v)
 
 }  // namespace
 
-hipError_t launch_gen_prep(const float* pos, uint32_t nv, const uint32_t* tri, uint32_t nt,
+bool gen_sort_wanted(int mode, uint32_t nt)
+{
+    return mode == 1 || (mode == 2 && nt >= kGenSortAuto);
+}
+
+hipError_t launch_gen_prep(const float* pos, uint32_t nv, const uint32_t* tri, uint32_t nt, int sort_mode,
                            float4* cull, float4* verts, uint32_t* err, hipStream_t s)
 {
     if (nt == 0) return hipSuccess;
-    const uint32_t blocks = (nt + 255) / 256;
-    hipLaunchKernelGGL(k_gen_prep, dim3(blocks), dim3(256), 0, s, pos, nv, tri, nt, cull, verts, err);
+    if (gen_sort_wanted(sort_mode, nt))
+        hipLaunchKernelGGL(k_gen_prep_sorted, dim3((nt + kGenSortBlock - 1) / kGenSortBlock), dim3(1024), 0, s, pos,
+                           nv, tri, nt, cull, verts, err);
+    else
+        hipLaunchKernelGGL(k_gen_prep, dim3((nt + 255) / 256), dim3(256), 0, s, pos, nv, tri, nt, cull, verts, err);
     return hipGetLastError();
 }
 
@@ -610,14 +752,13 @@ hipError_t gen_batched_grid(int group, int cus, uint32_t* grid)
     return hipSuccess;
 }
 
-hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total_tris, uint64_t total_chunks,
+hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total_blocks, uint64_t total_chunks,
                               uint32_t total_items, float R, uint32_t* counter, uint32_t* err, uint32_t grid,
                               int group, hipStream_t s)
 {
     if (njobs == 0) return hipSuccess;
-    if (total_tris > 0) {
-        hipLaunchKernelGGL(k_gen_prep_batched, dim3((uint32_t)((total_tris + 255) / 256)), dim3(256), 0, s, jobs, njobs,
-                           total_tris, err);
+    if (total_blocks > 0) {
+        hipLaunchKernelGGL(k_gen_prep_batched, dim3((uint32_t)total_blocks), dim3(1024), 0, s, jobs, njobs, err);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_gen_clusters_batched, dim3((uint32_t)((total_chunks + 3) / 4)), dim3(256), 0, s, jobs,

@@ -16,20 +16,32 @@ constexpr size_t kTriCullBytes = 16;
 constexpr size_t kTriVertBytes = 48;
 
 // One mesh of a batched call (device copy).  cull / clusters / verts point at
-// this job's part of the scratch; tri_start / chunk_start / item_start are the
-// job's first triangle, 64-triangle chunk and image-group work item in the
-// flattened index spaces of the batched kernels.
+// this job's part of the scratch; block_start / chunk_start / item_start are
+// the job's first triangle sort block (kGenSortBlock triangles), 64-triangle
+// chunk and image-group work item in the flattened index spaces of the batched
+// kernels.
+// triangles per Morton-sorted block of the triangle preparation (one
+// workgroup), and the mesh size from which the automatic mode sorts (measured:
+// the sort pays on the 691k-triangle clutter scene, not on the 47k-triangle
+// union of 12 shapes)
+constexpr uint32_t kGenSortBlock = 4096;
+constexpr uint32_t kGenSortAuto = 1u << 17;
+
 struct GenJob {
     const float* pos; uint32_t nv;
     const uint32_t* tri; uint32_t nt;
     const float* op_pos; const float* op_nrm; uint32_t n;
     uint32_t* out;
     float4* cull; float4* clusters; float4* verts;
-    uint64_t tri_start, chunk_start;
+    uint64_t block_start, chunk_start;
     uint32_t item_start;
+    int sort;                     // triangles stored in Morton order within blocks
 };
 
-hipError_t launch_gen_prep(const float* pos, uint32_t nv, const uint32_t* tri, uint32_t nt,
+// sort mode: 0 mesh order, 1 Morton order within blocks, 2 Morton order for
+// meshes of at least kGenSortAuto triangles
+bool gen_sort_wanted(int mode, uint32_t nt);
+hipError_t launch_gen_prep(const float* pos, uint32_t nv, const uint32_t* tri, uint32_t nt, int sort_mode,
                            float4* cull, float4* verts, uint32_t* err, hipStream_t s);
 hipError_t launch_gen_clusters(const float4* cull, uint32_t nt, float4* clusters, hipStream_t s);
 hipError_t launch_gen(const float4* cull, const float4* clusters, const float4* verts, uint32_t nt,
@@ -40,7 +52,7 @@ uint32_t gen_group_images(int group);
 // workgroups of the persistent generation kernel that fit the device at once
 hipError_t gen_batched_grid(int group, int cus, uint32_t* grid);
 // prep + clusters + persistent generation over `njobs` jobs stored largest first
-hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total_tris, uint64_t total_chunks,
+hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total_blocks, uint64_t total_chunks,
                               uint32_t total_items, float R, uint32_t* counter, uint32_t* err, uint32_t grid,
                               int group, hipStream_t s);
 

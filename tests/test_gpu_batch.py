@@ -106,6 +106,31 @@ def test_batch_small_search_tile(ctx):
     c128.close()
 
 
+def test_batch_sorted_triangles(ctx):
+    """A plan whose meshes store their triangles in Morton order gives the
+    plain path's images (mesh order) bit for bit, ragged sort blocks included."""
+    from paper_2007_02306_amd import Context
+    meshes = _meshes(10, 5, 3000, 12000)
+    cs = Context(0)
+    cs.set_tuning("gen_sort_triangles", 1)
+    c0 = Context(0)
+    c0.set_tuning("gen_sort_triangles", 0)
+    jobs = [dict(positions=dev_f32(p), triangles=dev_u32(t), op_positions=dev_f32(p), op_normals=dev_f32(n),
+                 true_index=dev_u32(ti)) for p, t, n, ti in meshes]
+    b = cs.batch(jobs, 0.3)
+    b.run()
+    cs.sync()
+    for k, j in enumerate(jobs):
+        img = c0.generate(j["positions"], j["triangles"], j["op_positions"], j["op_normals"], 0.3)
+        rk, ds = c0.distance_rank(img, img, j["true_index"])
+        c0.sync()
+        assert np.array_equal(host_u32(b.images[k]), host_u32(img)), f"mesh {k}"
+        assert np.array_equal(host_u32(b.rank[k]), host_u32(rk))
+    b.close()
+    cs.close()
+    c0.close()
+
+
 def test_batch_with_early_exit(ctx):
     """A plan recorded with the search's early exit gives the plain path's
     exact ranks (shuffled true matches: non-trivial thresholds)."""

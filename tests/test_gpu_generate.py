@@ -202,3 +202,57 @@ def test_group_sizes_agree_at_full_size(ctx, ctx4):
     a = gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
     b = gpu_images(ctx4, s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
     assert np.array_equal(a, b)
+
+
+@pytest.fixture()
+def ctx_order():
+    """Handles storing the triangles in mesh order and in Morton order."""
+    from paper_2007_02306_amd import Context
+    c0, c1 = Context(0), Context(0)
+    c0.set_tuning("gen_sort_triangles", 0)
+    c1.set_tuning("gen_sort_triangles", 1)
+    assert (c0.get_tuning("gen_sort_triangles"), c1.get_tuning("gen_sort_triangles")) == (0, 1)
+    yield c0, c1
+    c0.close()
+    c1.close()
+
+
+def test_triangle_orders_agree(ctx, ctx_order):
+    """The generation kernel's culls see the triangles in mesh order or in
+    Morton order (compact runs); counts are integer sums over the same
+    triangles, so every image is identical: the union of 12 shapes in full
+    (below the automatic threshold, so the default handle keeps mesh order),
+    sampled clutter images (above it), a ragged tiny scene, and bad inputs
+    reported the same way."""
+    c0, c1 = ctx_order
+    s = synth.config2_union12()
+    a = gpu_images(c0, s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    b = gpu_images(c1, s.positions, s.triangles, s.op_positions, s.op_normals, s.support_radius)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals,
+                                        s.support_radius))
+    c = synth.config3_clutter()
+    rng = np.random.default_rng(34)
+    sel = np.sort(rng.choice(c.num_haystack, 64, replace=False))
+    a = gpu_images(c0, c.positions, c.triangles, c.op_positions[sel], c.op_normals[sel], c.support_radius)
+    b = gpu_images(ctx, c.positions, c.triangles, c.op_positions[sel], c.op_normals[sel], c.support_radius)
+    assert np.array_equal(a, b)
+    t = synth.config1_icosphere()
+    tri = t.triangles[: 4096 + 77]                  # one full sort block and a ragged one (tiled below)
+    tri = np.concatenate([tri] * (1 + (4096 + 77) // len(tri)))[: 4096 + 77]
+    a = gpu_images(c0, t.positions, tri, t.op_positions, t.op_normals, 1.0)
+    b = gpu_images(c1, t.positions, tri, t.op_positions, t.op_normals, 1.0)
+    assert np.array_equal(a, b)
+    o, fl, _ = oracle.rici_rowrange(t.positions, tri, t.op_positions[:8], t.op_normals[:8], 1.0)
+    assert_images_match(b[:8], o, fl, "sorted tiny scene")
+    from paper_2007_02306_amd import RiciError
+    bad = t.triangles.copy()
+    bad[5, 1] = t.positions.shape[0] + 3
+    with pytest.raises(RiciError) as e:
+        gpu_images(c1, t.positions, bad, t.op_positions[:3], t.op_normals[:3], 1.0)
+    assert "RICI_ERR_DEVICE" in str(e.value) and c1.device_errors() & 1
+    pos = t.positions.copy()
+    pos[7, 2] = np.nan
+    with pytest.raises(RiciError):
+        gpu_images(c1, pos, t.triangles, t.op_positions[:3], t.op_normals[:3], 1.0)
+    assert c1.device_errors() & 2

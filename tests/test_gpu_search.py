@@ -213,6 +213,9 @@ def test_tuning_rejects_bad_values(ctx):
         ctx.set_tuning("gen_images_per_group", 3)
     with pytest.raises(RiciError):
         ctx.set_tuning("search_early_exit", 2)
+    with pytest.raises(RiciError):
+        ctx.set_tuning("gen_sort_triangles", 3)
+    assert ctx.get_tuning("gen_sort_triangles") == 2
     assert ctx.get_tuning("search_tile_m") == 256
     assert ctx.get_tuning("gen_images_per_group") == 2
 
