@@ -2,6 +2,7 @@
 
 Knobs (results never depend on them, only speed):
     gen_images_per_group   images sharing a generation workgroup: 2 or 4
+    gen_sort_triangles     triangle order for the generation culls: 0 mesh order, 1 Morton order
     search_tile_m          needles per search workgroup tile: 256 or 128
 
 A choice is made per shape class by timing every candidate on a calibration
@@ -33,6 +34,7 @@ import os
 import threading
 
 GEN_CHOICES = (2, 4)
+SORT_CHOICES = (0, 1)
 SEARCH_CHOICES = (256, 128)
 
 _lock = threading.Lock()
@@ -112,11 +114,12 @@ class Tuner:
         half_octaves = max(-12, min(12, int(math.floor(2 * math.log2(rel)))))
         return f"gen|t{_log2_bucket(triangles.shape[0], 30)}|n{_log2_bucket(op_positions.shape[0], 30)}|r{half_octaves}"
 
-    def tune_generate(self, positions, triangles, op_positions, op_normals, R: float) -> int:
+    def tune_generate(self, positions, triangles, op_positions, op_normals, R: float) -> tuple:
+        """(gen_images_per_group, gen_sort_triangles) for this shape class."""
         key = self.gen_class(positions, triangles, op_positions, R)
         v = self._get(key)
         if v is not None:
-            return int(v)
+            return (int(v), 2) if isinstance(v, int) else (int(v[0]), int(v[1]))
         torch = _torch()
         n = op_positions.shape[0]
         m = min(n, self.gen_sample)
@@ -124,21 +127,27 @@ class Tuner:
         opp = op_positions.index_select(0, idx).contiguous()
         opn = op_normals.index_select(0, idx).contiguous()
         out = torch.empty((m, 64, 64), dtype=torch.int32, device=opp.device)
-        old = self.ctx.get_tuning("gen_images_per_group")
+        old = (self.ctx.get_tuning("gen_images_per_group"), self.ctx.get_tuning("gen_sort_triangles"))
         best, best_ms = None, None
-        for c in GEN_CHOICES:
-            self.ctx.set_tuning("gen_images_per_group", c)
-            ms = self._time("gen", lambda: self.ctx.generate(positions, triangles, opp, opn, R, out=out))
-            self.measurements.append((key, c, ms))
-            if best_ms is None or ms < best_ms:
-                best, best_ms = c, ms
-        self.ctx.set_tuning("gen_images_per_group", old)
-        self._put(key, best)
+        for g in GEN_CHOICES:
+            for o in SORT_CHOICES:
+                self.ctx.set_tuning("gen_images_per_group", g)
+                self.ctx.set_tuning("gen_sort_triangles", o)
+                # the triangle preparation is part of the cost of an order
+                ms = sum(self._time(k, lambda: self.ctx.generate(positions, triangles, opp, opn, R, out=out))
+                         for k in ("gen_prep", "gen"))
+                self.measurements.append((key, (g, o), ms))
+                if best_ms is None or ms < best_ms:
+                    best, best_ms = (g, o), ms
+        self.ctx.set_tuning("gen_images_per_group", old[0])
+        self.ctx.set_tuning("gen_sort_triangles", old[1])
+        self._put(key, list(best))
         return best
 
     def generate(self, positions, triangles, op_positions, op_normals, R: float, out=None, stream=None):
-        c = self.tune_generate(positions, triangles, op_positions, op_normals, R)
-        self.ctx.set_tuning("gen_images_per_group", c)
+        g, o = self.tune_generate(positions, triangles, op_positions, op_normals, R)
+        self.ctx.set_tuning("gen_images_per_group", g)
+        self.ctx.set_tuning("gen_sort_triangles", o)
         return self.ctx.generate(positions, triangles, op_positions, op_normals, R, out=out, stream=stream)
 
     # ----------------------------------------------------------- search

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 def test_tuned_calls_match_default_calls(tmp_path):
     import torch
     from paper_2007_02306_amd import Context
-    from paper_2007_02306_amd.tune import GEN_CHOICES, SEARCH_CHOICES, Tuner
+    from paper_2007_02306_amd.tune import GEN_CHOICES, SEARCH_CHOICES, SORT_CHOICES, Tuner
     ctx, ref = Context(0), Context(0)
     s = synth.config1_icosphere()
     pos, tri = dev_f32(s.positions), dev_u32(s.triangles)
@@ -34,7 +34,9 @@ def test_tuned_calls_match_default_calls(tmp_path):
     data = json.loads(path.read_text())[t.arch]
     gen_keys = [k for k in data if k.startswith("gen|")]
     search_keys = [k for k in data if k.startswith("search|")]
-    assert len(gen_keys) == 1 and data[gen_keys[0]] in GEN_CHOICES
+    assert len(gen_keys) == 1
+    g, o = data[gen_keys[0]]
+    assert g in GEN_CHOICES and o in SORT_CHOICES
     assert len(search_keys) == 1 and data[search_keys[0]] in SEARCH_CHOICES
     n_meas = len(t.measurements)
     t.generate(pos, tri, opp, opn, s.support_radius)       # cached: no new measurement

@@ -7,7 +7,7 @@ import json
 import pytest
 import torch
 
-from paper_2007_02306_amd.tune import GEN_CHOICES, SEARCH_CHOICES, Tuner
+from paper_2007_02306_amd.tune import GEN_CHOICES, SEARCH_CHOICES, SORT_CHOICES, Tuner
 
 
 class FakeCtx:
@@ -16,7 +16,7 @@ class FakeCtx:
     device = 0
 
     def __init__(self, gen_ms, search_ms, batch_ms):
-        self.knobs = {"gen_images_per_group": 2, "search_tile_m": 256}
+        self.knobs = {"gen_images_per_group": 2, "search_tile_m": 256, "gen_sort_triangles": 2}
         self.gen_ms, self.search_ms, self.batch_ms = gen_ms, search_ms, batch_ms
         self.calls = []
         self._last = {}
@@ -37,8 +37,10 @@ class FakeCtx:
         return self._last.get(kernel, 0.0), 1
 
     def generate(self, pos, tri, opp, opn, R, out=None, stream=None):
-        self.calls.append(("generate", self.knobs["gen_images_per_group"], opp.shape[0]))
-        self._last["gen"] = self.gen_ms[self.knobs["gen_images_per_group"]]
+        g, o = self.knobs["gen_images_per_group"], self.knobs["gen_sort_triangles"]
+        self.calls.append(("generate", g, o, opp.shape[0]))
+        # gen_ms maps (group, order) -> (preparation ms, generation ms)
+        self._last["gen_prep"], self._last["gen"] = self.gen_ms[(g, o)]
         return out
 
     def distance_rank(self, n, h, t, **kw):
@@ -72,24 +74,33 @@ def _no_cuda_sync(monkeypatch):
 
 
 def test_generation_picks_fastest_and_caches(tmp_path):
-    ctx = FakeCtx({2: 5.0, 4: 3.0}, {256: 1.0, 128: 2.0}, {})
+    # (group, order) -> (prep ms, gen ms): the Morton order's costlier
+    # preparation decides between (4, 0) and (4, 1)
+    ms = {(2, 0): (0.1, 5.0), (2, 1): (0.5, 4.9), (4, 0): (0.1, 3.0), (4, 1): (0.5, 2.8)}
+    ctx = FakeCtx(ms, {256: 1.0, 128: 2.0}, {})
     path = tmp_path / "tune.json"
     t = Tuner(ctx, str(path), reps=2, gen_sample=16, arch="gfx-test")
     pos, tri, opp, opn = _mesh()
-    assert t.tune_generate(pos, tri, opp, opn, 0.3) == 4
-    assert {c for c in GEN_CHOICES} == {m[1] for m in t.measurements}
-    assert all(c[2] == 16 for c in ctx.calls)              # calibration subset only
+    assert t.tune_generate(pos, tri, opp, opn, 0.3) == (4, 0)
+    assert {(g, o) for g in GEN_CHOICES for o in SORT_CHOICES} == {m[1] for m in t.measurements}
+    assert all(c[3] == 16 for c in ctx.calls)              # calibration subset only
     assert ctx.knobs["gen_images_per_group"] == 2           # restored after tuning
+    assert ctx.knobs["gen_sort_triangles"] == 2
     data = json.loads(path.read_text())
-    assert list(data["gfx-test"].values()) == [4]
+    assert list(data["gfx-test"].values()) == [[4, 0]]
     # a fresh tuner reads the cache and measures nothing
-    ctx2 = FakeCtx({2: 1.0, 4: 9.0}, {}, {})
+    ctx2 = FakeCtx({k: (0.0, 9.0) for k in ms}, {}, {})
     t2 = Tuner(ctx2, str(path), arch="gfx-test")
     t2.generate(pos, tri, opp, opn, 0.3)
-    assert t2.measurements == [] and ctx2.calls == [("generate", 4, 50)]
+    assert t2.measurements == [] and ctx2.calls == [("generate", 4, 0, 50)]
     # another architecture is tuned anew
-    t3 = Tuner(FakeCtx({2: 1.0, 4: 9.0}, {}, {}), str(path), arch="gfx-other")
-    assert t3.tune_generate(pos, tri, opp, opn, 0.3) == 2
+    ms3 = {(2, 0): (0.1, 2.0), (2, 1): (0.2, 1.0), (4, 0): (0.1, 3.0), (4, 1): (0.2, 2.5)}
+    t3 = Tuner(FakeCtx(ms3, {}, {}), str(path), arch="gfx-other")
+    assert t3.tune_generate(pos, tri, opp, opn, 0.3) == (2, 1)
+    # a cache written before the order knob existed (a bare group) still reads
+    path2 = tmp_path / "old.json"
+    path2.write_text(json.dumps({"gfx-test": {Tuner.gen_class(pos, tri, opp, 0.3): 4}}))
+    assert Tuner(FakeCtx(ms, {}, {}), str(path2), arch="gfx-test").tune_generate(pos, tri, opp, opn, 0.3) == (4, 2)
 
 
 def test_search_classes_and_choice(tmp_path):
