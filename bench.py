@@ -197,7 +197,8 @@ def host_cpu():
 def value_distributions(images):
     """Statistics of a device image set (torch int32 [N,64,64]) that set the
     search's arithmetic paths: count histogram summary, needle-mask density
-    (fraction of D != 0), per-image max |D| classes."""
+    (fraction of D != 0), per-image max |D| classes (<= 15: two contraction
+    phases; 16..127: three; above: the exact int64 path)."""
     import torch
     x = images.to(torch.int64)
     d = x[:, :, 1:] - x[:, :, :-1]
@@ -208,8 +209,8 @@ def value_distributions(images):
         "count_histogram_0_to_16plus": hist,
         "max_count": int(images.max()),
         "mask_density": float((d != 0).float().mean()),
-        "max_abs_delta_share": {"le_11": float((mx <= 11).sum()) / n,
-                                "12_to_127": float(((mx > 11) & (mx <= 127)).sum()) / n,
+        "max_abs_delta_share": {"le_15": float((mx <= 15).sum()) / n,
+                                "16_to_127": float(((mx > 15) & (mx <= 127)).sum()) / n,
                                 "gt_127": float((mx > 127).sum()) / n},
     }
 

@@ -66,16 +66,16 @@ constexpr size_t kFragBytes = 1024;              // 16 images x 64 columns
 constexpr size_t kPlaneGroupBytes = NB * kFragBytes;   // one group, all 64 rows
 
 // needle planes: 0 = -D (int8), 1 = mask [D != 0] (0/1)
-// haystack planes: 0 = D, 1 = D^2 mod 128, 2 = D^2 / 128
+// haystack planes: 0 = D, 1 = r = (D^2 mod 256) - 128, 2 = q = D^2 div 256
 // Needles keep their order (slot = image).  The haystack is permuted: images
-// whose deltas all satisfy |D| <= 11 take slots from the front, the others
+// whose deltas all satisfy |D| <= 15 (so q = 0) take slots from the front, the others
 // from the back, with at least one whole tile of padding in between, so that a
 // search tile holds only one kind and only tiles of the second kind pay the
 // third contraction phase.  Ranks are counts, so the order is free; the
 // distance matrix maps slots back through `perm`.
 struct SearchPrep {
     int8_t* planes;        // [nplanes][ngroups][64][1024]
-    int64_t* sumsq;        // needles: |D|^2 per slot
+    int64_t* sumsq;        // needles: |D|^2 + 128 * #(D != 0) per slot (the contraction's constant)
     uint32_t* maxabs;      // max |D| per slot (saturating; padding = 0xFFFFFFFF)
     uint32_t* maxabs_img;  // max |D| per original image (== maxabs for needles)
     uint32_t* perm;        // haystack: slot -> image (0xFFFFFFFF = padding); needles: nullptr

@@ -8,13 +8,16 @@
 // length-4096 int8 dot products -- a dense int8 x int8 -> int32 GEMM over all
 // pairs, which is what MFMA does best.  Operands stay exact int8 under a range
 // check: needles with |D| <= 127 use planes (-D_n, m_n); haystack images with
-// |D| <= 127 use (D_h, D_h^2 mod 128, D_h^2 div 128).  The accumulator is
-// scaled between phases so a single int32 accumulator holds
-//     128 <m, q> ... (x64) ... - <D_n, D_h> ... (x2) ... + <m, r>
-//   = <m, D_h^2> - 2 <D_n, D_h>          with D_h^2 = 128 q + r,
-// and the q phase is skipped for haystack tiles where every |D_h| <= 11.
-// All partial sums stay below 2^31 (4032 * 127^2 * 3 < 2^31).  Any image
-// outside the int8 range goes to an exact int64 VALU path instead.
+// |D| <= 127 use (D_h, r, q) with D_h^2 = 256 q + r + 128, i.e.
+// r = (D_h^2 mod 256) - 128 in [-128, 127] and q = D_h^2 div 256 in [0, 63].
+// The accumulator is scaled between phases so a single int32 accumulator holds
+//     128 <m, q> ... (x128) ... - <D_n, D_h> ... (x2) ... + <m, r>
+//   = <m, D_h^2> - 2 <D_n, D_h> - 128 |m|,
+// and the needle's constant |D_n|^2 + 128 |m| (|m| = its non-zero deltas) is
+// added outside.  The q phase is skipped for haystack tiles where every
+// |D_h| <= 15 (then q = 0).  All partial sums stay far below 2^31
+// (4032 * 63 * 256 + 2 * 4032 * 127^2 + 4032 * 128 < 2^31).  Any image outside
+// the int8 range goes to an exact int64 VALU path instead.
 //
 // Ranking never sorts: rank_i = #{ h : CRD(n_i, h) < CRD(n_i, h_true) } is a
 // sum of per-tile counts, so tiles add their counts with integer atomics and
@@ -29,7 +32,7 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr uint32_t kSlow = 127;     // largest |D| an int8 operand holds
-constexpr uint32_t kSmallD = 11;    // |D| <= 11  =>  D^2 <= 121 fits int8 directly
+constexpr uint32_t kSmallD = 15;    // |D| <= 15  =>  D^2 <= 225: q = 0, r = D^2 - 128 fits int8
 constexpr uint32_t kPad = 0xFFFFFFFFu;
 
 // ------------------------------------------------------------------ delta prep
@@ -69,7 +72,7 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
                 int64_t dd = (q == 0 && k == 0) ? 0 : (int64_t)v[k + 1] - (int64_t)v[k];
                 uint64_t a = dd < 0 ? (uint64_t)(-dd) : (uint64_t)dd;
                 mx = (uint32_t)max((uint64_t)mx, min(a, (uint64_t)0xFFFFFFFEu));
-                ss += dd * dd;
+                ss += dd * dd + (dd != 0 ? 128 : 0);   // |D|^2 + 128 |m|
                 d[k] = (int32_t)max(min(dd, (int64_t)127), (int64_t)-127);
             }
         } else {
@@ -93,8 +96,8 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
                     p2 = 0u;
                 } else {
                     p0 = (uint32_t)(uint8_t)(int8_t)x;
-                    p1 = sq & 127u;
-                    p2 = sq >> 7;
+                    p1 = (sq & 255u) ^ 0x80u;   // (D^2 mod 256) - 128 as an int8 byte
+                    p2 = sq >> 8;
                 }
                 a0 |= p0 << (8 * b); a1 |= p1 << (8 * b); a2 |= p2 << (8 * b);
             }
@@ -133,7 +136,7 @@ k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
 
 // Haystack slot assignment.  k_hay_init marks every slot as padding;
 // k_hay_stats (one wavefront per image) finds max |D|; k_hay_assign (one
-// workgroup, prefix sums) gives images with |D| <= 11 the front slots and the
+// workgroup, prefix sums) gives images with |D| <= 15 the front slots and the
 // others the back slots, both in image order, so the layout is deterministic.
 __global__ void __launch_bounds__(256)
 k_hay_init(uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs, uint32_t nslots)
@@ -389,7 +392,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     const uint32_t ga0 = tm * C::GA, gb0 = tn * C::GB;
 
     // q phase needed iff some usable haystack image of the tile has
-    // 11 < |D| <= 127; a tile without any usable haystack image is skipped
+    // 15 < |D| <= 127; a tile without any usable haystack image is skipped
     int flags = 0;
     for (int j = tid; j < C::BN; j += C::kThreads) {
         const uint32_t m = A.hmax[gb0 * 16 + j];
@@ -414,7 +417,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     const int nstage = (hq ? 3 : 2) * NB;
 
     // Stage s = phase s / 64, image row s % 64.  Phase -> planes: needle planes
-    // 0 = -D, 1 = mask; haystack planes 0 = D, 1 = D^2 mod 128, 2 = D^2 div 128.
+    // 0 = -D, 1 = mask; haystack planes 0 = D, 1 = r, 2 = q (D^2 = 256 q + r + 128).
     // Each wave moves kLPW whole fragments (1 KiB, one instruction each) from
     // global memory straight into the stage's LDS slot.  Fragment j of wave w
     // is fragment w + j * kWaves of the stage (the GA needle groups, then the
@@ -434,9 +437,8 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         const int g = wv + j * C::kWaves - (j < kJA ? 0 : C::GA);
         voff[j] = (uint32_t)g * (uint32_t)kPlaneGroupBytes + (uint32_t)lane * 16;
     }
-    // planes of phases 0, 1 (, 2): needles -D, mask; haystack D, D^2 mod 128.
-    // With the q phase first (hq): needles mask, -D, mask; haystack
-    // D^2 div 128, D, D^2 mod 128.
+    // planes of phases 0, 1 (, 2): needles -D, mask; haystack D, r.  With the
+    // q phase first (hq): needles mask, -D, mask; haystack q, D, r.
     const int8_t* a_p0 = a_base + (hq ? a_ps : 0);
     const int8_t* a_p1 = a_base + (hq ? 0 : a_ps);
     const int8_t* b_p0 = b_base + (hq ? 2 * b_ps : 0);
@@ -475,11 +477,13 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // block; the loads go out after the first MFMA and the reads after the
     // next ones, so that the wait in front of the MFMAs covers only the
     // previous step's reads.
-    // Early exit (rank mode): in the last phase the partial sums only grow
-    // (they add <m, D_h^2> or <m, D_h^2 mod 128>, both >= 0), so once no pair
-    // of the tile is below its needle's threshold none will be, and the tile
-    // adds nothing to any rank.  Checked every 16 rows of that phase: each
-    // wave votes through LDS, the next stage barrier publishes the votes.
+    // Early exit (rank mode): the last phase adds <m, r> with r >= -128, so
+    // after k of its 64 rows no partial sum can fall by more than
+    // 128 * 63 * (64 - k) (all remaining deltas of the needle non-zero).  Once
+    // no pair of the tile is below its needle's threshold by that margin none
+    // will end below it, and the tile adds nothing to any rank.  Checked every
+    // 16 rows of that phase: each wave votes through LDS, the next stage
+    // barrier publishes the votes.
     const bool exit_ok = EXIT && A.early_exit && A.thr && !A.matrix;
     volatile uint32_t* votes = reinterpret_cast<volatile uint32_t*>(lds + C::kVote);
     int32_t* thr_l = reinterpret_cast<int32_t*>(lds + C::kThr);
@@ -495,7 +499,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         }
         for (int j = tid; j < C::BN; j += C::kThreads) col_l[j] = A.hmax[gb0 * 16 + j] <= kSlow ? 1 : 0;
     }
-    auto vote = [&]() {
+    auto vote = [&](int32_t slack) {
         bool alive = false;
         const int cl = lane & 15, rq = lane >> 4;
         bool colok[C::kNBK];
@@ -506,9 +510,9 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             // one block row at a time (four thresholds live), in program order
             const v4i t = *reinterpret_cast<const v4i*>(thr_l + (wm * C::kMB + mb) * 16 + 4 * rq);
 #pragma unroll
-            for (int nb = 0; nb < C::kNBK; ++nb)
-                alive |= colok[nb] && (acc[mb][nb].x < t.x || acc[mb][nb].y < t.y || acc[mb][nb].z < t.z ||
-                                       acc[mb][nb].w < t.w);
+            for (int nb = 0; nb < C::kNBK; ++nb)   // |acc| + slack stays far from the int32 limits
+                alive |= colok[nb] && (acc[mb][nb].x - slack < t.x || acc[mb][nb].y - slack < t.y ||
+                                       acc[mb][nb].z - slack < t.z || acc[mb][nb].w - slack < t.w);
             __builtin_amdgcn_sched_barrier(0);
         }
         const uint64_t any_alive = __ballot(alive);   // every lane takes part
@@ -564,8 +568,8 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             if constexpr (kRest > 0) __builtin_amdgcn_sched_group_barrier(0x008, kRest, 0);
         }
         if (k == C::kNS - 1 && (s + 1) % NB == 0 && s + 1 < nstage) {
-            // end of a phase: scale the partial sum (x64 after q, x2 after -D.D)
-            const int sh = (hq && s + 1 == NB) ? 6 : 1;
+            // end of a phase: scale the partial sum (x128 after q, x2 after -D.D)
+            const int sh = (hq && s + 1 == NB) ? 7 : 1;
 #pragma unroll
             for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
@@ -588,7 +592,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         step(3, s + 3, fr1, fr0);
         // after 16, 32 and 48 rows of the last phase: vote, publish, decide
         if (exit_ok && s + 4 > last_phase && (s + 4 - last_phase) % 16 == 0 && s + 4 < nstage) {
-            vote();
+            vote(128 * 63 * (NB - (s + 4 - last_phase)));
             __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the votes are written
             stage_barrier();
             if (all_done()) {

@@ -43,9 +43,10 @@ def test_matrix_small_deltas(ctx, nn, nh, scale):
     assert np.array_equal(gpu_matrix(ctx, n, h), oracle.distance_matrix(n, h))
 
 
-@pytest.mark.parametrize("nmax,hmax", [(11, 12), (11, 127), (127, 11), (127, 127), (128, 11), (11, 128), (300, 500)])
+@pytest.mark.parametrize("nmax,hmax", [(11, 12), (11, 127), (127, 11), (127, 127), (128, 11), (11, 128), (300, 500),
+                                       (15, 15), (15, 16), (16, 15)])
 def test_matrix_delta_ranges(ctx, nmax, hmax):
-    """Every arithmetic path: |D_h| <= 11 (two phases), 11 < |D_h| <= 127
+    """Every arithmetic path: |D_h| <= 15 (two phases), 15 < |D_h| <= 127
     (three phases), |D| > 127 (int64 path) on either side."""
     rng = np.random.default_rng(nmax * 7 + hmax)
     n = synth.step_images(rng, 70, delta_scale=3)
@@ -57,6 +58,45 @@ def test_matrix_delta_ranges(ctx, nmax, hmax):
     n[6] = h[40]
     got = gpu_matrix(ctx, n, h)
     assert np.array_equal(got, oracle.distance_matrix(n, h))
+
+
+def _exact_step_images(rng, n, peak):
+    """Sparse small steps plus one step of exactly `peak` (so max |D| = peak)
+    per image; `peak` <= 2 keeps only the small steps."""
+    im = synth.step_images(rng, n, density=0.05, delta_scale=2).astype(np.int64)
+    if peak > 2:
+        for k in range(n):
+            r, c = rng.integers(0, 64), rng.integers(1, 64)
+            im[k, r, c:] += peak - (im[k, r, c] - im[k, r, c - 1])   # that delta becomes exactly peak
+    return im.astype(np.uint32)
+
+
+@pytest.mark.parametrize("tile,exit_", [(256, 0), (128, 0), (256, 1)])
+def test_delta_range_boundaries(tile, exit_):
+    """Haystack and needle images whose largest delta sits exactly on each side
+    of the two-phase limit (15), the int8 limit (127) and in between, mixed in
+    one haystack: exact matrix and ranks against the oracle, for both tile
+    heights and with the early exit."""
+    from paper_2007_02306_amd import Context
+    c = Context(0)
+    c.set_tuning("search_tile_m", tile)
+    c.set_tuning("search_early_exit", exit_)
+    rng = np.random.default_rng(tile + exit_)
+    peaks = [0, 11, 12, 15, 16, 17, 60, 127, 128]
+    h = np.concatenate([_exact_step_images(rng, 40, p) for p in peaks])
+    for i, p in zip(range(0, len(h), 40), peaks):
+        d = np.abs(np.diff(h[i:i + 40].astype(np.int64), axis=2)).max(axis=(1, 2))
+        assert (d >= p).all() and (p < 3 or (d == p).all())
+    t = rng.integers(0, len(h), 200).astype(np.uint32)
+    n = synth.perturb(rng, h[t], frac=0.01)
+    n[:9] = np.stack([_exact_step_images(rng, 1, p)[0] for p in peaks])
+    t[:9] = rng.integers(0, len(h), 9)
+    if not exit_:
+        assert np.array_equal(gpu_matrix(c, n, h), oracle.distance_matrix(n, h))
+    rk, ds = gpu_rank(c, n, h, t)
+    ork, ods = oracle.rank(n, h, t)
+    assert np.array_equal(ds, ods) and np.array_equal(rk, ork)
+    c.close()
 
 
 @pytest.mark.parametrize("seed", range(3))
