@@ -336,6 +336,7 @@ __device__ __forceinline__ void wave_sync_lds()
 
 constexpr int kDiffStride = 65;   // column 64 of each row is a sink for "past the image"
 constexpr int kMapCap = 1024;     // slices mapped per round
+constexpr uint32_t kOwn = 2;       // slices of a pair done by the lane that projected it
 
 // LDS of a workgroup owning G images: the difference arrays, the per-wave
 // survivor rings and slice maps, and the frames.  The per-pair records of the
@@ -372,7 +373,7 @@ __device__ __forceinline__ uint32_t lane_fetch(uint32_t v, int src_x4)
 // its slice's pair from the owning lane with cross-lane permutes and adds the
 // slice's single / double ranges to the row's difference array.
 template <int G>
-__device__ void process_batch(GenLds<G>& L, int wave, int lane, uint32_t head, uint32_t cnt,
+__device__ __forceinline__ void process_batch(GenLds<G>& L, int wave, int lane, uint32_t head, uint32_t cnt,
                               const float4* __restrict__ verts)
 {
     wave_sync_lds();
@@ -417,14 +418,61 @@ __device__ void process_batch(GenLds<G>& L, int wave, int lane, uint32_t head, u
         sx1 = (xb - xa) * i1; sy1 = (yb - ya) * i1;
         sx2 = (xc - xb) * i2; sy2 = (yc - yb) * i2;
     }
-    const uint32_t incl = wave_inclusive_scan(nrows, lane);
-    const uint32_t pre = incl - nrows;
+    // One slice (pair record, row r, image gi): Sec. 3.1.2 steps 1-6 and the
+    // difference-row updates.
+    auto slice = [&](double Ra, double Rb, double Rxa, double Rya, double Rsxl, double Rsyl, double Rxb, double Ryb,
+                     double Rsx1, double Rsy1, double Rsx2, double Rsy2, int r, uint32_t gi) {
+        const double beta = (double)r - 31.5;
+        // step 1: crossings on the long edge and on the short edge whose
+        // z-range holds beta
+        const double hl = beta - Ra;
+        const double e0x = Rxa + hl * Rsxl, e0y = Rya + hl * Rsyl;
+        const bool low = beta <= Rb;
+        const double h1 = low ? hl : beta - Rb;
+        const double e1x = (low ? Rxa : Rxb) + h1 * (low ? Rsx1 : Rsx2);
+        const double e1y = (low ? Rya : Ryb) + h1 * (low ? Rsy1 : Rsy2);
+        // steps 3-4: squared distances from the axis; single range (lo, hi)
+        const double d0 = e0x * e0x + e0y * e0y, d1 = e1x * e1x + e1y * e1y;
+        const double lo2 = fmin(d0, d1), hi2 = fmax(d0, d1);
+        // steps 5-6: double range (|C|, lo) iff the foot C of the axis on
+        // line E0E1 lies strictly inside the segment
+        const double dx = e1x - e0x, dy = e1y - e0y;
+        const double dd = dx * dx + dy * dy;
+        const bool between = (e0x * dx + e0y * dy) < 0.0 && (e1x * dx + e1y * dy) > 0.0;
+        const double cr = e0x * e1y - e0y * e1x;
+        const bool ok = lo2 <= 1.0e300 && hi2 <= 1.0e300;
+        int c_lo = first_col(lo2), c_hi = first_col(hi2);
+        int c_c = between ? min(first_col_ratio(cr * cr, dd), c_lo) : c_lo;
+        if (!ok) { c_lo = c_hi = c_c = 64; }
+        // +2 on [c_c, c_lo), +1 on [c_lo, c_hi) as a difference row: +2 at
+        // c_c, -1 at c_lo, -1 at c_hi, with coinciding columns merged and
+        // zero or past-the-image (column 64) updates dropped (LDS atomics
+        // are the slice stage's most expensive instructions)
+        uint32_t v0 = 2u, v1 = (uint32_t)-1, v2 = (uint32_t)-1;
+        if (c_c == c_lo) { v0 = 0u; v1 = 1u; }
+        if (c_lo == c_hi) { v1 -= 1u; v2 = 0u; }
+        uint32_t* row = L.diff[gi] + r * kDiffStride;
+        if (v0 != 0u && c_c < 64) atomicAdd(row + c_c, v0);
+        if (v1 != 0u && c_lo < 64) atomicAdd(row + c_lo, v1);
+        if (v2 != 0u && c_hi < 64) atomicAdd(row + c_hi, v2);
+    };
+
+    // The first kOwn slices of every pair stay on the lane that projected it
+    // (no cross-lane reads; most pairs span only a few rows) ...
+#pragma unroll
+    for (uint32_t k = 0; k < kOwn; ++k)
+        if (k < nrows) slice(za, zb, xa, ya, sxl, syl, xb, yb, sx1, sy1, sx2, sy2, r0 + (int)k, g);
+    // ... and the rest are spread evenly over the lanes, each reading its
+    // slice's pair record from the owning lane.
+    const uint32_t nrest = nrows > kOwn ? nrows - kOwn : 0u;
+    const uint32_t incl = wave_inclusive_scan(nrest, lane);
+    const uint32_t pre = incl - nrest;
     const uint32_t total = __shfl(incl, 63, 64);
-    // row of slice k of this pair = r0 + (k - pre); stored with its image
-    key = ((uint32_t)(r0 - (int)pre + 8192) << 2) | g;
+    // row of slice k of this pair = r0 + kOwn + (k - pre); stored with its image
+    key = ((uint32_t)(r0 + (int)kOwn - (int)pre + 8192) << 2) | g;
 
     for (uint32_t base = 0; base < total; base += kMapCap) {
-        const uint32_t lo = max(pre, base), hi = min(pre + nrows, base + kMapCap);
+        const uint32_t lo = max(pre, base), hi = min(pre + nrest, base + kMapCap);
         for (uint32_t k = lo; k < hi; ++k) L.map[wave][k - base] = (uint8_t)lane;
         wave_sync_lds();
         const uint32_t n_round = min(total - base, (uint32_t)kMapCap);
@@ -441,40 +489,7 @@ __device__ void process_batch(GenLds<G>& L, int wave, int lane, uint32_t head, u
             const double Rsx2 = lane_fetch(sx2, src), Rsy2 = lane_fetch(sy2, src);
             if (!valid) continue;
             const int r = (int)(m >> 2) - 8192 + (int)(base + k);
-            const uint32_t gi = m & (G - 1);
-            const double beta = (double)r - 31.5;
-            // Sec. 3.1.2 step 1: crossings on the long edge and on the short
-            // edge whose z-range holds beta
-            const double hl = beta - Ra;
-            const double e0x = Rxa + hl * Rsxl, e0y = Rya + hl * Rsyl;
-            const bool low = beta <= Rb;
-            const double h1 = low ? hl : beta - Rb;
-            const double e1x = (low ? Rxa : Rxb) + h1 * (low ? Rsx1 : Rsx2);
-            const double e1y = (low ? Rya : Ryb) + h1 * (low ? Rsy1 : Rsy2);
-            // steps 3-4: squared distances from the axis; single range (lo, hi)
-            const double d0 = e0x * e0x + e0y * e0y, d1 = e1x * e1x + e1y * e1y;
-            const double lo2 = fmin(d0, d1), hi2 = fmax(d0, d1);
-            // steps 5-6: double range (|C|, lo) iff the foot C of the axis on
-            // line E0E1 lies strictly inside the segment
-            const double dx = e1x - e0x, dy = e1y - e0y;
-            const double dd = dx * dx + dy * dy;
-            const bool between = (e0x * dx + e0y * dy) < 0.0 && (e1x * dx + e1y * dy) > 0.0;
-            const double cr = e0x * e1y - e0y * e1x;
-            const bool ok = lo2 <= 1.0e300 && hi2 <= 1.0e300;
-            int c_lo = first_col(lo2), c_hi = first_col(hi2);
-            int c_c = between ? min(first_col_ratio(cr * cr, dd), c_lo) : c_lo;
-            if (!ok) { c_lo = c_hi = c_c = 64; }
-            // +2 on [c_c, c_lo), +1 on [c_lo, c_hi) as a difference row: +2 at
-            // c_c, -1 at c_lo, -1 at c_hi, with coinciding columns merged and
-            // zero or past-the-image (column 64) updates dropped (LDS atomics
-            // are the slice stage's most expensive instructions)
-            uint32_t v0 = 2u, v1 = (uint32_t)-1, v2 = (uint32_t)-1;
-            if (c_c == c_lo) { v0 = 0u; v1 = 1u; }
-            if (c_lo == c_hi) { v1 -= 1u; v2 = 0u; }
-            uint32_t* row = L.diff[gi] + r * kDiffStride;
-            if (v0 != 0u && c_c < 64) atomicAdd(row + c_c, v0);
-            if (v1 != 0u && c_lo < 64) atomicAdd(row + c_lo, v1);
-            if (v2 != 0u && c_hi < 64) atomicAdd(row + c_hi, v2);
+            slice(Ra, Rb, Rxa, Rya, Rsxl, Rsyl, Rxb, Ryb, Rsx1, Rsy1, Rsx2, Rsy2, r, m & (G - 1));
         }
         wave_sync_lds();
     }
