@@ -37,14 +37,16 @@ constexpr uint32_t kPad = 0xFFFFFFFFu;
 
 // ------------------------------------------------------------------ delta prep
 
+constexpr int kDeltaWaves = 8;   // wavefronts per delta-prep workgroup (rows split among them; 8 measured best)
+
 // One block per group of 16 images; thread (row-in-step, lane) with
 // lane = 16 * q + i writes columns 16 q .. 16 q + 15 of image i.
 __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
                             int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
                             uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm, uint32_t grp)
 {
-    __shared__ uint32_t smax[4][kGroup];
-    __shared__ int64_t ssum[4][kGroup];
+    __shared__ uint32_t smax[kDeltaWaves][kGroup];
+    __shared__ int64_t ssum[kDeltaWaves][kGroup];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, q = lane >> 4;
     const uint32_t slot = grp * kGroup + i;
@@ -54,7 +56,7 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
 
     uint32_t mx = 0;
     int64_t ss = 0;
-    for (int r = wave; r < NB; r += 4) {
+    for (int r = wave; r < NB; r += kDeltaWaves) {
         int32_t d[16];
         if (live) {
             const uint32_t* row = images + (size_t)img * NPIX + r * NB + 16 * q;
@@ -109,7 +111,7 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
             *reinterpret_cast<uint4*>(planes + 2 * plane_stride + frag) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
     }
     if (perm) return;   // the haystack's statistics come from k_hay_stats
-    // per-image reductions: 4 lanes (q) per wave and 4 waves share image i
+    // per-image reductions: 4 lanes (q) per wave and kDeltaWaves waves share image i
 #pragma unroll
     for (int o = 16; o < 64; o <<= 1) {
         mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
@@ -119,14 +121,16 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
     __syncthreads();
     if (tid < kGroup) {
         const uint32_t im = grp * kGroup + tid;
-        uint32_t m = max(max(smax[0][tid], smax[1][tid]), max(smax[2][tid], smax[3][tid]));
-        int64_t s = ssum[0][tid] + ssum[1][tid] + ssum[2][tid] + ssum[3][tid];
+        uint32_t m = 0;
+        int64_t s = 0;
+#pragma unroll
+        for (int w = 0; w < kDeltaWaves; ++w) { m = max(m, smax[w][tid]); s += ssum[w][tid]; }
         maxabs[im] = im < n ? m : kPad;
         if (sumsq) sumsq[im] = im < n ? s : 0;
     }
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kDeltaWaves * 64)
 k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
              int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
              uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm)
@@ -825,7 +829,7 @@ __device__ __forceinline__ uint32_t job_of(const SearchJob* __restrict__ jobs, u
     return lo;
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kDeltaWaves * 64)
 k_needle_prep_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
 {
     const SearchJob& J = jobs[job_of<0>(jobs, njobs, blockIdx.x)];
@@ -866,7 +870,7 @@ k_hay_assign_batched(const SearchJob* __restrict__ jobs)
     hay_assign_block(J.hp.maxabs_img, J.A.nh, J.hp.ngroups * kGroup, J.hp.perm, J.hp.maxabs);
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kDeltaWaves * 64)
 k_hay_prep_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
 {
     const SearchJob& J = jobs[job_of<3>(jobs, njobs, blockIdx.x)];
@@ -949,7 +953,8 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
             if (e != hipSuccess) return e;
         }
     }
-    hipLaunchKernelGGL(k_delta_prep, dim3(p.ngroups), dim3(256), 0, s, images, n, needle_side, p.planes, p.ngroups,
+    hipLaunchKernelGGL(k_delta_prep, dim3(p.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, needle_side, p.planes,
+                       p.ngroups,
                        p.sumsq, p.maxabs, p.perm);
     return hipGetLastError();
 }
@@ -1025,7 +1030,8 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
         hipError_t e_ = hipGetLastError();                 \
         if (e_ != hipSuccess) return e_;                   \
     } while (0)
-    if (T.needle_groups) RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(256), 0, s, jobs, njobs);
+    if (T.needle_groups)
+        RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
     if (T.hay_slots)
         RICI_LAUNCH(k_hay_init_batched, dim3((uint32_t)((T.hay_slots + 255) / 256)), dim3(256), 0, s, jobs, njobs,
                     T.hay_slots);
@@ -1033,7 +1039,8 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
         RICI_LAUNCH(k_hay_stats_batched, dim3((uint32_t)((T.hay_images + 3) / 4)), dim3(256), 0, s, jobs, njobs,
                     T.hay_images);
     RICI_LAUNCH(k_hay_assign_batched, dim3(njobs), dim3(1024), 0, s, jobs);
-    if (T.hay_groups) RICI_LAUNCH(k_hay_prep_batched, dim3((uint32_t)T.hay_groups), dim3(256), 0, s, jobs, njobs);
+    if (T.hay_groups)
+        RICI_LAUNCH(k_hay_prep_batched, dim3((uint32_t)T.hay_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
     if (T.needles)
         RICI_LAUNCH(k_true_distance_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
                     T.needles);
