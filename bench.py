@@ -567,7 +567,10 @@ def main():
         roof_gen = {"bound": "alu", "achieved": gen_achieved, "peak": PEAK_ALU_TOPS, "unit": "TFLOP/s",
                     "frac": gen_achieved / PEAK_ALU_TOPS, "traffic": measured_traffic("k_gen"),
                     "counters": measured_busy("k_gen"), "kernel": "k_gen", "ops_per_launch": gen_ops,
-                    "ops_basis": "oracle work counters on the CPU-baseline sample"}
+                    "ops_basis": "oracle work counters on the CPU-baseline sample",
+                    "note": "the algorithmic count credits every (image, triangle) pair, as the method visits "
+                            "all triangles per image; the kernel's exact bounding-sphere culls skip most of them, "
+                            "so frac can exceed 1; counters.valu_busy is the hardware issue utilisation"}
 
     batched = batched_vs_plain(ctx, args.batch_meshes) if args.batch_meshes > 0 else None
     others = per_config(ctx) if args.other_configs else None
