@@ -914,7 +914,6 @@ k_fallback_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
     }
 }
 
-__global__ void k_zero_counter(uint32_t* __restrict__ c) { if (threadIdx.x == 0) *c = 0u; }
 __global__ void k_zero_counters8(uint32_t* __restrict__ c) { if (threadIdx.x < 8) c[threadIdx.x] = 0u; }
 
 }  // namespace
