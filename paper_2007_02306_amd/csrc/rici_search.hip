@@ -618,11 +618,21 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         colok[nb] = A.hmax[slot] <= kSlow;            // padding and |D| > 127 excluded
         col[nb] = colok[nb] ? A.hperm[slot] : 0u;     // original haystack index
     }
+    // rank mode: the kWN waves sharing a needle row add their counts in LDS
+    // (the idle ring head), then one global atomic per row of the tile
+    uint32_t* rowcnt = reinterpret_cast<uint32_t*>(lds);
+    const bool ranks = A.matrix == nullptr;
+    if (ranks) {
+        __syncthreads();   // every wave is done with the ring, its last reads included
+        for (int j = tid; j < C::BM; j += C::kThreads) rowcnt[j] = 0u;
+        __syncthreads();
+    }
 #pragma unroll
     for (int mb = 0; mb < C::kMB; ++mb) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const uint32_t row = (ga0 + wm * C::kMB + mb) * 16 + 4 * rq + v;
+            const int lrow = (wm * C::kMB + mb) * 16 + 4 * rq + v;   // row within the tile
+            const uint32_t row = ga0 * 16 + (uint32_t)lrow;
             const bool rowok = row < A.nn;
             if (A.matrix) {
                 if (rowok && A.nmax[row] <= kSlow) {
@@ -640,8 +650,15 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
                 cnt += __shfl_xor(cnt, 2, 64);
                 cnt += __shfl_xor(cnt, 4, 64);
                 cnt += __shfl_xor(cnt, 8, 64);
-                if (cl == 0 && rowok && cnt) atomicAdd(A.rank + row, cnt);
+                if (cl == 0 && rowok && cnt) atomicAdd(rowcnt + lrow, cnt);
             }
+        }
+    }
+    if (ranks) {
+        __syncthreads();
+        for (int j = tid; j < C::BM; j += C::kThreads) {
+            const uint32_t c = rowcnt[j], row = ga0 * 16 + (uint32_t)j;
+            if (c && row < A.nn) atomicAdd(A.rank + row, c);
         }
     }
 }
