@@ -339,16 +339,33 @@ def batched_vs_plain(ctx, meshes: int, seed: int = 4, reps: int = 3):
             best = dt if best is None else min(best, dt)
         return best
 
+    def snapshot():
+        """Per-image sums of the counts (int64), ranks and true distances of
+        every mesh, as left in the plan's output buffers by the last run."""
+        torch.cuda.synchronize()
+        out = []
+        for k in range(len(jobs)):
+            im = plan.images[k]
+            out.append((im.reshape(im.shape[0], -1).sum(dim=1, dtype=torch.int64).cpu(),
+                        plan.rank[k].cpu().clone(), plan.true_distance[k].cpu().clone()))
+        return out
+
     t_plain = timeit(plain)
+    ref = snapshot()
     t_batch = timeit(plan.run)
+    got = snapshot()
     ctx.sync()
     plain_ctx.sync()
+    check = {"per_image_count_sums_equal": all(torch.equal(a[0], b[0]) for a, b in zip(ref, got)),
+             "ranks_equal": all(torch.equal(a[1], b[1]) for a, b in zip(ref, got)),
+             "true_distances_equal": all(torch.equal(a[2], b[2]) for a, b in zip(ref, got))}
     n_img = sum(v for v, _ in sizes)
     pairs = sum(v * v for v, _ in sizes)
     out = {"meshes": meshes, "images": n_img, "triangles": sum(t for _, t in sizes), "distance_pairs": pairs,
            "plain_s": t_plain, "batched_s": t_batch, "speedup": t_plain / t_batch,
            "batched_rici_per_s": n_img / t_batch, "plain_rici_per_s": n_img / t_plain,
            "plan_scratch_gb": plan.scratch_bytes / 1e9,
+           "batched_equals_plain": check,
            "autotuned": {"gen_images_per_group": knobs[0], "search_tile_m": knobs[1], "tune_s": tune_s,
                          "candidates_ms": {f"{g}x{m}": ms for _, (g, m), ms in tuner.measurements}},
            "plain_knobs": {"gen_images_per_group": plain_ctx.get_tuning("gen_images_per_group"),
