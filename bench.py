@@ -263,6 +263,8 @@ def per_config(ctx, reps: int = 3):
                      "rici_per_s": (nh + (0 if nimg is himg else nn)) / wall,
                      "image_triangle_pairs_per_s": pairs_gen / (gen_ms * 1e-3),
                      "distance_pairs_per_s": float(nn) * nh / (search_ms * 1e-3),
+                     "search_int8_peak_frac": float(nn) * nh * OPS_PER_PAIR / (search_ms * 1e-3) / 1e12
+                                              / PEAK_INT8_TOPS,
                      "ranks_per_s": nn / wall,
                      "max_rank": int(rank.max())}
         if name == "clutter":
