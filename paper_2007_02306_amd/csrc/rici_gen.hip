@@ -264,40 +264,44 @@ k_gen_clusters(const float4* __restrict__ cull, uint32_t nt, float4* __restrict_
 // ------------------------------------------------------------ exact pieces
 
 // Per-image frame in FP64 (Eq. 1), with the second rotation and the in-plane
-// y row pre-multiplied by 64/R so that projected coordinates come out in bin
-// units: bin radii are c + 1/2 and row heights r - 31.5, exactly.
+// y row pre-multiplied by 128/R so that projected coordinates come out in
+// half-bin units: bin radii are 2c + 1 and row heights 2r - 63, all small odd
+// integers.  (Scaling by a power of two changes no rounding, so every
+// decision is the one made in bin units.)
 struct Frame {
     double sx, sy, sz;        // Spin Vertex
     double nax, nay;          // first rotation (about z)
-    double nax_d, nay_d;      // first rotation x 64/R (y coordinate)
-    double nbx_d, nbz_d;      // second rotation (about y) x 64/R
+    double nax_d, nay_d;      // first rotation x 128/R (y coordinate)
+    double nbx_d, nbz_d;      // second rotation (about y) x 128/R
     double pad;
 };
 
-// First column c in [0, 64] whose bin radius c + 1/2 exceeds sqrt(s), s >= 0,
-// decided by an exact FP64 comparison.  The guess comes from the hardware FP32
-// square root (about 1 ulp, no refinement), biased low by 2e-5 so that it is
-// the answer or one below it.
+// First column c in [0, 64] whose bin radius exceeds sqrt(s), s >= 0 the
+// squared distance in half-bin units: the first c with (2c + 1)^2 > s.  The
+// left side is an integer, so comparing it with floor(s) is exact; s is
+// clamped to 16640 = 129^2 - 1 (c = 64 for all larger s, and for NaN).  The
+// guess comes from the hardware FP32 square root (about 1 ulp), biased low by
+// 2e-5 so that it is the answer or one below it, and never above 64.
 __device__ __forceinline__ int first_col(double s)
 {
-    float f = __builtin_amdgcn_sqrtf(fminf((float)s, 1.0e4f) * 0.99998f);
-    int c = (int)floorf(f - 0.5f) + 1;
-    c = min(c, 64);
-    const double t = (double)c + 0.5;
-    c += (c < 64 && t * t <= s) ? 1 : 0;
-    return c;
+    const uint32_t t = (uint32_t)fmin(s, 16640.0);
+    const float f = __builtin_amdgcn_sqrtf((float)t);
+    const uint32_t c = (uint32_t)fmaf(f, 0.49999f, 0.5f) & 127u;   // <= 64; the mask keeps the square in 24 bits
+    const uint32_t u = 2 * c + 1;
+    return (int)(c + (u * u <= t ? 1u : 0u));
 }
 
-// Same for the ratio cr2 / dd (dd > 0): first c with (c + 1/2)^2 dd > cr2.
+// Same for the ratio cr2 / dd (dd > 0): the first c with (2c + 1)^2 dd > cr2,
+// decided by an FP64 comparison of the product; the guess also allows for the
+// hardware reciprocal's error.  Results above 64 are not exact, and callers
+// clamp them with a column that is at most 64.
 __device__ __forceinline__ int first_col_ratio(double cr2, double dd)
 {
     const double approx = cr2 * __builtin_amdgcn_rcp(dd);
-    float f = __builtin_amdgcn_sqrtf(fminf((float)approx, 1.0e4f) * 0.99990f);
-    int c = (int)floorf(f - 0.5f) + 1;
-    c = min(max(c, 0), 64);
-    const double t = (double)c + 0.5;
-    c += (c < 64 && t * t * dd <= cr2) ? 1 : 0;
-    return c;
+    const float f = __builtin_amdgcn_sqrtf(fminf((float)approx, 16640.0f));
+    const uint32_t c = (uint32_t)fmaf(f, 0.49995f, 0.5f) & 127u;
+    const uint32_t u = 2 * c + 1;
+    return (int)(c + ((double)(u * u) * dd <= cr2 ? 1u : 0u));
 }
 
 __device__ __forceinline__ void csort(double& x0, double& y0, double& z0, double& x1, double& y1, double& z1)
@@ -366,7 +370,7 @@ __device__ __forceinline__ uint32_t lane_fetch(uint32_t v, int src_x4)
 
 // Exact work for up to 64 queued (image, triangle) pairs of one wavefront.
 //
-// Stage A: lane i projects pair i (Eq. 2-4 in FP64, bin units), sorts its
+// Stage A: lane i projects pair i (Eq. 2-4 in FP64, half-bin units), sorts its
 // vertices by height and keeps, in registers, the edge slopes and the first
 // row of its beta extent.  Stage B: the slices of all pairs (one per row in
 // the extent) are spread evenly over the lanes; a lane reads the record of
@@ -396,8 +400,8 @@ __device__ __forceinline__ void process_batch(GenLds<G>& L, int wave, int lane, 
             const double py = (double)v[k].y - F.sy;
             const double pz = (double)v[k].z - F.sz;
             const double qx = F.nax * px + F.nay * py;        // Eq. 3 (x)
-            Y[k] = -F.nay_d * px + F.nax_d * py;              // Eq. 3 (y), bin units
-            X[k] = F.nbz_d * qx - F.nbx_d * pz;               // Eq. 4, bin units
+            Y[k] = -F.nay_d * px + F.nax_d * py;              // Eq. 3 (y), half-bin units
+            X[k] = F.nbz_d * qx - F.nbx_d * pz;               // Eq. 4, half-bin units
             Z[k] = F.nbx_d * qx + F.nbz_d * pz;
         }
         double xc = X[2], yc = Y[2], zc = Z[2];
@@ -405,9 +409,10 @@ __device__ __forceinline__ void process_batch(GenLds<G>& L, int wave, int lane, 
         csort(xa, ya, za, xb, yb, zb);
         csort(xb, yb, zb, xc, yc, zc);
         csort(xa, ya, za, xb, yb, zb);
-        // rows r with r - 31.5 in (z_a, z_c]: a vertex is above iff z >= beta
-        const double f0 = floor(fmin(fmax(za + 31.5, -2.0), 70.0)) + 1.0;
-        const double f1 = floor(fmin(fmax(zc + 31.5, -2.0), 70.0));
+        // rows r with 2r - 63 in (z_a, z_c]: a vertex is above iff z >= beta
+        // (z / 2 + 31.5 rounds as z + 31.5 does in bin units)
+        const double f0 = floor(fmin(fmax(fma(za, 0.5, 31.5), -2.0), 70.0)) + 1.0;
+        const double f1 = floor(fmin(fmax(fma(zc, 0.5, 31.5), -2.0), 70.0));
         r0 = max((int)f0, 0);
         const int r1 = min((int)f1, 63);
         const double il = recip(zc - za);
@@ -422,7 +427,7 @@ __device__ __forceinline__ void process_batch(GenLds<G>& L, int wave, int lane, 
     // difference-row updates.
     auto slice = [&](double Ra, double Rb, double Rxa, double Rya, double Rsxl, double Rsyl, double Rxb, double Ryb,
                      double Rsx1, double Rsy1, double Rsx2, double Rsy2, int r, uint32_t gi) {
-        const double beta = (double)r - 31.5;
+        const double beta = (double)(2 * r - 63);
         // step 1: crossings on the long edge and on the short edge whose
         // z-range holds beta
         const double hl = beta - Ra;
@@ -432,16 +437,18 @@ __device__ __forceinline__ void process_batch(GenLds<G>& L, int wave, int lane, 
         const double e1x = (low ? Rxa : Rxb) + h1 * (low ? Rsx1 : Rsx2);
         const double e1y = (low ? Rya : Ryb) + h1 * (low ? Rsy1 : Rsy2);
         // steps 3-4: squared distances from the axis; single range (lo, hi)
+        // (first_col is monotone, so the columns of the two ends order as
+        // their distances do)
         const double d0 = e0x * e0x + e0y * e0y, d1 = e1x * e1x + e1y * e1y;
-        const double lo2 = fmin(d0, d1), hi2 = fmax(d0, d1);
+        const int k0 = first_col(d0), k1 = first_col(d1);
         // steps 5-6: double range (|C|, lo) iff the foot C of the axis on
         // line E0E1 lies strictly inside the segment
         const double dx = e1x - e0x, dy = e1y - e0y;
         const double dd = dx * dx + dy * dy;
         const bool between = (e0x * dx + e0y * dy) < 0.0 && (e1x * dx + e1y * dy) > 0.0;
         const double cr = e0x * e1y - e0y * e1x;
-        const bool ok = lo2 <= 1.0e300 && hi2 <= 1.0e300;
-        int c_lo = first_col(lo2), c_hi = first_col(hi2);
+        const bool ok = d0 <= 1.0e300 && d1 <= 1.0e300;
+        int c_lo = min(k0, k1), c_hi = max(k0, k1);
         int c_c = between ? min(first_col_ratio(cr * cr, dd), c_lo) : c_lo;
         if (!ok) { c_lo = c_hi = c_c = 64; }
         // +2 on [c_c, c_lo), +1 on [c_lo, c_hi) as a difference row: +2 at
@@ -451,7 +458,7 @@ __device__ __forceinline__ void process_batch(GenLds<G>& L, int wave, int lane, 
         uint32_t v0 = 2u, v1 = (uint32_t)-1, v2 = (uint32_t)-1;
         if (c_c == c_lo) { v0 = 0u; v1 = 1u; }
         if (c_lo == c_hi) { v1 -= 1u; v2 = 0u; }
-        uint32_t* row = L.diff[gi] + r * kDiffStride;
+        uint32_t* row = L.diff[gi] + __umul24((uint32_t)r, (uint32_t)kDiffStride);
         if (v0 != 0u && c_c < 64) atomicAdd(row + c_c, v0);
         if (v1 != 0u && c_lo < 64) atomicAdd(row + c_lo, v1);
         if (v2 != 0u && c_hi < 64) atomicAdd(row + c_hi, v2);
@@ -522,7 +529,7 @@ __device__ void gen_images(GenLds<G>& L, const GenJob& J, uint32_t img0, float R
                 atomicOr(err, 2u);
                 live = false;
             } else {
-                const double inv_d = (double)NB / (double)Rf;
+                const double inv_d = (double)(2 * NB) / (double)Rf;
                 f.sx = sp[0]; f.sy = sp[1]; f.sz = sp[2];
                 const double nx = sn[0], ny = sn[1], nz = sn[2];
                 // Eq. 1: [N_ax, N_ay] = Normalize[S_nx, S_ny]; identity if both vanish
