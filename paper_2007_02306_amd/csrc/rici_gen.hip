@@ -276,30 +276,48 @@ struct Frame {
     double pad;
 };
 
+// Column guesses.  In half-bin units the bin radii are the odd integers
+// 2c + 1, so the first column whose radius exceeds sqrt(s) is the first c
+// with (2c + 1)^2 > s.  Odd squares are 1 mod 8 and at least 8 apart, so each
+// run of 8 consecutive integers 8i .. 8i + 7 holds at most one of them: a
+// table entry per run (the answer at 8i) is the answer or one below it for
+// every s in the run, and one exact comparison settles it.  s is clamped to
+// 16640 = 129^2 - 1, the last value whose answer is 64.
+constexpr int kColTab = 16640 / 8 + 1;
+
+// entry i: the first c with (2c + 1)^2 > 8i, i.e. (isqrt(8i) + 1) / 2
+__device__ void fill_col_table(uint8_t* __restrict__ tab, int tid, int nthreads)
+{
+    for (int i = tid; i < kColTab; i += nthreads) {
+        const uint32_t x = 8u * (uint32_t)i;
+        uint32_t k = (uint32_t)sqrtf((float)x);
+        while (k * k > x) --k;
+        while ((k + 1) * (k + 1) <= x) ++k;
+        tab[i] = (uint8_t)((k + 1) / 2);
+    }
+}
+
 // First column c in [0, 64] whose bin radius exceeds sqrt(s), s >= 0 the
-// squared distance in half-bin units: the first c with (2c + 1)^2 > s.  The
-// left side is an integer, so comparing it with floor(s) is exact; s is
-// clamped to 16640 = 129^2 - 1 (c = 64 for all larger s, and for NaN).  The
-// guess comes from the hardware FP32 square root (about 1 ulp), biased low by
-// 2e-5 so that it is the answer or one below it, and never above 64.
-__device__ __forceinline__ int first_col(double s)
+// squared distance in half-bin units (c = 64 for s >= 16640 and for NaN).
+// (2c + 1)^2 is an integer, so comparing it with floor(s) is exact.
+__device__ __forceinline__ int first_col(const uint8_t* __restrict__ tab, double s)
 {
     const uint32_t t = (uint32_t)fmin(s, 16640.0);
-    const float f = __builtin_amdgcn_sqrtf((float)t);
-    const uint32_t c = (uint32_t)fmaf(f, 0.49999f, 0.5f) & 127u;   // <= 64; the mask keeps the square in 24 bits
+    const uint32_t c = tab[t >> 3];
     const uint32_t u = 2 * c + 1;
     return (int)(c + (u * u <= t ? 1u : 0u));
 }
 
 // Same for the ratio cr2 / dd (dd > 0): the first c with (2c + 1)^2 dd > cr2,
-// decided by an FP64 comparison of the product; the guess also allows for the
-// hardware reciprocal's error.  Results above 64 are not exact, and callers
-// clamp them with a column that is at most 64.
-__device__ __forceinline__ int first_col_ratio(double cr2, double dd)
+// decided by an FP64 comparison of the product.  The table is read at an
+// estimate of the ratio from the hardware reciprocal; an estimate within 1 of
+// the ratio still lands in a run whose entry is the answer or one below it.
+// Results above 64 are not exact, and callers clamp them with a column that
+// is at most 64.
+__device__ __forceinline__ int first_col_ratio(const uint8_t* __restrict__ tab, double cr2, double dd)
 {
     const double approx = cr2 * __builtin_amdgcn_rcp(dd);
-    const float f = __builtin_amdgcn_sqrtf(fminf((float)approx, 16640.0f));
-    const uint32_t c = (uint32_t)fmaf(f, 0.49995f, 0.5f) & 127u;
+    const uint32_t c = tab[(uint32_t)fmin(approx, 16640.0) >> 3];
     const uint32_t u = 2 * c + 1;
     return (int)(c + ((double)(u * u) * dd <= cr2 ? 1u : 0u));
 }
@@ -351,6 +369,7 @@ struct GenLds {
     uint32_t diff[G][NB * kDiffStride];
     uint32_t ring[kWaves][kRing];
     uint8_t map[kWaves][kMapCap]; // slice -> survivor lane
+    uint8_t coltab[(kColTab + 15) & ~15];   // column guesses (first_col)
     Frame frames[G];
     float cp[G][8];               // FP32 cull parameters
 };
@@ -440,7 +459,7 @@ __device__ __forceinline__ void process_batch(GenLds<G>& L, int wave, int lane, 
         // (first_col is monotone, so the columns of the two ends order as
         // their distances do)
         const double d0 = e0x * e0x + e0y * e0y, d1 = e1x * e1x + e1y * e1y;
-        const int k0 = first_col(d0), k1 = first_col(d1);
+        const int k0 = first_col(L.coltab, d0), k1 = first_col(L.coltab, d1);
         // steps 5-6: double range (|C|, lo) iff the foot C of the axis on
         // line E0E1 lies strictly inside the segment
         const double dx = e1x - e0x, dy = e1y - e0y;
@@ -449,7 +468,7 @@ __device__ __forceinline__ void process_batch(GenLds<G>& L, int wave, int lane, 
         const double cr = e0x * e1y - e0y * e1x;
         const bool ok = d0 <= 1.0e300 && d1 <= 1.0e300;
         int c_lo = min(k0, k1), c_hi = max(k0, k1);
-        int c_c = between ? min(first_col_ratio(cr * cr, dd), c_lo) : c_lo;
+        int c_c = between ? min(first_col_ratio(L.coltab, cr * cr, dd), c_lo) : c_lo;
         if (!ok) { c_lo = c_hi = c_c = 64; }
         // +2 on [c_c, c_lo), +1 on [c_lo, c_hi) as a difference row: +2 at
         // c_c, -1 at c_lo, -1 at c_hi, with coinciding columns merged and
@@ -653,6 +672,7 @@ __global__ void __launch_bounds__(kWaves * 64, kGenWavesPerEU<G>)
 k_gen(GenJob J, float Rf, uint32_t* __restrict__ err)
 {
     __shared__ GenLds<G> L;
+    fill_col_table(L.coltab, threadIdx.x, kWaves * 64);   // published by gen_images' first barrier
     gen_images<G>(L, J, blockIdx.x * G, Rf, err);
 }
 
@@ -668,6 +688,7 @@ k_gen_batched(const GenJob* __restrict__ jobs, uint32_t njobs, uint32_t total_it
 {
     __shared__ GenLds<G> L;
     __shared__ uint32_t s_item;
+    fill_col_table(L.coltab, threadIdx.x, kWaves * 64);   // published by the first barrier below
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
         __syncthreads();
