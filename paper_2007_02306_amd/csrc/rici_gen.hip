@@ -358,7 +358,7 @@ __device__ __forceinline__ void wave_sync_lds()
 
 constexpr int kDiffStride = 65;   // column 64 of each row is a sink for "past the image"
 constexpr int kMapCap = 1024;     // slices mapped per round
-constexpr uint32_t kOwn = 2;       // slices of a pair done by the lane that projected it
+constexpr uint32_t kOwn = 3;       // slices of a pair done by the lane that projected it
 
 // LDS of a workgroup owning G images: the difference arrays, the per-wave
 // survivor rings and slice maps, and the frames.  The per-pair records of the
