@@ -396,12 +396,27 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     const uint32_t ga0 = tm * C::GA, gb0 = tn * C::GB;
 
     // q phase needed iff some usable haystack image of the tile has
-    // 15 < |D| <= 127; a tile without any usable haystack image is skipped
+    // 15 < |D| <= 127; a tile without any usable haystack image is skipped.
+    // The same loads fill the tile's usable-column flags and (rank mode) its
+    // needle thresholds in LDS past the ring, for the epilogue and the early
+    // exit votes: issued together, they cost one load latency per tile, and
+    // the epilogue reads no global memory in rank mode.
+    int32_t* thr_l = reinterpret_cast<int32_t*>(lds + C::kThr);
+    uint8_t* col_l = reinterpret_cast<uint8_t*>(lds + C::kCol);
+    const bool ranks = A.matrix == nullptr;
     int flags = 0;
-    for (int j = tid; j < C::BN; j += C::kThreads) {
-        const uint32_t m = A.hmax[gb0 * 16 + j];
-        flags |= (m > kSmallD && m <= kSlow) ? 1 : 0;
-        flags |= (m <= kSlow) ? 2 : 0;
+    constexpr int kPro = C::BM > C::BN ? C::BM : C::BN;
+    for (int j = tid; j < kPro; j += C::kThreads) {
+        // both loads before either value is used
+        const uint32_t m = j < C::BN ? A.hmax[gb0 * 16 + j] : kPad;
+        const uint32_t row = ga0 * 16 + j;
+        const int32_t t = (ranks && j < C::BM && row < A.nn) ? A.thr[row] : INT_MIN;
+        if (j < C::BN) {
+            flags |= (m > kSmallD && m <= kSlow) ? 1 : 0;
+            flags |= (m <= kSlow) ? 2 : 0;
+            col_l[j] = m <= kSlow ? 1 : 0;               // padding and |D| > 127 excluded
+        }
+        if (j < C::BM) thr_l[j] = t;
     }
     // workgroup OR of the flags through the head of the (still idle) ring: the
     // ring is all of the LDS, so no other shared array may be allocated
@@ -488,21 +503,11 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // will end below it, and the tile adds nothing to any rank.  Checked every
     // 16 rows of that phase: each wave votes through LDS, the next stage
     // barrier publishes the votes.
-    const bool exit_ok = EXIT && A.early_exit && A.thr && !A.matrix;
+    // (the votes read the tile's thresholds and usable columns from LDS:
+    // global loads there would drain the stage loads in flight)
+    const bool exit_ok = EXIT && A.early_exit && A.thr && ranks;
     volatile uint32_t* votes = reinterpret_cast<volatile uint32_t*>(lds + C::kVote);
-    int32_t* thr_l = reinterpret_cast<int32_t*>(lds + C::kThr);
-    uint8_t* col_l = reinterpret_cast<uint8_t*>(lds + C::kCol);
     const int last_phase = nstage - NB;
-    if (exit_ok) {
-        // the tile's thresholds and usable columns, read by the votes from LDS
-        // (global loads there would drain the stage loads in flight); visible
-        // after the first stage barrier, long before the first vote
-        for (int j = tid; j < C::BM; j += C::kThreads) {
-            const uint32_t row = ga0 * 16 + j;
-            thr_l[j] = row < A.nn ? A.thr[row] : INT_MIN;
-        }
-        for (int j = tid; j < C::BN; j += C::kThreads) col_l[j] = A.hmax[gb0 * 16 + j] <= kSlow ? 1 : 0;
-    }
     auto vote = [&](int32_t slack) {
         bool alive = false;
         const int cl = lane & 15, rq = lane >> 4;
@@ -615,13 +620,12 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
 #pragma unroll
     for (int nb = 0; nb < C::kNBK; ++nb) {
         const uint32_t slot = (gb0 + wn * C::kNBK + nb) * 16 + cl;
-        colok[nb] = A.hmax[slot] <= kSlow;            // padding and |D| > 127 excluded
-        col[nb] = colok[nb] ? A.hperm[slot] : 0u;     // original haystack index
+        colok[nb] = col_l[(wn * C::kNBK + nb) * 16 + cl] != 0;
+        col[nb] = (!ranks && colok[nb]) ? A.hperm[slot] : 0u;   // original haystack index (matrix mode)
     }
     // rank mode: the kWN waves sharing a needle row add their counts in LDS
     // (the idle ring head), then one global atomic per row of the tile
     uint32_t* rowcnt = reinterpret_cast<uint32_t*>(lds);
-    const bool ranks = A.matrix == nullptr;
     if (ranks) {
         __syncthreads();   // every wave is done with the ring, its last reads included
         for (int j = tid; j < C::BM; j += C::kThreads) rowcnt[j] = 0u;
@@ -629,6 +633,9 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     }
 #pragma unroll
     for (int mb = 0; mb < C::kMB; ++mb) {
+        // the four thresholds of this lane's rows in the block (INT_MIN past the needles)
+        const v4i t4 = ranks ? *reinterpret_cast<const v4i*>(thr_l + (wm * C::kMB + mb) * 16 + 4 * rq)
+                             : v4i{0, 0, 0, 0};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int lrow = (wm * C::kMB + mb) * 16 + 4 * rq + v;   // row within the tile
@@ -642,7 +649,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
                         if (colok[nb]) A.matrix[(size_t)row * A.nh + col[nb]] = base + (int64_t)acc[mb][nb][v];
                 }
             } else {
-                const int32_t t = rowok ? A.thr[row] : INT_MIN;
+                const int32_t t = t4[v];
                 uint32_t cnt = 0;
 #pragma unroll
                 for (int nb = 0; nb < C::kNBK; ++nb) cnt += (colok[nb] && acc[mb][nb][v] < t) ? 1u : 0u;
