@@ -310,11 +310,13 @@ struct SearchCfg {
     static constexpr int kStage = kFrags * (int)kFragBytes;
     static constexpr int kLPW = kFrags / kWaves;     // fragment loads per wave per stage
     // after the ring: early-exit votes (one word per wave), the tile's needle
-    // thresholds (BM int32) and haystack usability flags (BN bytes)
+    // thresholds (BM int32), haystack usability flags (BN bytes) and per-row
+    // hit counts of the rank epilogue (BM uint32)
     static constexpr int kVote = NS * kStage;
     static constexpr int kThr = kVote + 64;
     static constexpr int kCol = kThr + BM * 4;
-    static constexpr int kLds = kCol + BN;
+    static constexpr int kRow = kCol + ((BN + 15) & ~15);
+    static constexpr int kLds = kRow + BM * 4;
     static_assert(kFrags % kWaves == 0, "fragments must split evenly over the waves");
 };
 
@@ -403,6 +405,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // the epilogue reads no global memory in rank mode.
     int32_t* thr_l = reinterpret_cast<int32_t*>(lds + C::kThr);
     uint8_t* col_l = reinterpret_cast<uint8_t*>(lds + C::kCol);
+    uint32_t* rowcnt = reinterpret_cast<uint32_t*>(lds + C::kRow);
     const bool ranks = A.matrix == nullptr;
     int flags = 0;
     constexpr int kPro = C::BM > C::BN ? C::BM : C::BN;
@@ -416,7 +419,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             flags |= (m <= kSlow) ? 2 : 0;
             col_l[j] = m <= kSlow ? 1 : 0;               // padding and |D| > 127 excluded
         }
-        if (j < C::BM) thr_l[j] = t;
+        if (j < C::BM) { thr_l[j] = t; rowcnt[j] = 0u; }
     }
     // workgroup OR of the flags through the head of the (still idle) ring: the
     // ring is all of the LDS, so no other shared array may be allocated
@@ -624,13 +627,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         col[nb] = (!ranks && colok[nb]) ? A.hperm[slot] : 0u;   // original haystack index (matrix mode)
     }
     // rank mode: the kWN waves sharing a needle row add their counts in LDS
-    // (the idle ring head), then one global atomic per row of the tile
-    uint32_t* rowcnt = reinterpret_cast<uint32_t*>(lds);
-    if (ranks) {
-        __syncthreads();   // every wave is done with the ring, its last reads included
-        for (int j = tid; j < C::BM; j += C::kThreads) rowcnt[j] = 0u;
-        __syncthreads();
-    }
+    // (zeroed in the prologue), then one global atomic per row of the tile
 #pragma unroll
     for (int mb = 0; mb < C::kMB; ++mb) {
         // the four thresholds of this lane's rows in the block (INT_MIN past the needles)
