@@ -421,17 +421,18 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         }
         if (j < C::BM) { thr_l[j] = t; rowcnt[j] = 0u; }
     }
-    // workgroup OR of the flags through the head of the (still idle) ring: the
-    // ring is all of the LDS, so no other shared array may be allocated
+    // workgroup OR of the flags through the early-exit vote words (all of the
+    // LDS is the kernel's dynamic block: no static shared array is allocated).
+    // The first vote comes many stage barriers later, after every wave has
+    // read the flags, so one barrier suffices here.
     {
-        volatile uint32_t* red = reinterpret_cast<volatile uint32_t*>(lds);
+        volatile uint32_t* red = reinterpret_cast<volatile uint32_t*>(lds + C::kVote);
         const uint64_t b1 = __ballot(flags & 1), b2 = __ballot(flags & 2);
         if (lane == 0) red[wave] = (b1 ? 1u : 0u) | (b2 ? 2u : 0u);
         __syncthreads();
         int all = 0;
 #pragma unroll
         for (int w = 0; w < C::kWaves; ++w) all |= (int)red[w];
-        __syncthreads();   // every wave has read the flags before the ring fills
         flags = __builtin_amdgcn_readfirstlane(all);   // uniform: scalar control flow below
     }
     const bool hq = (flags & 1) != 0;
