@@ -1,0 +1,51 @@
+"""Scenes with closed-form RICIs, shared by the oracle pins (CPU) and the GPU
+parity tests.  Test infrastructure: the expected images are written from the
+geometry of Sec. 3.1 (a circle of radius rho_c in the row plane beta_r crosses
+a segment once if exactly one end lies outside it, twice if both ends lie
+outside and the segment's closest point to the axis lies inside)."""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def bin_radius_boundaries(R: float = 1.0, delta: float = 1e-4, b0: float = -0.31, b1: float = 0.23):
+    """Ranges starting `delta` bins inside and outside each of the 64 bin
+    radii, for the oriented point at the origin with normal +z.  Each radius r
+    gets a radial rectangle (inner edge at r, outer edge at 2R: one crossing
+    for every bin radius above r) and a chord rectangle (a segment at distance
+    r from the axis, both ends at about 2R: two crossings for every bin radius
+    above r), both spanning heights b0 .. b1, at golden-angle azimuths.
+
+    Returns (positions float32 [V, 3], triangles uint32 [T, 3], expected
+    image int64 [64, 64]) with the expectation computed in float64 from the
+    float32 coordinates."""
+    verts, tris = [], []
+
+    def rect(p0, p1):
+        k = len(verts)
+        verts.extend([(p0[0], p0[1], b0), (p1[0], p1[1], b0), (p1[0], p1[1], b1), (p0[0], p0[1], b1)])
+        tris.extend([(k, k + 1, k + 2), (k, k + 2, k + 3)])
+
+    n = 0
+    for c in range(64):
+        for d in (-delta, delta):
+            r = (c + 0.5 + d) * R / 64
+            phi = 2.399963 * n
+            u = np.array([np.cos(phi), np.sin(phi)])
+            w = np.array([-u[1], u[0]])
+            rect(r * u, 2.0 * R * u)
+            rect(r * w - 2.0 * R * u, r * w + 2.0 * R * u)
+            n += 1
+    v = np.array(verts, np.float32)
+    t = np.array(tris, np.uint32)
+    V = v.astype(np.float64)
+    rho = (np.arange(64) + 0.5) * R / 64
+    beta = -R / 2 + (np.arange(64) + 0.5) * R / 64
+    rows = (beta > np.float64(np.float32(b0))) & (beta < np.float64(np.float32(b1)))
+    per_col = np.zeros(64, np.int64)
+    for k in range(0, len(V), 8):
+        per_col += rho > np.hypot(V[k, 0], V[k, 1])       # radial rectangle: its inner edge
+        p, q = V[k + 4, :2], V[k + 5, :2]                 # chord: distance of its line from the axis
+        per_col += 2 * (rho > abs(p[0] * q[1] - p[1] * q[0]) / np.hypot(*(q - p)))
+    return v, t, rows[:, None] * per_col[None, :]

@@ -4,6 +4,7 @@ closed forms: bit-exact at every pixel the oracle does not flag as degenerate.""
 import numpy as np
 import pytest
 
+import closed_forms
 import oracle
 import synth
 from gpu_util import assert_images_match, dev_f32, dev_u32, gpu_images, say
@@ -89,6 +90,19 @@ def test_planar_square_closed_form(ctx):
     L1f, L2f, b0f, b1f = (np.float64(np.float32(x)) for x in (L1, L2, b0, b1))
     exp = ((beta > b0f) & (beta < b1f))[:, None] * ((rho < L1f).astype(int) + (rho < L2f).astype(int))[None, :]
     assert np.array_equal(g[0], exp.astype(np.uint32))
+
+
+def test_columns_next_to_every_bin_radius(ctx):
+    """Ranges that start 1e-4 bins inside and outside each of the 64 bin radii
+    (single ranges from radial rectangles, double ranges from chords): the
+    column decisions at every bin radius, both sides; closed form and oracle."""
+    v, t, exp = closed_forms.bin_radius_boundaries()
+    sv, sn = np.zeros((1, 3), np.float32), np.array([[0, 0, 1]], np.float32)
+    g = gpu_images(ctx, v, t, sv, sn, 1.0)
+    assert np.array_equal(g[0].astype(np.int64), exp)
+    o, fl, _ = oracle.rici_rowrange(v, t, sv, sn, 1.0)
+    assert not fl.any()
+    assert_images_match(g, o, fl, "bin-radius boundaries")
 
 
 def test_off_axis_sphere_closed_form(ctx):

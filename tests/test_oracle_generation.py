@@ -12,6 +12,7 @@
 import numpy as np
 import pytest
 
+import closed_forms
 import oracle
 import synth
 
@@ -156,6 +157,22 @@ def test_off_axis_sphere(case):
 
 
 # ------------------------------------------------------------------- invariants
+
+def test_columns_next_to_every_bin_radius():
+    """Single ranges (radial rectangles) and double ranges (chords) that start
+    1e-4 bins inside and outside each of the 64 bin radii: the oracle's image
+    equals the closed form exactly and flags nothing (the margin is far above
+    the degenerate-case tolerance)."""
+    v, t, exp = closed_forms.bin_radius_boundaries()
+    o, fl, _ = oracle.rici_rowrange(v, t, np.zeros((1, 3), np.float32), np.array([[0, 0, 1]], np.float32), 1.0)
+    assert not fl.any()
+    assert np.array_equal(o[0].astype(np.int64), exp)
+    # column c lies above 2c + 1 of the 128 radii: 3 (2c + 1) crossings on the
+    # rows inside the rectangles' height, none elsewhere
+    inside = exp.any(axis=1)
+    assert inside.sum() == 35   # rows 12 .. 46: beta_r in (-0.31, 0.23)
+    assert (exp[inside] == 3 * (2 * np.arange(64) + 1)).all() and (exp[~inside] == 0).all()
+
 
 def test_closed_surface_counts_are_even():
     s = synth.config2_union12()
