@@ -49,3 +49,44 @@ def bin_radius_boundaries(R: float = 1.0, delta: float = 1e-4, b0: float = -0.31
         p, q = V[k + 4, :2], V[k + 5, :2]                 # chord: distance of its line from the axis
         per_col += 2 * (rho > abs(p[0] * q[1] - p[1] * q[0]) / np.hypot(*(q - p)))
     return v, t, rows[:, None] * per_col[None, :]
+
+
+def row_plane_boundaries(R: float = 1.0, delta: float = 1e-4):
+    """Radial rectangles whose lower and upper edges lie `delta` bins above or
+    below row planes, for the oriented point at the origin with normal +z.
+    Rectangle (r, s) has its lower edge at beta_r + s * delta (s = -1, +1) and
+    its upper edge at beta_{r+3} - s * delta (or above the image near the top),
+    its inner edge between two bin radii and its outer edge at 2R.  A row plane
+    beta cuts a rectangle spanning z_lo .. z_hi iff z_lo < beta <= z_hi (a
+    vertex at z >= beta counts as above it), and then adds one crossing for
+    each bin radius beyond the inner edge.
+
+    Returns (positions float32 [V, 3], triangles uint32 [T, 3], expected
+    image int64 [64, 64])."""
+    b = R / 64
+    beta = -R / 2 + (np.arange(64) + 0.5) * b
+    rho = (np.arange(64) + 0.5) * b
+    verts, tris, rects = [], [], []
+    n = 0
+    for r in range(64):
+        for s in (-1.0, 1.0):
+            lo = beta[r] + s * delta * b
+            hi = beta[r + 3] - s * delta * b if r + 3 < 64 else R / 2 + 0.3 * b
+            rin = ((7 * n) % 60 + 0.75) * b
+            phi = 2.399963 * n
+            u = np.array([np.cos(phi), np.sin(phi)])
+            k = len(verts)
+            p0, p1 = rin * u, 2.0 * R * u
+            verts.extend([(p0[0], p0[1], lo), (p1[0], p1[1], lo), (p1[0], p1[1], hi), (p0[0], p0[1], hi)])
+            tris.extend([(k, k + 1, k + 2), (k, k + 2, k + 3)])
+            n += 1
+    v = np.array(verts, np.float32)
+    t = np.array(tris, np.uint32)
+    V = v.astype(np.float64)
+    exp = np.zeros((64, 64), np.int64)
+    for k in range(0, len(V), 4):
+        z_lo, z_hi = V[k, 2], V[k + 2, 2]
+        rows = (beta > z_lo) & (beta <= z_hi)
+        cols = rho > np.hypot(V[k, 0], V[k, 1])
+        exp += rows[:, None] * cols[None, :]
+    return v, t, exp

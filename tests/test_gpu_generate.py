@@ -105,6 +105,19 @@ def test_columns_next_to_every_bin_radius(ctx):
     assert_images_match(g, o, fl, "bin-radius boundaries")
 
 
+def test_rows_next_to_every_row_plane(ctx):
+    """Rectangle edges 1e-4 bins above and below every row plane: the row
+    range of each pair (which rows a triangle spans) at every plane, both
+    sides; closed form and oracle."""
+    v, t, exp = closed_forms.row_plane_boundaries()
+    sv, sn = np.zeros((1, 3), np.float32), np.array([[0, 0, 1]], np.float32)
+    g = gpu_images(ctx, v, t, sv, sn, 1.0)
+    assert np.array_equal(g[0].astype(np.int64), exp)
+    o, fl, _ = oracle.rici_rowrange(v, t, sv, sn, 1.0)
+    assert not fl.any()
+    assert_images_match(g, o, fl, "row-plane boundaries")
+
+
 def test_off_axis_sphere_closed_form(ctx):
     a, dist, q, R = 0.3, 0.1, 0.02, 1.0
     m = synth.icosphere(5)

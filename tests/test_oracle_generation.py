@@ -174,6 +174,18 @@ def test_columns_next_to_every_bin_radius():
     assert (exp[inside] == 3 * (2 * np.arange(64) + 1)).all() and (exp[~inside] == 0).all()
 
 
+def test_rows_next_to_every_row_plane():
+    """Rectangles whose lower and upper edges lie 1e-4 bins above or below
+    the row planes: the oracle includes exactly the rows with z_lo < beta <=
+    z_hi, flags nothing, and a plane just below an edge cuts the rectangle
+    while one just above it does not."""
+    v, t, exp = closed_forms.row_plane_boundaries()
+    o, fl, _ = oracle.rici_rowrange(v, t, np.zeros((1, 3), np.float32), np.array([[0, 0, 1]], np.float32), 1.0)
+    assert not fl.any()
+    assert np.array_equal(o[0].astype(np.int64), exp)
+    assert exp[0].sum() > 0 and exp[63].sum() > 0
+
+
 def test_closed_surface_counts_are_even():
     s = synth.config2_union12()
     sel = np.random.default_rng(0).choice(s.num_haystack, 64, replace=False)
