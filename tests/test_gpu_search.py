@@ -71,6 +71,36 @@ def _exact_step_images(rng, n, peak):
     return im.astype(np.uint32)
 
 
+@pytest.mark.parametrize("tile", [256, 128])
+def test_extreme_deltas_at_the_accumulator_bound(tile):
+    """Images whose 4 032 deltas are all +-127 (ramps up and down, zigzags),
+    flat images (no mask) and their mixes: the largest distances the int8
+    contraction can meet (4 032 * 254^2 between opposite ramps), exact
+    against the oracle in the matrix and in the ranks."""
+    from paper_2007_02306_amd import Context
+    c = Context(0)
+    c.set_tuning("search_tile_m", tile)
+    col = np.arange(64, dtype=np.uint32)
+    up = np.tile(col * 127, (64, 1))
+    down = np.tile((63 - col) * 127, (64, 1))
+    zig = np.tile((col % 2) * 127, (64, 1))
+    zag = np.tile(((col + 1) % 2) * 127, (64, 1))
+    flat = np.full((64, 64), 5000, np.uint32)
+    mixed = np.where((np.arange(64) % 2)[:, None] == 0, up, zag).astype(np.uint32)
+    base = np.stack([up, down, zig, zag, flat, mixed]).astype(np.uint32)
+    rng = np.random.default_rng(tile)
+    h = np.concatenate([base, base[rng.integers(0, 6, 300)]])
+    n = np.concatenate([base, base[::-1]])
+    o = oracle.distance_matrix(n, h)
+    assert o.max() == 4032 * 254 * 254
+    assert np.array_equal(gpu_matrix(c, n, h), o)
+    t = rng.integers(0, len(h), len(n)).astype(np.uint32)
+    rk, ds = gpu_rank(c, n, h, t)
+    ork, ods = oracle.rank(n, h, t)
+    assert np.array_equal(ds, ods) and np.array_equal(rk, ork)
+    c.close()
+
+
 @pytest.mark.parametrize("tile,exit_", [(256, 0), (128, 0), (256, 1)])
 def test_delta_range_boundaries(tile, exit_):
     """Haystack and needle images whose largest delta sits exactly on each side
