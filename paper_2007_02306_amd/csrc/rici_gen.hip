@@ -80,6 +80,10 @@ __device__ __forceinline__ void prep_triangle(const float* __restrict__ pos, uin
     float r = sqrtf(fmaxf(ra, fmaxf(rb, rc)));
     float mag = fmaxf(fabsf(mx), fmaxf(fabsf(my), fabsf(mz)));
     r = r * 1.0001f + 1e-5f * (mag + r) + 1e-30f;
+    // a sphere whose centre or radius is beyond 1e18 would overflow the FP32
+    // squares of the cull: it is stored with an infinite radius, which every
+    // cull passes (the exact FP64 stage handles any finite coordinates)
+    if (!(mag < 1e18f) || !(r < 1e18f)) { mx = my = mz = 0.f; r = INFINITY; }
     cull[t] = make_float4(mx, my, mz, r);
 }
 
@@ -232,7 +236,8 @@ __device__ __forceinline__ void cluster_sphere(const float4* __restrict__ cull, 
 {
     const uint32_t t = c * 64 + lane;
     const float4 s = t < nt ? cull[t] : make_float4(0.f, 0.f, 0.f, -INFINITY);
-    const bool live = s.w >= 0.f;
+    const bool giant = __ballot(s.w == INFINITY) != 0;   // then the run always passes
+    const bool live = s.w >= 0.f && s.w != INFINITY;
     float lo[3] = { live ? s.x - s.w : INFINITY, live ? s.y - s.w : INFINITY, live ? s.z - s.w : INFINITY };
     float hi[3] = { live ? s.x + s.w : -INFINITY, live ? s.y + s.w : -INFINITY, live ? s.z + s.w : -INFINITY };
 #pragma unroll
@@ -249,8 +254,9 @@ __device__ __forceinline__ void cluster_sphere(const float4* __restrict__ cull, 
     if (lane == 0) {
         const float mag = fmaxf(fabsf(cx), fmaxf(fabsf(cy), fabsf(cz)));
         const bool any = r >= 0.f;   // at least one live triangle
-        clusters[c] = any ? make_float4(cx, cy, cz, r * 1.0001f + 1e-5f * (mag + r) + 1e-30f)
-                          : make_float4(0.f, 0.f, 0.f, -INFINITY);
+        clusters[c] = giant ? make_float4(0.f, 0.f, 0.f, INFINITY)
+                    : any   ? make_float4(cx, cy, cz, r * 1.0001f + 1e-5f * (mag + r) + 1e-30f)
+                            : make_float4(0.f, 0.f, 0.f, -INFINITY);
     }
 }
 
@@ -593,14 +599,15 @@ __device__ void gen_images(GenLds<G>& L, const GenJob& J, uint32_t img0, float R
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     // Conservative FP32 sphere test against image g's support volume: the slab
-    // |beta| <= R/2 and the cylinder alpha <= R, both with margins.
+    // |beta| <= R/2 and the cylinder alpha <= R, both with margins.  An infinite
+    // radius (a sphere too large for FP32 squares) reaches every live image.
     auto reaches = [&](const float4& sp, int g) -> bool {
         const float dx = sp.x - P[g][0], dy = sp.y - P[g][1], dz = sp.z - P[g][2];
         const float h = P[g][3] * dx + P[g][4] * dy + P[g][5] * dz;
         const float d2 = dx * dx + dy * dy + dz * dz;
         const float a2 = d2 - h * h;
         const float la = P[g][7] + sp.w;
-        return (fabsf(h) <= P[g][6] + sp.w) & (a2 <= la * la);
+        return ((fabsf(h) <= P[g][6] + sp.w) & (a2 <= la * la)) | ((sp.w == INFINITY) & (P[g][6] > 0.f));
     };
 
     // Test one run of 64 triangles (spheres s, triangle t = run * 64 + lane)

@@ -137,6 +137,33 @@ def test_off_axis_sphere_closed_form(ctx):
     assert np.array_equal(g[0][ok], exp[ok])
 
 
+def test_giant_triangles_do_not_hide_their_neighbours(ctx):
+    """Triangles with coordinates near 1e30 (finite, but beyond FP32 squares)
+    far from every support volume, interleaved with an icosphere's triangles
+    in the same runs of 64: they add nothing, and the icosphere's counts must
+    be unchanged (a run's bounding sphere must not become NaN and cull its
+    ordinary triangles)."""
+    s = synth.config1_icosphere()
+    pos = np.asarray(s.positions, np.float32)
+    tri = np.asarray(s.triangles, np.uint32)
+    giant = np.array([[1e30, 0, 5e29], [-1e30, 1e30, 5.1e29], [0, -1e30, 6e29],
+                      [3e38, -3e38, 2e38], [-3e38, 3e38, 2.5e38], [3e38, 3e38, 3e38]], np.float32)
+    gi = len(pos) + np.array([[0, 1, 2], [3, 4, 5]], np.uint32)
+    mixed = []
+    for k in range(len(tri)):
+        mixed.append(tri[k])
+        if k % 7 == 3:
+            mixed.append(gi[k % 2])
+    mixed = np.array(mixed, np.uint32)
+    allpos = np.concatenate([pos, giant])
+    g = gpu_images(ctx, allpos, mixed, s.op_positions, s.op_normals, s.support_radius)
+    ref = gpu_images(ctx, pos, tri, s.op_positions, s.op_normals, s.support_radius)
+    o, fl, _ = oracle.rici_rowrange(pos, tri, s.op_positions, s.op_normals, s.support_radius)
+    assert_images_match(ref, o, fl, "icosphere")
+    assert np.array_equal(g, ref)
+    assert g.max() > 0
+
+
 def test_empty_scene_and_no_points(ctx):
     import torch
     opp = np.array([[0, 0, 0], [1, 2, 3]], np.float32)
