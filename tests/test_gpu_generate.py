@@ -184,11 +184,15 @@ def test_zero_normal_is_plus_z(ctx):
     assert np.array_equal(a, b)
 
 
-def test_power_of_two_scaling_bit_identical(ctx):
+@pytest.mark.parametrize("k", [3, -64, 64, -100, 100])
+def test_power_of_two_scaling_bit_identical(ctx, k):
+    """Scaling scene and R by 2^k changes no FP64 rounding, so the images are
+    bit-identical, also where the FP32 culls' squares underflow (2^-100) or
+    overflow (2^100)."""
     s = synth.config1_icosphere()
     a = gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals, 1.0)
-    f = np.float32(8.0)
-    b = gpu_images(ctx, s.positions * f, s.triangles, s.op_positions * f, s.op_normals, 8.0)
+    f = np.float32(2.0 ** k)
+    b = gpu_images(ctx, s.positions * f, s.triangles, s.op_positions * f, s.op_normals, float(f))
     assert np.array_equal(a, b)
 
 
