@@ -90,3 +90,29 @@ def row_plane_boundaries(R: float = 1.0, delta: float = 1e-4):
         cols = rho > np.hypot(V[k, 0], V[k, 1])
         exp += rows[:, None] * cols[None, :]
     return v, t, exp
+
+
+def degenerate_triangles():
+    """Degenerate and boundary triangles near the origin (support radius 1,
+    normal +z): a point, a vertical and a slanted segment, a triangle lying in
+    a row plane, one with an edge in a row plane, one with vertices on two
+    row planes, and one with an edge on the axis.  (No closed form: used to
+    compare the row-range algorithm with the brute-force definition and the
+    GPU with the oracle.)"""
+    b = 1.0 / 64
+    beta = lambda r: -0.5 + (r + 0.5) * b
+    V, T = [], []
+
+    def tri(p, q, s):
+        k = len(V)
+        V.extend([p, q, s])
+        T.append((k, k + 1, k + 2))
+
+    tri((0.2, 0.1, 0.05), (0.2, 0.1, 0.05), (0.2, 0.1, 0.05))
+    tri((0.1, -0.2, -0.3), (0.1, -0.2, 0.0), (0.1, -0.2, 0.3))
+    tri((-0.3, 0.0, -0.2), (0.0, 0.1, 0.0), (0.3, 0.2, 0.2))
+    tri((-0.4, -0.4, beta(40)), (0.4, -0.3, beta(40)), (0.0, 0.5, beta(40)))
+    tri((-0.3, 0.25, beta(20)), (0.3, 0.25, beta(20)), (0.0, 0.25, beta(28)))
+    tri((0.15, 0.0, beta(10)), (0.15, 0.0, beta(30)), (0.45, 0.0, beta(10)))
+    tri((0.0, 0.0, -0.45), (0.0, 0.0, 0.45), (0.3, 0.0, 0.0))
+    return np.array(V, np.float32), np.array(T, np.uint32)

@@ -118,6 +118,19 @@ def test_rows_next_to_every_row_plane(ctx):
     assert_images_match(g, o, fl, "row-plane boundaries")
 
 
+def test_degenerate_triangles(ctx):
+    """Points, segments, a triangle lying in a row plane, edges and vertices
+    on row planes and an edge on the axis, seen from the origin along +z and
+    from a few tilted frames: equal to the oracle outside flagged pixels."""
+    v, t = closed_forms.degenerate_triangles()
+    sv = np.array([[0, 0, 0], [0.05, -0.02, 0.01], [0, 0, 0.1]], np.float32)
+    sn = np.array([[0, 0, 1], [0.3, 0.2, 1.0], [1, 0, 0]], np.float32)
+    g = gpu_images(ctx, v, t, sv, sn, 1.0)
+    o, fl, _ = oracle.rici_rowrange(v, t, sv, sn, 1.0)
+    assert not fl[0].any() and g[0].sum() > 0
+    assert_images_match(g, o, fl, "degenerate triangles")
+
+
 def test_off_axis_sphere_closed_form(ctx):
     a, dist, q, R = 0.3, 0.1, 0.02, 1.0
     m = synth.icosphere(5)

@@ -186,6 +186,20 @@ def test_rows_next_to_every_row_plane():
     assert exp[0].sum() > 0 and exp[63].sum() > 0
 
 
+def test_degenerate_triangles_rowrange_equals_brute_force():
+    """Points, segments, a triangle in a row plane, edges and vertices on row
+    planes and an edge on the axis: the row-range algorithm equals the
+    brute-force definition wherever neither flags a pixel, and flags none
+    itself (the half-open row convention decides every plane contact)."""
+    v, t = closed_forms.degenerate_triangles()
+    sv, sn = np.zeros((1, 3), np.float32), np.array([[0, 0, 1]], np.float32)
+    o, fl, _ = oracle.rici_rowrange(v, t, sv, sn, 1.0)
+    ob, flb = oracle.rici_brute(v, t, sv, sn, 1.0)
+    assert not fl.any() and o.sum() > 0
+    m = ~(fl | flb)
+    assert np.array_equal(o[m], ob[m])
+
+
 def test_closed_surface_counts_are_even():
     s = synth.config2_union12()
     sel = np.random.default_rng(0).choice(s.num_haystack, 64, replace=False)
