@@ -50,6 +50,11 @@ def load():
             lib.oracle_rici_rowrange.restype = I32
             lib.oracle_rici_brute.argtypes = [P, U32, P, U32, P, P, U32, F32, P, P, I32]
             lib.oracle_rici_brute.restype = I32
+            F64 = ctypes.c_double
+            lib.oracle_rici_rowrange_f64.argtypes = [P, U32, P, U32, P, P, U32, F64, P, P, P, I32]
+            lib.oracle_rici_rowrange_f64.restype = I32
+            lib.oracle_rici_brute_f64.argtypes = [P, U32, P, U32, P, P, U32, F64, P, P, I32]
+            lib.oracle_rici_brute_f64.restype = I32
             lib.oracle_project.argtypes = [P, P, P, I64, I32, P, P, P]
             lib.oracle_project.restype = None
             lib.oracle_crd.argtypes = [P, P]
@@ -72,14 +77,21 @@ def _ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data) if a is not None else None
 
 
-def _mesh_args(positions, triangles, op_positions, op_normals):
-    pos = _c(positions, np.float32).reshape(-1, 3)
+def _mesh_args(positions, triangles, op_positions, op_normals, dtype=np.float32):
+    pos = _c(positions, dtype).reshape(-1, 3)
     tri = _c(triangles, np.uint32).reshape(-1, 3)
-    opp = _c(op_positions, np.float32).reshape(-1, 3)
-    opn = _c(op_normals, np.float32).reshape(-1, 3)
+    opp = _c(op_positions, dtype).reshape(-1, 3)
+    opn = _c(op_normals, dtype).reshape(-1, 3)
     if opp.shape != opn.shape:
         raise ValueError("op_positions and op_normals differ in shape")
     return pos, tri, opp, opn
+
+
+def _check(rc: int, what: str):
+    if rc == -1:
+        raise ValueError(f"{what} out of range")
+    if rc != 0:
+        raise MemoryError("the oracle ran out of host memory")
 
 
 def threads(nthreads: int = 0) -> int:
@@ -87,33 +99,36 @@ def threads(nthreads: int = 0) -> int:
 
 
 def rici_rowrange(positions, triangles, op_positions, op_normals, support_radius: float,
-                  nthreads: int = 0):
+                  nthreads: int = 0, f64: bool = False):
     """Row-range oracle: returns (images u32 [N,64,64], flags bool [N,64,64],
-    work u64 [N,3] = (triangles visited, slices, pixel updates))."""
-    pos, tri, opp, opn = _mesh_args(positions, triangles, op_positions, op_normals)
+    work u64 [N,3] = (triangles visited, slices, pixel updates)).  Inputs are
+    fp32 (the library's input type) unless `f64`, which passes positions,
+    oriented points and the support radius in FP64."""
+    dt = np.float64 if f64 else np.float32
+    pos, tri, opp, opn = _mesh_args(positions, triangles, op_positions, op_normals, dt)
     n = opp.shape[0]
     images = np.zeros((n, NBINS, NBINS), dtype=np.uint32)
     flags = np.zeros((n, NBINS, NBINS), dtype=np.uint8)
     work = np.zeros((n, 3), dtype=np.uint64)
-    rc = load().oracle_rici_rowrange(_ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], _ptr(opp), _ptr(opn),
-                                     n, float(support_radius), _ptr(images), _ptr(flags), _ptr(work),
-                                     int(nthreads))
-    if rc != 0:
-        raise ValueError("triangle index out of range")
+    fn = load().oracle_rici_rowrange_f64 if f64 else load().oracle_rici_rowrange
+    rc = fn(_ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], _ptr(opp), _ptr(opn), n, float(support_radius),
+            _ptr(images), _ptr(flags), _ptr(work), int(nthreads))
+    _check(rc, "triangle index")
     return images, flags.astype(bool), work
 
 
 def rici_brute(positions, triangles, op_positions, op_normals, support_radius: float,
-               nthreads: int = 0):
+               nthreads: int = 0, f64: bool = False):
     """Brute-force oracle (plain definition): returns (images, flags)."""
-    pos, tri, opp, opn = _mesh_args(positions, triangles, op_positions, op_normals)
+    dt = np.float64 if f64 else np.float32
+    pos, tri, opp, opn = _mesh_args(positions, triangles, op_positions, op_normals, dt)
     n = opp.shape[0]
     images = np.zeros((n, NBINS, NBINS), dtype=np.uint32)
     flags = np.zeros((n, NBINS, NBINS), dtype=np.uint8)
-    rc = load().oracle_rici_brute(_ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], _ptr(opp), _ptr(opn),
-                                  n, float(support_radius), _ptr(images), _ptr(flags), int(nthreads))
-    if rc != 0:
-        raise ValueError("triangle index out of range")
+    fn = load().oracle_rici_brute_f64 if f64 else load().oracle_rici_brute
+    rc = fn(_ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], _ptr(opp), _ptr(opn), n, float(support_radius),
+            _ptr(images), _ptr(flags), int(nthreads))
+    _check(rc, "triangle index")
     return images, flags.astype(bool)
 
 
@@ -141,7 +156,8 @@ def distance_matrix(needles, haystack, nthreads: int = 0) -> np.ndarray:
     nd = _c(needles, np.uint32).reshape(-1, NBINS, NBINS)
     hs = _c(haystack, np.uint32).reshape(-1, NBINS, NBINS)
     out = np.zeros((nd.shape[0], hs.shape[0]), dtype=np.int64)
-    load().oracle_distance_matrix(_ptr(nd), nd.shape[0], _ptr(hs), hs.shape[0], _ptr(out), int(nthreads))
+    rc = load().oracle_distance_matrix(_ptr(nd), nd.shape[0], _ptr(hs), hs.shape[0], _ptr(out), int(nthreads))
+    _check(rc, "index")
     return out
 
 
@@ -156,6 +172,5 @@ def rank(needles, haystack, true_index, nthreads: int = 0):
     ds = np.zeros(nd.shape[0], dtype=np.int64)
     rc = load().oracle_rank(_ptr(nd), nd.shape[0], _ptr(hs), hs.shape[0], _ptr(ti), _ptr(rk), _ptr(ds),
                             int(nthreads))
-    if rc != 0:
-        raise ValueError("true_index out of range")
+    _check(rc, "true_index")
     return rk, ds

@@ -11,11 +11,13 @@
  *   rowrange : the paper's generation algorithm (Sec. 3.1: project the
  *              triangle, slice it with each row plane, single/double radius
  *              ranges, increment bins), with degeneracy flags and work counters.
+ *              Inputs are fp32 (converted exactly) or FP64.
  *   brute    : the plain definition of a RICI bin (number of points where the
  *              bin's circle meets the scene's triangles), solved per circle and
  *              triangle with trigonometry and barycentric coordinates.
- *   crd      : the clutter-resistant distance, Sec. 3.2 (Eq. 6-7), summed
- *              literally in int64.
+ *   crd      : the clutter-resistant distance, Sec. 3.2: the Eq. 6 delta
+ *              planes of both images, then the Eq. 7 sum of squared
+ *              differences over the needle's non-zero deltas, in int64.
  *   rank     : 0-based rank of the true match, ties taking the best rank
  *              (Sec. 4.1, clutterbox step 6c, and the tie rule of Sec. 4.2).
  *
@@ -29,8 +31,22 @@
  *       centres: rho_c = (c + 1/2) R/64, beta_r = -R/2 + (r + 1/2) R/64.
  *       Column c grows with radius, row r with beta.
  *   R3  A vertex lies "above" a row plane iff z >= beta (half-open).
- *   R4  Counts use open intervals; any pixel whose decision lies within
- *       EPS of its threshold is flagged as degenerate instead (C-D rules).
+ *   R4  Counts use open intervals.  A pixel is flagged as degenerate (and
+ *       excluded from parity) when a decision that sets its count lies within
+ *       EPS of its threshold, widened by a forward bound on the FP64 rounding
+ *       error of the compared quantity (so that the count of every unflagged
+ *       pixel is certain, whatever the FP64 evaluation order):
+ *         (i)   the bin radius vs a slice end |E0|, |E1|;
+ *         (ii)  the bin radius vs the foot point |C| of a double range, and
+ *               the whole double range when "C inside E0E1" is uncertain;
+ *         (iii) a vertex within that band of the row plane: the slice is also
+ *               taken with the vertex on the other side, and the pixels where
+ *               the two slices disagree, or near the second one's decisions,
+ *               are flagged;
+ *         (iv)  an edge or the whole triangle within the band of the row
+ *               plane (Sec. 3.1.2 leaves infinite intersections out): every
+ *               radius the edge or triangle covers.
+ *       A zero normal flags the whole image.
  *   R5  CRD sums r in [0, 64) and c in [1, 64) (64 x 63 terms); the printed
  *       ranges [0..N_bins] / [1..N_bins] are read half-open.
  *   R6  rank = #{h : CRD(n, h) < CRD(n, h_true)} (strict: ties -> best rank).
@@ -45,10 +61,10 @@
 #include <unistd.h>
 
 #define NBINS 64
-#define EPS 1e-9          /* decision band in scene units (R4)                  */
-#define VBAND 1e-6        /* radial band around a vertex that sits on a row plane */
-#define FLAT_DZ 1e-6      /* a crossing edge flatter than this is ill-conditioned */
-#define SHORT_SLICE 1e-6  /* a slice shorter than this has an ill-conditioned |C| */
+#define EPS 1e-9          /* decision band in scene units (R4)                       */
+#define U64 0x1p-53       /* unit roundoff of FP64                                     */
+#define CULL_MARGIN 1e-6  /* rows further than this from a triangle are not examined  */
+#define VBAND 1e-6        /* brute force: touching points this close to an edge count */
 
 /* ------------------------------------------------------------------ pixel grid */
 
@@ -81,7 +97,7 @@ static void normalize2(double a, double b, double* oa, double* ob, int identity_
     }
 }
 
-static void make_frame(const float* sv, const float* sn, frame_t* f)
+static void make_frame(const double* sv, const double* sn, frame_t* f)
 {
     double nx = sn[0], ny = sn[1], nz = sn[2];
     f->sv[0] = sv[0]; f->sv[1] = sv[1]; f->sv[2] = sv[2];
@@ -114,8 +130,9 @@ void oracle_project(const float* sv, const float* sn, const double* pts, int64_t
                     int printed, double* alpha, double* beta, double* txy)
 {
     frame_t f;
-    make_frame(sv, sn, &f);
-    if (printed) normalize2((double)sn[0], (double)sn[2], &f.nbx, &f.nbz, 0);
+    double svd[3] = { sv[0], sv[1], sv[2] }, snd[3] = { sn[0], sn[1], sn[2] };
+    make_frame(svd, snd, &f);
+    if (printed) normalize2(snd[0], snd[2], &f.nbx, &f.nbz, 0);
     for (int64_t i = 0; i < n; ++i) {
         double tx, ty, tz;
         project(&f, pts[3 * i], pts[3 * i + 1], pts[3 * i + 2], &tx, &ty, &tz);
@@ -128,24 +145,47 @@ void oracle_project(const float* sv, const float* sn, const double* pts, int64_t
 /* ------------------------------------------------------ row-range generation */
 
 typedef struct {
-    const float* pos; uint32_t nv;
+    const double* pos; uint32_t nv;
     const uint32_t* tri; uint32_t nt;
-    const float* op_pos; const float* op_nrm; uint32_t n;
+    const double* op_pos; const double* op_nrm; uint32_t n;
     double R;
     uint32_t* images;   /* [n][64][64] */
     uint8_t* flags;     /* [n][64][64] or NULL */
     uint64_t* work;     /* [n][3]: triangles visited, slices, pixel updates */
     int64_t first, last;
-    int status;
 } gen_job_t;
 
-static void flag_band(uint8_t* fl, int r, double R, double lo, double hi)
+/* One projected triangle: Eq. 2-4 coordinates of its vertices, their
+ * distances from the axis (Eq. 5), and a bound `ep` on the absolute rounding
+ * error of any projected coordinate.  The bound covers this file's FP64
+ * evaluation and any other FP64 evaluation of Eq. 1-4 from the same fp32
+ * inputs (a handful of roundings, each at most U64 times the magnitude of
+ * P - S_v), with a factor of 4 to spare. */
+typedef struct {
+    double x[3], y[3], z[3], a[3];
+    double ep;
+} ptri_t;
+
+/* Flag every column whose bin radius lies in [lo, hi] (row-relative: `fr` is
+ * the row's own 64 flags). */
+static void flag_band(uint8_t* fr, double R, double lo, double hi)
 {
-    if (!fl) return;
+    if (!fr || !(lo <= hi)) return;
     for (int c = 0; c < NBINS; ++c) {
         double rho = bin_radius(R, c);
-        if (rho >= lo && rho <= hi) fl[r * NBINS + c] = 1;
+        if (rho >= lo && rho <= hi) fr[c] = 1;
     }
+}
+
+/* distance from the origin to the 2-D segment p q */
+static double origin_segment_dist2d(double px, double py, double qx, double qy)
+{
+    double dx = qx - px, dy = qy - py;
+    double l2 = dx * dx + dy * dy;
+    double t = l2 > 0 ? -(px * dx + py * dy) / l2 : 0.0;
+    if (t < 0) t = 0;
+    if (t > 1) t = 1;
+    return hypot(px + t * dx, py + t * dy);
 }
 
 /* distance from the origin to the 2-D triangle (0 when it contains the origin) */
@@ -158,16 +198,144 @@ static double origin_triangle_dist2d(const double* x, const double* y)
     double best = INFINITY;
     for (int k = 0; k < 3; ++k) {
         int j = (k + 1) % 3;
-        double dx = x[j] - x[k], dy = y[j] - y[k];
-        double l2 = dx * dx + dy * dy;
-        double t = l2 > 0 ? -(x[k] * dx + y[k] * dy) / l2 : 0.0;
-        if (t < 0) t = 0;
-        if (t > 1) t = 1;
-        double qx = x[k] + t * dx, qy = y[k] + t * dy;
-        double d = sqrt(qx * qx + qy * qy);
+        double d = origin_segment_dist2d(x[k], y[k], x[j], y[j]);
         if (d < best) best = d;
     }
     return best;
+}
+
+/* The slice of a triangle by one row plane (Sec. 3.1.2 steps 1-6) under a
+ * given classification of its vertices (bit k of `above` set: vertex k lies
+ * above the plane), with error bounds for every quantity a decision compares.
+ * The crossing parameters are clamped to [0, 1], so a classification that
+ * disagrees with the computed heights (used for the alternatives of rule
+ * (iii)) still yields points on the triangle's edges. */
+typedef struct {
+    double d0, d1;        /* |E0|, |E1| */
+    double err0, err1;    /* bounds on their rounding errors */
+    double lo, hi;        /* single-intersection radii (lo, hi) */
+    int dbl;              /* double range (|C|, lo) present */
+    int dbl_unsure;       /* that decision lies within its error bound */
+    double cdist, errc;   /* |C| and its error bound */
+} slice_t;
+
+/* error bound of a crossing point on edge l -> o: the crossing parameter
+ * (beta - z_l) / (z_o - z_l) moves by about ep / |z_o - z_l| per unit error of
+ * a height, which the edge's length in the plane carries over to the point;
+ * clamping keeps the point on the edge, so the error never exceeds that
+ * length (plus the projection's own error) */
+static double crossing_err(const ptri_t* T, int l, int o)
+{
+    double dz = fabs(T->z[o] - T->z[l]);
+    double len = hypot(T->x[o] - T->x[l], T->y[o] - T->y[l]);
+    double e = dz > 0.0 ? 4.0 * T->ep * (1.0 + len / dz) : INFINITY;
+    return fmin(e, len + 4.0 * T->ep);
+}
+
+static double clamp01(double t) { return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t); }
+
+static int slice_row(const ptri_t* T, double beta, int above, slice_t* s)
+{
+    int na = ((above >> 0) & 1) + ((above >> 1) & 1) + ((above >> 2) & 1);
+    if (na == 0 || na == 3) return 0;
+    /* the vertex alone on its side; the slice joins its two edges */
+    int lone = 0;
+    for (int k = 0; k < 3; ++k) {
+        int up = (above >> k) & 1;
+        if ((na == 1 && up) || (na == 2 && !up)) lone = k;
+    }
+    int ia = (lone + 1) % 3, ib = (lone + 2) % 3;
+    const double* x = T->x; const double* y = T->y; const double* z = T->z;
+
+    /* step 1: the points E0, E1 where the plane crosses the two edges */
+    double t0 = clamp01((beta - z[lone]) / (z[ia] - z[lone]));
+    double t1 = clamp01((beta - z[lone]) / (z[ib] - z[lone]));
+    if (t0 != t0) t0 = 0.5;   /* 0/0: an edge lying in the plane (rule (iv) flags it) */
+    if (t1 != t1) t1 = 0.5;
+    double e0x = x[lone] + t0 * (x[ia] - x[lone]);
+    double e0y = y[lone] + t0 * (y[ia] - y[lone]);
+    double e1x = x[lone] + t1 * (x[ib] - x[lone]);
+    double e1y = y[lone] + t1 * (y[ib] - y[lone]);
+    double eE0 = crossing_err(T, lone, ia), eE1 = crossing_err(T, lone, ib);
+
+    /* step 2: rotate about z so that E0 -> E1 points along +x; the normalised
+     * E0E1 vector supplies cosine and sine directly */
+    double dx = e1x - e0x, dy = e1y - e0y;
+    double len = sqrt(dx * dx + dy * dy);
+    double x0r = 0, x1r = 0, yr = 0;
+    if (len > 0.0) {
+        double cs = dx / len, sn = dy / len;
+        x0r = e0x * cs + e0y * sn;
+        x1r = e1x * cs + e1y * sn;
+        yr = -e0x * sn + e0y * cs;
+    }
+    /* step 3: distances of E0 and E1 from the axis */
+    s->d0 = sqrt(e0x * e0x + e0y * e0y);
+    s->d1 = sqrt(e1x * e1x + e1y * e1y);
+    s->err0 = eE0 + 4.0 * U64 * s->d0;
+    s->err1 = eE1 + 4.0 * U64 * s->d1;
+    /* step 4: single intersections for radii in (min, max) */
+    s->lo = fmin(s->d0, s->d1);
+    s->hi = fmax(s->d0, s->d1);
+    /* step 5: a double intersection iff the rotated x coordinates of E0 and
+     * E1 have different signs (the foot C of the axis lies inside E0E1) */
+    s->dbl = (len > 0.0) && ((x0r < 0.0 && x1r > 0.0) || (x0r > 0.0 && x1r < 0.0));
+    /* step 6: double intersections for radii in (|C|, min(|E0|, |E1|)) */
+    s->cdist = len > 0.0 ? fabs(yr) : s->lo;
+
+    /* Error bounds of the step 5-6 quantities.  |C| = |E0 x E1| / |E1 - E0|:
+     * the cross product carries the points' errors times the other point's
+     * length, and the division amplifies both by 1 / |E1 - E0|.  When C lies
+     * inside the segment, |C| is at least lo - |E1 - E0|, so no bound needs
+     * to exceed the segment's length plus the points' errors. */
+    double eE = eE0 + eE1;
+    double dsum = s->d0 + s->d1;
+    double bound_c = len > 0.0 ? (eE * dsum + 4.0 * U64 * s->d0 * s->d1) / len
+                                 + s->cdist * (eE + 4.0 * U64 * len) / len + 4.0 * U64 * dsum
+                               : INFINITY;
+    s->errc = fmin(bound_c, len + 2.0 * eE);
+    /* the rotated x coordinates are E_k . (E1 - E0) / |E1 - E0|; their error
+     * is the points' errors times the lengths involved */
+    double err_x = eE * (dsum + len) / (len > 0.0 ? len : 1.0) + eE + 8.0 * U64 * dsum;
+    s->dbl_unsure = (len == 0.0) || fabs(x0r) <= err_x || fabs(x1r) <= err_x;
+    return 1;
+}
+
+/* Add one slice's counts to a row (Sec. 3.1 step 3) and return the number of
+ * pixels it changes. */
+static uint64_t slice_counts(const slice_t* s, double R, uint32_t* add)
+{
+    uint64_t updates = 0;
+    for (int c = 0; c < NBINS; ++c) {
+        double rho = bin_radius(R, c);
+        uint32_t v = 0;
+        if (s->lo < rho && rho < s->hi) v += 1;
+        if (s->dbl && s->cdist < rho && rho < s->lo) v += 2;
+        add[c] += v;
+        updates += v != 0;
+    }
+    return updates;
+}
+
+/* Rules (i) and (ii): pixels whose radius lies within EPS (plus the rounding
+ * bound of the computed quantity) of a slice end or of the foot point. */
+static void slice_flags(const slice_t* s, double R, uint8_t* fr)
+{
+    if (!fr) return;
+    flag_band(fr, R, s->d0 - EPS - s->err0, s->d0 + EPS + s->err0);                  /* (i)  */
+    flag_band(fr, R, s->d1 - EPS - s->err1, s->d1 + EPS + s->err1);
+    if (s->dbl_unsure) {                                                              /* (ii) */
+        /* were C inside the exact slice, its double range would lie between
+         * the exact slice's distance from the axis and its nearer end; the
+         * exact slice lies within the end points' errors of the computed one,
+         * whose distance from the axis is |C| (C inside) or lo (C outside) */
+        double elo = s->d0 <= s->d1 ? s->err0 : s->err1;
+        double emax = fmax(s->err0, s->err1);
+        double from = s->dbl ? s->cdist - fmax(s->errc, emax) : s->lo - emax;
+        flag_band(fr, R, from - EPS, s->lo + EPS + elo);
+    } else if (s->dbl) {
+        flag_band(fr, R, s->cdist - EPS - s->errc, s->cdist + EPS + s->errc);
+    }
 }
 
 static void rici_one_image(const gen_job_t* J, int64_t img)
@@ -187,99 +355,70 @@ static void rici_one_image(const gen_job_t* J, int64_t img)
 
     for (uint32_t t = 0; t < J->nt; ++t) {
         /* Step 1: project the triangle's vertices (Eq. 2 - 5). */
-        double x[3], y[3], z[3], a[3];
+        ptri_t T;
+        double mag = 0.5 * R;
         for (int k = 0; k < 3; ++k) {
-            const float* p = J->pos + 3 * (size_t)J->tri[3 * (size_t)t + k];
-            project(&f, p[0], p[1], p[2], &x[k], &y[k], &z[k]);
-            a[k] = sqrt(x[k] * x[k] + y[k] * y[k]);
+            const double* p = J->pos + 3 * (size_t)J->tri[3 * (size_t)t + k];
+            project(&f, p[0], p[1], p[2], &T.x[k], &T.y[k], &T.z[k]);
+            T.a[k] = sqrt(T.x[k] * T.x[k] + T.y[k] * T.y[k]);
+            mag = fmax(mag, fabs(p[0] - f.sv[0]) + fabs(p[1] - f.sv[1]) + fabs(p[2] - f.sv[2]));
         }
-        double zmin = fmin(z[0], fmin(z[1], z[2])), zmax = fmax(z[0], fmax(z[1], z[2]));
-        if (zmax < beta_lo - VBAND || zmin > beta_hi + VBAND) continue;
+        T.ep = 64.0 * U64 * mag;
+        const double band = EPS + T.ep;   /* a height this close to a row plane is ambiguous */
+        double zmin = fmin(T.z[0], fmin(T.z[1], T.z[2])), zmax = fmax(T.z[0], fmax(T.z[1], T.z[2]));
+        if (zmax < beta_lo - CULL_MARGIN || zmin > beta_hi + CULL_MARGIN) continue;
 
         /* Step 2: for each row plane in the triangle's beta extent, the radius
          * ranges of single and double intersections. */
         for (int r = 0; r < NBINS; ++r) {
             const double beta = bin_height(R, r);
-            uint8_t* flr = fl ? fl + r * NBINS : NULL;
-
-            /* C-D (iii): a vertex (almost) on the row plane */
-            int on_plane = 0;
+            uint8_t* fr = fl ? fl + (size_t)r * NBINS : NULL;
+            int above = 0, amb = 0, namb = 0;
             for (int k = 0; k < 3; ++k) {
-                if (fabs(z[k] - beta) < EPS) {
-                    ++on_plane;
-                    flag_band(flr, r, R, a[k] - VBAND, a[k] + VBAND);
+                if (T.z[k] >= beta) above |= 1 << k;                      /* R3 */
+                if (fabs(T.z[k] - beta) <= band) { amb |= 1 << k; ++namb; }
+            }
+
+            slice_t s;
+            if (slice_row(&T, beta, above, &s)) {
+                /* Step 3 of the triangle loop: increment the bins */
+                ++slices;
+                updates += slice_counts(&s, R, out + (size_t)r * NBINS);
+                slice_flags(&s, R, fr);
+            }
+            if (!fr || namb == 0) continue;
+
+            if (namb == 3) {
+                /* (iv) the whole triangle lies in the row plane (Sec. 3.1.2:
+                 * infinitely many intersections are not handled): every radius
+                 * the triangle covers is flagged */
+                double amax = fmax(T.a[0], fmax(T.a[1], T.a[2]));
+                flag_band(fr, R, origin_triangle_dist2d(T.x, T.y) - band, amax + band);
+            } else if (namb == 2) {
+                /* (iv) an edge lies in the row plane: the crossing can be
+                 * anywhere on it, so every radius the edge covers is flagged,
+                 * widened by the error of the crossings near its ends on the
+                 * third vertex's edges */
+                int m = (amb & 1) == 0 ? 0 : ((amb & 2) == 0 ? 1 : 2);
+                int k = (m + 1) % 3, j = (m + 2) % 3;
+                double w = band + fmax(crossing_err(&T, m, k), crossing_err(&T, m, j));
+                flag_band(fr, R, origin_segment_dist2d(T.x[k], T.y[k], T.x[j], T.y[j]) - w,
+                          fmax(T.a[k], T.a[j]) + w);
+            } else {
+                /* (iii) one vertex within `band` of the row plane: its side is
+                 * ambiguous, so the slice is also taken with that vertex on the
+                 * other side, and every pixel where the two disagree, or near a
+                 * decision of the other slice, is flagged */
+                uint32_t base[NBINS] = { 0 }, alt[NBINS] = { 0 };
+                slice_t s2;
+                if (slice_row(&T, beta, above, &s)) slice_counts(&s, R, base);
+                if (slice_row(&T, beta, above ^ amb, &s2)) {
+                    slice_counts(&s2, R, alt);
+                    slice_flags(&s2, R, fr);
                 }
+                for (int c = 0; c < NBINS; ++c)
+                    if (base[c] != alt[c]) fr[c] = 1;
             }
-            /* C-D (iv): the whole triangle lies in the row plane (Sec. 3.1.2:
-             * infinitely many intersections are not handled) */
-            if (on_plane == 3) {
-                double amax = fmax(a[0], fmax(a[1], a[2]));
-                flag_band(flr, r, R, origin_triangle_dist2d(x, y) - VBAND, amax + VBAND);
-            }
-
-            int above[3], na = 0;
-            for (int k = 0; k < 3; ++k) { above[k] = (z[k] >= beta); na += above[k]; }  /* R3 */
-            if (na == 0 || na == 3) continue;
-
-            /* the vertex alone on its side; the slice joins its two edges */
-            int lone = 0;
-            for (int k = 0; k < 3; ++k)
-                if ((na == 1 && above[k]) || (na == 2 && !above[k])) lone = k;
-            int ia = (lone + 1) % 3, ib = (lone + 2) % 3;
-
-            /* Sec. 3.1.2 step 1: intersection points E0, E1 of the plane with
-             * the two crossing edges */
-            double t0 = (beta - z[lone]) / (z[ia] - z[lone]);
-            double t1 = (beta - z[lone]) / (z[ib] - z[lone]);
-            double e0x = x[lone] + t0 * (x[ia] - x[lone]);
-            double e0y = y[lone] + t0 * (y[ia] - y[lone]);
-            double e1x = x[lone] + t1 * (x[ib] - x[lone]);
-            double e1y = y[lone] + t1 * (y[ib] - y[lone]);
-
-            /* step 2: rotate about z so that E0 -> E1 points along +x; the
-             * normalised E0E1 vector supplies cosine and sine directly */
-            double dx = e1x - e0x, dy = e1y - e0y;
-            double len = sqrt(dx * dx + dy * dy);
-            double x0r = 0, x1r = 0, yr = 0;
-            if (len > 0.0) {
-                double cs = dx / len, sn = dy / len;
-                x0r = e0x * cs + e0y * sn;
-                x1r = e1x * cs + e1y * sn;
-                yr = -e0x * sn + e0y * cs;
-            }
-            /* step 3: distances of E0 and E1 from the z axis */
-            double d0 = sqrt(e0x * e0x + e0y * e0y);
-            double d1 = sqrt(e1x * e1x + e1y * e1y);
-            /* step 4: single intersections for radii in (min, max) */
-            double lo = fmin(d0, d1), hi = fmax(d0, d1);
-            /* step 5: a double intersection exists iff the rotated x
-             * coordinates of E0 and E1 have different signs */
-            int dbl = (len > 0.0) && ((x0r < 0.0 && x1r > 0.0) || (x0r > 0.0 && x1r < 0.0));
-            /* step 6: double intersections for radii in (|y|, min(|E0|, |E1|)) */
-            double cdist = fabs(yr);
-
-            /* Step 3 of the triangle loop: increment the bins */
-            ++slices;
-            for (int c = 0; c < NBINS; ++c) {
-                double rho = bin_radius(R, c);
-                uint32_t add = 0;
-                if (lo < rho && rho < hi) add += 1;
-                if (dbl && cdist < rho && rho < lo) add += 2;
-                if (add) { out[r * NBINS + c] += add; ++updates; }
-                if (flr) {
-                    if (fabs(rho - d0) < EPS || fabs(rho - d1) < EPS) flr[c] = 1;   /* C-D (i)  */
-                    if (dbl && fabs(rho - cdist) < EPS) flr[c] = 1;                 /* C-D (ii) */
-                }
-            }
-            /* C-D (v): a crossing edge almost parallel to the row plane puts
-             * the intersection point out of reach of FP64 rounding bounds */
-            if (fabs(z[ia] - z[lone]) < FLAT_DZ || fabs(z[ib] - z[lone]) < FLAT_DZ)
-                flag_band(flr, r, R, (dbl ? cdist : lo) - VBAND, hi + VBAND);
-            /* C-D (vi): for a very short slice the direction E0 -> E1, hence
-             * |C| and the double/single decision, is ill-conditioned; every
-             * radius it can affect lies within SHORT_SLICE of lo */
-            if (len < SHORT_SLICE)
-                flag_band(flr, r, R, lo - SHORT_SLICE - VBAND, hi + VBAND);
         }
     }
     if (J->work) {
@@ -354,8 +493,8 @@ static void brute_one_image(const gen_job_t* J, int64_t img)
     memset(out, 0, sizeof(uint32_t) * NBINS * NBINS);
     if (fl) memset(fl, 0, NBINS * NBINS);
 
-    const float* svf = J->op_pos + 3 * img;
-    const float* snf = J->op_nrm + 3 * img;
+    const double* svf = J->op_pos + 3 * img;
+    const double* snf = J->op_nrm + 3 * img;
     double sv[3] = { svf[0], svf[1], svf[2] };
     double n[3] = { snf[0], snf[1], snf[2] };
     double nl = sqrt(dot3(n, n));
@@ -367,7 +506,7 @@ static void brute_one_image(const gen_job_t* J, int64_t img)
     for (uint32_t t = 0; t < J->nt; ++t) {
         double p[3][3];
         for (int k = 0; k < 3; ++k) {
-            const float* q = J->pos + 3 * (size_t)J->tri[3 * (size_t)t + k];
+            const double* q = J->pos + 3 * (size_t)J->tri[3 * (size_t)t + k];
             p[k][0] = q[0]; p[k][1] = q[1]; p[k][2] = q[2];
         }
         double e1[3], e2[3], m[3];
@@ -476,14 +615,47 @@ static int check_mesh(const uint32_t* tri, uint32_t nt, uint32_t nv)
     return 0;
 }
 
-/* RICI images by the paper's row-range algorithm.  flags / work may be NULL.
- * Returns 0, or -1 when a triangle index is out of range. */
+static double* widen(const float* a, size_t n)
+{
+    double* d = (double*)malloc((n ? n : 1) * sizeof(double));
+    if (d) for (size_t i = 0; i < n; ++i) d[i] = a[i];
+    return d;
+}
+
+static int run_widened(const float* pos, uint32_t nv, const uint32_t* tri, uint32_t nt,
+                       const float* op_pos, const float* op_nrm, uint32_t n, float R,
+                       uint32_t* images, uint8_t* flags, uint64_t* work, img_fn fn, int nthreads)
+{
+    if (check_mesh(tri, nt, nv)) return -1;
+    double* p = widen(pos, (size_t)nv * 3);
+    double* o = widen(op_pos, (size_t)n * 3);
+    double* m = widen(op_nrm, (size_t)n * 3);
+    int rc = -2;
+    if (p && o && m) {
+        gen_job_t J = { p, nv, tri, nt, o, m, n, (double)R, images, flags, work, 0, n };
+        rc = run_images(&J, fn, nthreads);
+    }
+    free(p); free(o); free(m);
+    return rc;
+}
+
+/* RICI images by the paper's row-range algorithm, from fp32 inputs (converted
+ * exactly to FP64).  flags / work may be NULL.  Returns 0, -1 when a triangle
+ * index is out of range, -2 when host memory runs out. */
 int oracle_rici_rowrange(const float* pos, uint32_t nv, const uint32_t* tri, uint32_t nt,
                          const float* op_pos, const float* op_nrm, uint32_t n, float R,
                          uint32_t* images, uint8_t* flags, uint64_t* work, int nthreads)
 {
+    return run_widened(pos, nv, tri, nt, op_pos, op_nrm, n, R, images, flags, work, rici_one_image, nthreads);
+}
+
+/* The same from FP64 inputs (for pins that need positions fp32 cannot hold). */
+int oracle_rici_rowrange_f64(const double* pos, uint32_t nv, const uint32_t* tri, uint32_t nt,
+                             const double* op_pos, const double* op_nrm, uint32_t n, double R,
+                             uint32_t* images, uint8_t* flags, uint64_t* work, int nthreads)
+{
     if (check_mesh(tri, nt, nv)) return -1;
-    gen_job_t J = { pos, nv, tri, nt, op_pos, op_nrm, n, (double)R, images, flags, work, 0, n, 0 };
+    gen_job_t J = { pos, nv, tri, nt, op_pos, op_nrm, n, R, images, flags, work, 0, n };
     return run_images(&J, rici_one_image, nthreads);
 }
 
@@ -492,101 +664,153 @@ int oracle_rici_brute(const float* pos, uint32_t nv, const uint32_t* tri, uint32
                       const float* op_pos, const float* op_nrm, uint32_t n, float R,
                       uint32_t* images, uint8_t* flags, int nthreads)
 {
+    return run_widened(pos, nv, tri, nt, op_pos, op_nrm, n, R, images, flags, NULL, brute_one_image, nthreads);
+}
+
+int oracle_rici_brute_f64(const double* pos, uint32_t nv, const uint32_t* tri, uint32_t nt,
+                          const double* op_pos, const double* op_nrm, uint32_t n, double R,
+                          uint32_t* images, uint8_t* flags, int nthreads)
+{
     if (check_mesh(tri, nt, nv)) return -1;
-    gen_job_t J = { pos, nv, tri, nt, op_pos, op_nrm, n, (double)R, images, flags, NULL, 0, n, 0 };
+    gen_job_t J = { pos, nv, tri, nt, op_pos, op_nrm, n, R, images, flags, NULL, 0, n };
     return run_images(&J, brute_one_image, nthreads);
 }
 
 /* ------------------------------------------------------ distance and rank */
 
-/* Eq. 6: D(rici, r, c) = rici(r, c) - rici(r, c - 1), in signed 64-bit. */
-static int64_t delta(const uint32_t* img, int r, int c)
+#define NDELTA (NBINS * (NBINS - 1))   /* R5: rows 0..63, columns 1..63 */
+
+/* Eq. 6 for every pixel the distance uses: D(r, c) = I(r, c) - I(r, c - 1),
+ * signed, stored at r * 63 + (c - 1). */
+static void delta_plane(const uint32_t* img, int64_t* D)
 {
-    return (int64_t)img[r * NBINS + c] - (int64_t)img[r * NBINS + c - 1];
+    for (int r = 0; r < NBINS; ++r)
+        for (int c = 1; c < NBINS; ++c)
+            D[r * (NBINS - 1) + c - 1] = (int64_t)img[r * NBINS + c] - (int64_t)img[r * NBINS + c - 1];
 }
 
-/* Eq. 7: squared differences of column deltas where the needle's delta is
- * non-zero (R5 index ranges). */
+/* Eq. 7 over two delta planes: the squared difference of the deltas, summed
+ * over the pixels where the needle's delta is non-zero. */
+static int64_t masked_sq_sum(const int64_t* Dn, const int64_t* Dh)
+{
+    int64_t sum = 0;
+    for (int i = 0; i < NDELTA; ++i) {
+        int64_t diff = Dn[i] - Dh[i];
+        int64_t mask = Dn[i] != 0;
+        sum += mask * diff * diff;
+    }
+    return sum;
+}
+
+/* CRD(needle, haystack) of Eq. 7 (Sec. 3.2). */
 int64_t oracle_crd(const uint32_t* needle, const uint32_t* haystack)
 {
-    int64_t score = 0;
-    for (int r = 0; r < NBINS; ++r) {
-        for (int c = 1; c < NBINS; ++c) {
-            int64_t nd = delta(needle, r, c);
-            int64_t hd = delta(haystack, r, c);
-            if (nd != 0) score += (nd - hd) * (nd - hd);
-        }
-    }
-    return score;
+    int64_t Dn[NDELTA], Dh[NDELTA];
+    delta_plane(needle, Dn);
+    delta_plane(haystack, Dh);
+    return masked_sq_sum(Dn, Dh);
 }
+
+/* Needles are handled in blocks: their delta planes are built once, then the
+ * threads split the haystack, each counting (or writing distances) for every
+ * needle of the block over its own range of haystack images. */
+#define NEEDLE_BLOCK 64
 
 typedef struct {
-    const uint32_t* needles; uint32_t nn;
+    const int64_t* planes; uint32_t nb;     /* this block's needle planes */
     const uint32_t* hay; uint32_t nh;
-    const uint32_t* true_idx;
-    uint32_t* rank; int64_t* dstar; int64_t* matrix;
-    int64_t first, last;
+    const int64_t* dstar;                   /* rank: thresholds of the block, else NULL */
+    uint32_t* counts;                       /* rank: this thread's [nb] counts */
+    int64_t* matrix; size_t row_stride;     /* matrix: rows of the block */
+    int64_t first, last;                    /* haystack range */
 } search_job_t;
 
-static void* rank_worker(void* arg)
+static void* search_worker(void* arg)
 {
     search_job_t* J = (search_job_t*)arg;
-    for (int64_t i = J->first; i < J->last; ++i) {
-        const uint32_t* nd = J->needles + (size_t)i * NBINS * NBINS;
-        int64_t d = oracle_crd(nd, J->hay + (size_t)J->true_idx[i] * NBINS * NBINS);
-        uint32_t k = 0;
-        for (uint32_t h = 0; h < J->nh; ++h)
-            if (oracle_crd(nd, J->hay + (size_t)h * NBINS * NBINS) < d) ++k;   /* R6 */
-        J->rank[i] = k;
-        if (J->dstar) J->dstar[i] = d;
+    int64_t Dh[NDELTA];
+    for (int64_t h = J->first; h < J->last; ++h) {
+        delta_plane(J->hay + (size_t)h * NBINS * NBINS, Dh);
+        for (uint32_t i = 0; i < J->nb; ++i) {
+            int64_t d = masked_sq_sum(J->planes + (size_t)i * NDELTA, Dh);
+            if (J->matrix) J->matrix[(size_t)i * J->row_stride + (size_t)h] = d;
+            else if (d < J->dstar[i]) ++J->counts[i];                         /* R6 */
+        }
     }
     return NULL;
 }
 
-static void* matrix_worker(void* arg)
-{
-    search_job_t* J = (search_job_t*)arg;
-    for (int64_t i = J->first; i < J->last; ++i) {
-        const uint32_t* nd = J->needles + (size_t)i * NBINS * NBINS;
-        for (uint32_t h = 0; h < J->nh; ++h)
-            J->matrix[(size_t)i * J->nh + h] = oracle_crd(nd, J->hay + (size_t)h * NBINS * NBINS);
-    }
-    return NULL;
-}
-
-static int run_search(search_job_t* base, void* (*fn)(void*), int nthreads)
+/* rank (counts != NULL) or matrix (matrix != NULL) of one needle block */
+static int search_block(const int64_t* planes, uint32_t nb, const uint32_t* hay, uint32_t nh,
+                        const int64_t* dstar, uint32_t* rank, int64_t* matrix, size_t row_stride, int nthreads)
 {
     int nt = resolve_threads(nthreads);
     if (nt > 512) nt = 512;
-    if ((int64_t)nt > (int64_t)base->nn) nt = base->nn > 0 ? (int)base->nn : 1;
+    if ((int64_t)nt > (int64_t)nh) nt = nh > 0 ? (int)nh : 1;
     pthread_t th[512];
     search_job_t jobs[512];
+    uint32_t* counts = rank ? (uint32_t*)calloc((size_t)nt * nb, sizeof(uint32_t)) : NULL;
+    if (rank && !counts) return -2;
     for (int k = 0; k < nt; ++k) {
-        jobs[k] = *base;
-        jobs[k].first = (int64_t)base->nn * k / nt;
-        jobs[k].last = (int64_t)base->nn * (k + 1) / nt;
-        if (pthread_create(&th[k], NULL, fn, &jobs[k]) != 0) { fn(&jobs[k]); th[k] = 0; }
+        search_job_t j = { planes, nb, hay, nh, dstar, counts ? counts + (size_t)k * nb : NULL, matrix, row_stride,
+                           (int64_t)nh * k / nt, (int64_t)nh * (k + 1) / nt };
+        jobs[k] = j;
+        if (pthread_create(&th[k], NULL, search_worker, &jobs[k]) != 0) { search_worker(&jobs[k]); th[k] = 0; }
     }
     for (int k = 0; k < nt; ++k) if (th[k]) pthread_join(th[k], NULL);
+    if (rank) {
+        for (uint32_t i = 0; i < nb; ++i) {
+            uint32_t s = 0;
+            for (int k = 0; k < nt; ++k) s += counts[(size_t)k * nb + i];
+            rank[i] = s;
+        }
+        free(counts);
+    }
     return 0;
 }
 
 /* rank[i] = #{h : CRD(needle_i, h) < CRD(needle_i, haystack[true_idx[i]])};
- * dstar (may be NULL) receives the true-match distances.  -1 on a bad index. */
+ * dstar (may be NULL) receives the true-match distances.  -1 on a bad index,
+ * -2 when host memory runs out. */
 int oracle_rank(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                 const uint32_t* true_idx, uint32_t* rank, int64_t* dstar, int nthreads)
 {
     for (uint32_t i = 0; i < nn; ++i) if (true_idx[i] >= nh) return -1;
-    search_job_t J = { needles, nn, hay, nh, true_idx, rank, dstar, NULL, 0, nn };
-    return run_search(&J, rank_worker, nthreads);
+    int64_t* planes = (int64_t*)malloc((size_t)NEEDLE_BLOCK * NDELTA * sizeof(int64_t));
+    int64_t thr[NEEDLE_BLOCK];
+    int64_t Dh[NDELTA];
+    if (!planes) return -2;
+    int rc = 0;
+    for (uint32_t b = 0; b < nn && rc == 0; b += NEEDLE_BLOCK) {
+        uint32_t nb = nn - b < NEEDLE_BLOCK ? nn - b : NEEDLE_BLOCK;
+        for (uint32_t i = 0; i < nb; ++i) {
+            int64_t* Dn = planes + (size_t)i * NDELTA;
+            delta_plane(needles + (size_t)(b + i) * NBINS * NBINS, Dn);
+            delta_plane(hay + (size_t)true_idx[b + i] * NBINS * NBINS, Dh);
+            thr[i] = masked_sq_sum(Dn, Dh);
+            if (dstar) dstar[b + i] = thr[i];
+        }
+        rc = search_block(planes, nb, hay, nh, thr, rank + b, NULL, 0, nthreads);
+    }
+    free(planes);
+    return rc;
 }
 
 /* full CRD matrix [nn][nh] */
 int oracle_distance_matrix(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                            int64_t* out, int nthreads)
 {
-    search_job_t J = { needles, nn, hay, nh, NULL, NULL, NULL, out, 0, nn };
-    return run_search(&J, matrix_worker, nthreads);
+    int64_t* planes = (int64_t*)malloc((size_t)NEEDLE_BLOCK * NDELTA * sizeof(int64_t));
+    if (!planes) return -2;
+    int rc = 0;
+    for (uint32_t b = 0; b < nn && rc == 0; b += NEEDLE_BLOCK) {
+        uint32_t nb = nn - b < NEEDLE_BLOCK ? nn - b : NEEDLE_BLOCK;
+        for (uint32_t i = 0; i < nb; ++i)
+            delta_plane(needles + (size_t)(b + i) * NBINS * NBINS, planes + (size_t)i * NDELTA);
+        rc = search_block(planes, nb, hay, nh, NULL, NULL, out + (size_t)b * nh, nh, nthreads);
+    }
+    free(planes);
+    return rc;
 }
 
 int oracle_threads(int nthreads) { return resolve_threads(nthreads); }

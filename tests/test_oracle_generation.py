@@ -189,15 +189,32 @@ def test_rows_next_to_every_row_plane():
 def test_degenerate_triangles_rowrange_equals_brute_force():
     """Points, segments, a triangle in a row plane, edges and vertices on row
     planes and an edge on the axis: the row-range algorithm equals the
-    brute-force definition wherever neither flags a pixel, and flags none
-    itself (the half-open row convention decides every plane contact)."""
+    brute-force definition wherever neither flags a pixel, and each triangle
+    flags exactly the pixels its contact with a row plane makes ambiguous, in
+    that row: the triangle lying in row plane 40 the radii it covers (its
+    farthest vertex is at 0.566, so columns 0..35); the edge in row plane 20
+    the radii of that edge (0.25 .. 0.39: columns 16..24); the edge in row
+    plane 10 the radii 0.15 .. 0.45 (columns 10..28).  A lone vertex on row
+    plane 30 flags nothing: both sides of it give the same slice."""
     v, t = closed_forms.degenerate_triangles()
     sv, sn = np.zeros((1, 3), np.float32), np.array([[0, 0, 1]], np.float32)
     o, fl, _ = oracle.rici_rowrange(v, t, sv, sn, 1.0)
     ob, flb = oracle.rici_brute(v, t, sv, sn, 1.0)
-    assert not fl.any() and o.sum() > 0
+    assert o.sum() > 0
     m = ~(fl | flb)
     assert np.array_equal(o[m], ob[m])
+    expected = np.zeros((NB, NB), bool)
+    expected[40, 0:36] = True
+    expected[20, 16:25] = True
+    expected[10, 10:29] = True
+    assert np.array_equal(fl[0], expected)
+    for k, (row, cols) in enumerate([(None, None), (None, None), (None, None), (40, range(0, 36)),
+                                     (20, range(16, 25)), (10, range(10, 29)), (None, None)]):
+        _, f1, _ = oracle.rici_rowrange(v, t[k:k + 1], sv, sn, 1.0)
+        want = np.zeros((NB, NB), bool)
+        if row is not None:
+            want[row, list(cols)] = True
+        assert np.array_equal(f1[0], want), k
 
 
 def test_closed_surface_counts_are_even():
