@@ -92,6 +92,33 @@ int rici_generate(rici_handle h,
                   float support_radius, uint32_t* out_images, void* stream);
 
 /*
+ * rici_generate_noalloc -- rici_generate for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, checks, kernels and results as
+ * rici_generate; the difference is where the triangle preparation records
+ * live: in a static workspace of the library (one per GPU, about 64 MiB, held
+ * until the process ends, its address looked up by rici_create) instead of the
+ * handle's growable scratch.  The call allocates nothing and never
+ * synchronises.
+ *   num_triangles  at most RICI_NOALLOC_MAX_TRIANGLES; a larger mesh returns
+ *                  RICI_ERR_UNSUPPORTED (checked right after the handle,
+ *                  before the other arguments) and nothing is enqueued.
+ * Every call on one GPU shares that GPU's workspace, whatever the handle:
+ * calls whose work overlaps on one GPU (on different streams, or from
+ * different threads) race and give unspecified images.  Serialise them, for
+ * instance on one stream.  Nothing in the workspace needs to start at zero
+ * (each call rewrites the records it reads).  Kernel timing does not cover
+ * this call.  RICI_ERR_HIP if the workspace's address could not be found.
+ */
+#define RICI_NOALLOC_MAX_TRIANGLES (1u << 20)
+
+int rici_generate_noalloc(rici_handle h,
+                          const float* positions, uint32_t num_vertices,
+                          const uint32_t* triangles, uint32_t num_triangles,
+                          const float* op_positions, const float* op_normals, uint32_t num_points,
+                          float support_radius, uint32_t* out_images, void* stream);
+
+/*
  * rici_distance_rank -- rank of the true match (Sec. 4.1 step 6c) under the
  * clutter-resistant distance CRD (Sec. 3.2, Eq. 6-7):
  *   CRD(n, h) = sum over rows r in [0, 64), columns c in [1, 64) with

@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "rici.h")
 
 EXPORTS = [
     "rici_create", "rici_destroy", "rici_last_error", "rici_sync", "rici_device_errors",
-    "rici_generate", "rici_distance_rank", "rici_distance_matrix",
+    "rici_generate", "rici_generate_noalloc", "rici_distance_rank", "rici_distance_matrix",
     "rici_timing_enable", "rici_timing_reset", "rici_timing_get",
     "rici_batch_create", "rici_batch_run", "rici_batch_destroy", "rici_batch_scratch_bytes",
     "rici_db_create", "rici_db_tiles", "rici_db_scratch_bytes", "rici_db_destroy",
@@ -75,6 +75,8 @@ def load(path: str = LIB_PATH):
         lib.rici_device_errors.restype = U32
         lib.rici_generate.argtypes = [P, P, U32, P, U32, P, P, U32, F32, P, P]
         lib.rici_generate.restype = I32
+        lib.rici_generate_noalloc.argtypes = [P, P, U32, P, U32, P, P, U32, F32, P, P]
+        lib.rici_generate_noalloc.restype = I32
         lib.rici_distance_rank.argtypes = [P, P, U32, P, U32, P, P, P, P]
         lib.rici_distance_rank.restype = I32
         lib.rici_distance_matrix.argtypes = [P, P, U32, P, U32, P, P]

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,7 @@ struct rici_ctx {
     uint32_t last_dev_err = 0;
     void* ws = nullptr;             // scratch
     size_t ws_size = 0;
+    void* noalloc = nullptr;        // this device's address of the static generation workspace
     bool timing = false;
     int search_variant = 0;         // search tile: 0 = 256 x 256, 1 = 128 x 256
     int gen_group = 2;              // images per generation workgroup: 2 or 4
@@ -94,6 +96,49 @@ hipError_t timed(rici_ctx* h, const char* name, hipStream_t s, F&& launch)
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ------------------------------------------------ static generation workspace
+// rici_generate_noalloc keeps the triangle preparation records of at most
+// RICI_NOALLOC_MAX_TRIANGLES triangles (bounding spheres, 64-triangle cluster
+// spheres, vertices) in this array instead of the handle's growable scratch.
+// Every GPU the library runs on holds one copy until the process ends.  In
+// host code `scratch` only names the variable: its device address is looked up
+// once per device (noalloc_address) and only that address is used.
+constexpr size_t kNoallocCullBytes = ((size_t)RICI_NOALLOC_MAX_TRIANGLES * rici::kTriCullBytes + 255) & ~(size_t)255;
+constexpr size_t kNoallocClusBytes =
+    (((size_t)RICI_NOALLOC_MAX_TRIANGLES + 63) / 64 * rici::kTriCullBytes + 255) & ~(size_t)255;
+constexpr size_t kNoallocVertBytes = ((size_t)RICI_NOALLOC_MAX_TRIANGLES * rici::kTriVertBytes + 255) & ~(size_t)255;
+constexpr size_t kNoallocBytes = kNoallocCullBytes + kNoallocClusBytes + kNoallocVertBytes;
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices];
+hipError_t g_noalloc_err[kMaxDevices];
+bool g_noalloc_done[kMaxDevices];
+
+// Device address of `scratch` on `device` (which must be current), looked up on
+// the first call for that device and kept.  Returns the lookup's error code.
+hipError_t noalloc_address(int device, void** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_done[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        g_noalloc_ptr[device] = p;
+        g_noalloc_err[device] = e;
+        g_noalloc_done[device] = true;
+    }
+    *out = g_noalloc_ptr[device];
+    return g_noalloc_err[device];
+}
 
 // Grows the handle's scratch to at least `bytes` (synchronises the device).
 int ensure_ws(rici_ctx* h, size_t bytes)
@@ -168,6 +213,8 @@ int rici_create(rici_handle* out, int device)
         delete h;
         return hip_fail(e, "hipMemset(error word)");
     }
+    // a failed lookup only disables rici_generate_noalloc (which reports it)
+    (void)noalloc_address(device, &h->noalloc);
     *out = h;
     return RICI_OK;
 }
@@ -210,39 +257,42 @@ int rici_sync(rici_handle h, void* stream)
 
 uint32_t rici_device_errors(rici_handle h) { return h ? h->last_dev_err : 0u; }
 
-int rici_generate(rici_handle h, const float* positions, uint32_t num_vertices, const uint32_t* triangles,
-                  uint32_t num_triangles, const float* op_positions, const float* op_normals, uint32_t num_points,
-                  float support_radius, uint32_t* out_images, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by rici_generate and rici_generate_noalloc.
+int check_generate_args(const char* fn, rici_handle h, const float* positions, uint32_t num_vertices,
+                        const uint32_t* triangles, uint32_t num_triangles, const float* op_positions,
+                        const float* op_normals, uint32_t num_points, float support_radius, const uint32_t* out_images)
 {
-    if (!h) return fail(RICI_ERR_INVALID, "rici_generate: NULL handle");
+    if (!h) return fail(RICI_ERR_INVALID, "%s: NULL handle", fn);
     if (!(isfinite(support_radius) && support_radius > 0.0f))
-        return fail(RICI_ERR_INVALID, "rici_generate: support_radius must be finite and > 0");
-    if (num_triangles >= (1u << 29)) return fail(RICI_ERR_UNSUPPORTED, "rici_generate: num_triangles >= 2^29");
-    if (num_points >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "rici_generate: num_points >= 2^31");
+        return fail(RICI_ERR_INVALID, "%s: support_radius must be finite and > 0", fn);
+    if (num_triangles >= (1u << 29)) return fail(RICI_ERR_UNSUPPORTED, "%s: num_triangles >= 2^29", fn);
+    if (num_points >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "%s: num_points >= 2^31", fn);
     if (num_points == 0) return RICI_OK;
     if (!op_positions || !op_normals || !out_images)
-        return fail(RICI_ERR_INVALID, "rici_generate: NULL oriented-point or output pointer");
+        return fail(RICI_ERR_INVALID, "%s: NULL oriented-point or output pointer", fn);
     if (num_triangles > 0 && (!triangles || !positions || num_vertices == 0))
-        return fail(RICI_ERR_INVALID, "rici_generate: NULL mesh pointer or no vertices");
-    if (misaligned(out_images)) return fail(RICI_ERR_INVALID, "rici_generate: out_images is not 16-byte aligned");
+        return fail(RICI_ERR_INVALID, "%s: NULL mesh pointer or no vertices", fn);
+    if (misaligned(out_images)) return fail(RICI_ERR_INVALID, "%s: out_images is not 16-byte aligned", fn);
     const size_t out_bytes = (size_t)num_points * rici::NPIX * sizeof(uint32_t);
     if (overlaps(out_images, out_bytes, positions, (size_t)num_vertices * 12) ||
         overlaps(out_images, out_bytes, triangles, (size_t)num_triangles * 12) ||
         overlaps(out_images, out_bytes, op_positions, (size_t)num_points * 12) ||
         overlaps(out_images, out_bytes, op_normals, (size_t)num_points * 12))
-        return fail(RICI_ERR_INVALID, "rici_generate: output overlaps an input");
+        return fail(RICI_ERR_INVALID, "%s: output overlaps an input", fn);
+    return RICI_OK;
+}
 
-    DeviceGuard g(h->device);
-    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-    hipStream_t s = (hipStream_t)stream;
-    const size_t cull_bytes = align256((size_t)num_triangles * rici::kTriCullBytes);
-    const size_t clus_bytes = align256(((size_t)num_triangles + 63) / 64 * rici::kTriCullBytes);
-    const size_t vert_bytes = align256((size_t)num_triangles * rici::kTriVertBytes);
-    int rc = ensure_ws(h, cull_bytes + clus_bytes + vert_bytes + 256);
-    if (rc) return rc;
-    float4* cull = (float4*)h->ws;
-    float4* clusters = (float4*)((char*)h->ws + cull_bytes);
-    float4* verts = (float4*)((char*)h->ws + cull_bytes + clus_bytes);
+// Triangle preparation, cluster spheres and the generation kernel, with the
+// preparation records at cull / clusters / verts.
+int enqueue_generate(rici_ctx* h, const float* positions, uint32_t num_vertices, const uint32_t* triangles,
+                     uint32_t num_triangles, const float* op_positions, const float* op_normals, uint32_t num_points,
+                     float support_radius, uint32_t* out_images, float4* cull, float4* clusters, float4* verts,
+                     hipStream_t s)
+{
     hipError_t e = timed(h, "gen_prep", s, [&] {
         hipError_t e1 = rici::launch_gen_prep(positions, num_vertices, triangles, num_triangles, h->gen_sort, cull, verts,
                                               h->d_err, s);
@@ -255,6 +305,65 @@ int rici_generate(rici_handle h, const float* positions, uint32_t num_vertices, 
     });
     if (e != hipSuccess) return hip_fail(e, "gen launch");
     return RICI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rici_generate(rici_handle h, const float* positions, uint32_t num_vertices, const uint32_t* triangles,
+                  uint32_t num_triangles, const float* op_positions, const float* op_normals, uint32_t num_points,
+                  float support_radius, uint32_t* out_images, void* stream)
+{
+    int rc = check_generate_args("rici_generate", h, positions, num_vertices, triangles, num_triangles, op_positions,
+                                 op_normals, num_points, support_radius, out_images);
+    if (rc || num_points == 0) return rc;
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    const size_t cull_bytes = align256((size_t)num_triangles * rici::kTriCullBytes);
+    const size_t clus_bytes = align256(((size_t)num_triangles + 63) / 64 * rici::kTriCullBytes);
+    const size_t vert_bytes = align256((size_t)num_triangles * rici::kTriVertBytes);
+    rc = ensure_ws(h, cull_bytes + clus_bytes + vert_bytes + 256);
+    if (rc) return rc;
+    float4* cull = (float4*)h->ws;
+    float4* clusters = (float4*)((char*)h->ws + cull_bytes);
+    float4* verts = (float4*)((char*)h->ws + cull_bytes + clus_bytes);
+    return enqueue_generate(h, positions, num_vertices, triangles, num_triangles, op_positions, op_normals, num_points,
+                            support_radius, out_images, cull, clusters, verts, (hipStream_t)stream);
+}
+
+int rici_generate_noalloc(rici_handle h, const float* positions, uint32_t num_vertices, const uint32_t* triangles,
+                          uint32_t num_triangles, const float* op_positions, const float* op_normals,
+                          uint32_t num_points, float support_radius, uint32_t* out_images, void* stream)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_generate_noalloc: NULL handle");
+    if (num_triangles > RICI_NOALLOC_MAX_TRIANGLES)
+        return fail(RICI_ERR_UNSUPPORTED,
+                    "rici_generate_noalloc: %u triangles exceed the static workspace of %u triangles "
+                    "(use rici_generate)", num_triangles, (unsigned)RICI_NOALLOC_MAX_TRIANGLES);
+    int rc = check_generate_args("rici_generate_noalloc", h, positions, num_vertices, triangles, num_triangles,
+                                 op_positions, op_normals, num_points, support_radius, out_images);
+    if (rc) return rc;
+    if (!h->noalloc) {
+        void* p = nullptr;
+        hipError_t e = noalloc_address(h->device, &p);
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                        "rici_generate_noalloc: hipGetSymbolAddress(static workspace)");
+    }
+    if (num_points == 0) return RICI_OK;
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    char* base = (char*)h->noalloc;
+    float4* cull = (float4*)base;
+    float4* clusters = (float4*)(base + kNoallocCullBytes);
+    float4* verts = (float4*)(base + kNoallocCullBytes + kNoallocClusBytes);
+    // no event bracketing: timing would create events
+    const bool timing = h->timing;
+    h->timing = false;
+    rc = enqueue_generate(h, positions, num_vertices, triangles, num_triangles, op_positions, op_normals, num_points,
+                          support_radius, out_images, cull, clusters, verts, (hipStream_t)stream);
+    h->timing = timing;
+    return rc;
 }
 
 namespace {
