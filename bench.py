@@ -1,16 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the whole RICI hot path on one MI355X.
 
-One step = describe and rank one synthetic scene: every vertex of the union of
-12 seeded superquadrics (23 352 oriented points, 46 656 triangles, support
-radius 0.3, 64x64 images) gets its RICI (rici_generate), and every RICI is
-ranked as a needle against all 23 352 RICIs as the haystack
-(rici_distance_rank: column deltas, CRD contractions, true-match distance,
-counts).  Inputs are resident in HBM before timing starts.
+Default workload, the largest single-GPU configuration: 256 seeded meshes
+(superquadrics and tori, triangle counts log-uniform in [1k, 200k], each in its
+own frame, support radius 0.3, 64x64 images).  One step = one replay of the
+batched describe-and-rank plan (rici_batch_run, a HIP graph of persistent
+kernels): every vertex of every mesh gets its RICI, and every RICI is ranked as
+a needle against all RICIs of its own mesh (column deltas, CRD contractions,
+true-match distance, counts).  Inputs are resident in HBM before timing starts.
+
+The same run also measures the plain per-mesh path on the same meshes
+(rici_generate + rici_distance_rank per mesh; batched / plain), checks that
+both give the same images, ranks and distances bit for bit, checks sampled
+images and small-mesh ranks against the CPU oracle, times the oracle on a
+bounded sample, and adds the icosphere / union-of-12 / clutter-scene figures
+and the serving sweep (Poisson requests against a 1M-image database).
 
 Prints one JSON line: throughput in RICIs described and ranked per second,
-per-kernel roofline figures measured with HIP events on the library's stream,
-and the CPU oracle timed on a bounded sample of the same workload.
+roofline figures for the plan's persistent kernels from HIP events recorded
+inside the graph, and the CPU oracle timed on a bounded sample.
 """
 
 from __future__ import annotations
@@ -29,6 +37,7 @@ PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
 PEAK_INT8_TOPS = 5000.0          # MI355X dense int8 MFMA
 PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes x 2.4 GHz, one op per lane per clock
 OPS_PER_PAIR = 2 * 2 * 64 * 63   # two contractions over 4032 deltas, multiply + add
+R_SUPPORT = 0.3
 
 
 def parse():
@@ -36,28 +45,32 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["batch", "union12", "serving", "clutterbox"], default="batch",
+                    help="batch: batched describe-and-rank of the 256 meshes (default); union12: the plain "
+                         "describe-and-rank step on the union of 12 superquadrics; serving: Poisson request "
+                         "sweep alone; clutterbox: the synthetic clutterbox experiment")
+    ap.add_argument("--batch-meshes", type=int, default=256, help="meshes of the batched workload")
+    ap.add_argument("--plain-reps", type=int, default=2, help="timed runs of the plain per-mesh path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-images", type=int, default=4096, help="oracle generation sample (images)")
-    ap.add_argument("--cpu-needles", type=int, default=128, help="oracle rank sample (needles)")
-    ap.add_argument("--workload", choices=["union12", "serving", "clutterbox"], default="union12",
-                    help="union12: the describe-and-rank step (default); serving: Poisson request sweep; "
-                         "clutterbox: the synthetic clutterbox experiment (rank-0 fractions at 1, 5, 10 objects)")
-    ap.add_argument("--trials", type=int, default=30, help="clutterbox: trials")
-    ap.add_argument("--batch-meshes", type=int, default=64,
-                    help="meshes in the batched-vs-plain comparison (0 to skip)")
-    ap.add_argument("--db-images", type=int, default=1_000_000, help="serving: database size")
-    ap.add_argument("--requests", type=int, default=48, help="serving: requests per arrival rate")
+    ap.add_argument("--cpu-per-mesh", type=int, default=16, help="oracle generation sample: images per mesh")
+    ap.add_argument("--cpu-images", type=int, default=4096, help="union12: oracle generation sample (images)")
+    ap.add_argument("--cpu-needles", type=int, default=128, help="union12: oracle rank sample (needles)")
     ap.add_argument("--no-other-configs", dest="other_configs", action="store_false",
-                    help="skip the icosphere and clutter-scene figures")
+                    help="skip the icosphere, union-of-12 and clutter-scene figures")
+    ap.add_argument("--no-serving", dest="serving", action="store_false",
+                    help="skip the serving sweep in the default run")
+    ap.add_argument("--db-images", type=int, default=1_000_000, help="serving: database size")
+    ap.add_argument("--requests", type=int, default=500, help="serving: requests per arrival rate")
+    ap.add_argument("--trials", type=int, default=30, help="clutterbox: trials")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scales the HBM byte counters)")
     return ap.parse_args()
 
 
-KERNEL_SOURCES = {
-    "k_gen": ["paper_2007_02306_amd/csrc/rici_gen.hip", "paper_2007_02306_amd/csrc/rici_internal.h"],
-    "k_search": ["paper_2007_02306_amd/csrc/rici_search.hip", "paper_2007_02306_amd/csrc/rici_internal.h"],
-}
+GEN_SOURCES = ["paper_2007_02306_amd/csrc/rici_gen.hip", "paper_2007_02306_amd/csrc/rici_internal.h"]
+SEARCH_SOURCES = ["paper_2007_02306_amd/csrc/rici_search.hip", "paper_2007_02306_amd/csrc/rici_internal.h"]
+KERNEL_SOURCES = {"k_gen": GEN_SOURCES, "k_gen_batched": GEN_SOURCES,
+                  "k_search": SEARCH_SOURCES, "k_search_batched": SEARCH_SOURCES}
 
 
 def source_digest(kernel: str) -> str:
@@ -69,10 +82,10 @@ def source_digest(kernel: str) -> str:
     return h.hexdigest()
 
 
-def measured_record(kernel: str):
-    """The committed counter record of `kernel` (see measured_traffic), or None
-    when missing or taken from other sources."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_union12_hbm_traffic.json")
+def measured_record(kernel: str, workload: str = "union12"):
+    """The committed counter record of `kernel` on `workload` (see
+    measured_traffic), or None when missing or taken from other sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -80,29 +93,25 @@ def measured_record(kernel: str):
     return rec if rec.get("source_sha256") == source_digest(kernel) else None
 
 
-def measured_busy(kernel: str):
+def measured_busy(kernel: str, workload: str = "union12"):
     """Counter-derived VALU / MFMA busy fractions of `kernel` (rocprofv3 SQ
     counters on the same workload), or None."""
-    rec = measured_record(kernel)
+    rec = measured_record(kernel, workload)
     if not rec or not rec.get("busy"):
         return None
-    b = rec["busy"]
-    key = "mfma_busy" if kernel == "k_search" else "valu_busy"
-    return {key: b[key], "source": "profiles/union12_hbm_counters.md"}
+    out = dict(rec["busy"])
+    out["source"] = rec.get("summary", f"profiles/{workload}_hbm_counters.md")
+    return out
 
 
-def measured_traffic(kernel: str, launches_per_record: int = 1):
+def measured_traffic(kernel: str, workload: str = "union12", launches_per_record: int = 1):
     """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/<kernel>_union12_hbm_traffic.json: FETCH_SIZE and WRITE_SIZE per
-    dispatch, each scaled by what the counter reads for a plain copy of known
-    size), or None when the kernel's sources changed after the counters were
-    taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_union12_hbm_traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    if rec.get("source_sha256") != source_digest(kernel):
+    (profiles/<kernel>_<workload>_hbm_traffic.json: FETCH_SIZE and WRITE_SIZE
+    per dispatch, each scaled by what the counter reads for a plain copy of
+    known size), or None when the kernel's sources changed after the counters
+    were taken."""
+    rec = measured_record(kernel, workload)
+    if rec is None:
         return None
     return rec["hbm_bytes_per_dispatch"] * launches_per_record
 
@@ -116,67 +125,6 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4, "copies": 3}}), flush=True)
-
-
-def cpu_baseline(scene, n_img, n_needles, gpu_images=None, gpu_rank=None):
-    """The oracle, as it stands, on a bounded sample of the benchmark workload:
-    generation of `n_img` seeded images and ranking of `n_needles` needles over
-    a full-size haystack of oracle images; scaled to RICIs per second.  Also a
-    1-thread figure on a smaller sample, and the parity verdict of the GPU's
-    images (and ranks, against the GPU images as haystack) on the sample."""
-    import numpy as np
-    import oracle
-
-    rng = np.random.default_rng(12345)
-    n = scene.num_haystack
-    sel = np.sort(rng.choice(n, min(n_img, n), replace=False))
-    cores = oracle.threads(0)
-    t0 = time.perf_counter()
-    imgs, flags, work = oracle.rici_rowrange(scene.positions, scene.triangles, scene.op_positions[sel],
-                                             scene.op_normals[sel], scene.support_radius, nthreads=cores)
-    t_gen = (time.perf_counter() - t0) / len(sel)
-    hay = np.resize(imgs, (n, 64, 64))          # full-size haystack of oracle images
-    nsel = np.arange(min(n_needles, len(sel)))
-    t0 = time.perf_counter()
-    oracle.rank(imgs[nsel], hay, nsel.astype(np.uint32), nthreads=cores)
-    t_rank = (time.perf_counter() - t0) / len(nsel)
-    per_img = t_gen + t_rank
-    # one thread, smaller sample
-    s1 = sel[:64]
-    t0 = time.perf_counter()
-    oracle.rici_rowrange(scene.positions, scene.triangles, scene.op_positions[s1], scene.op_normals[s1],
-                         scene.support_radius, nthreads=1)
-    t_gen1 = (time.perf_counter() - t0) / len(s1)
-    t0 = time.perf_counter()
-    oracle.rank(imgs[:4], hay, np.arange(4, dtype=np.uint32), nthreads=1)
-    t_rank1 = (time.perf_counter() - t0) / 4
-    out = {
-        "value": 1.0 / per_img,
-        "unit": "RICIs/s",
-        "cores": cores,
-        "kind": "oracle",
-        "sample": f"generation of {len(sel)} of {n} images + rank of {len(nsel)} needles against {n} "
-                  f"haystack images; {t_gen * 1e3:.2f} ms/image + {t_rank * 1e3:.2f} ms/needle on {cores} threads",
-        "single_thread": {"value": 1.0 / (t_gen1 + t_rank1), "unit": "RICIs/s",
-                          "sample": f"generation of {len(s1)} images + rank of 4 needles on 1 thread"},
-        "host": host_cpu(),
-    }
-    if gpu_images is not None:
-        # parity of the GPU's images on the sample: equal at every pixel the
-        # oracle does not flag; ranks of the sample needles against the GPU's
-        # full haystack, true match = themselves shuffled
-        g = gpu_images[sel]
-        diff = (g != imgs)
-        verdict = {"images": int(len(sel)), "pixels": int(diff.size), "flagged_pixels": int(flags.sum()),
-                   "mismatches_outside_flags": int((diff & ~flags.astype(bool)).sum())}
-        if gpu_rank is not None:
-            ranks_gpu, needles_idx, true_idx = gpu_rank
-            k = min(32, len(needles_idx))
-            ork, _ = oracle.rank(gpu_images[needles_idx[:k]], gpu_images, true_idx[:k], nthreads=cores)
-            verdict["ranks_checked"] = int(k)
-            verdict["rank_mismatches"] = int((ork != ranks_gpu[:k]).sum())
-        out["parity"] = verdict
-    return out, work, sel
 
 
 def host_cpu():
@@ -194,24 +142,418 @@ def host_cpu():
     return {"cpu_model": model, "logical_cpus": os.cpu_count()}
 
 
-def value_distributions(images):
-    """Statistics of a device image set (torch int32 [N,64,64]) that set the
-    search's arithmetic paths: count histogram summary, needle-mask density
-    (fraction of D != 0), per-image max |D| classes (<= 15: two contraction
-    phases; 16..127: three; above: the exact int64 path)."""
+def value_distributions(images, max_images: int = 32768):
+    """Statistics of a device image set (torch int32 [N,64,64], or a list of
+    such sets) that set the search's arithmetic paths: count histogram summary,
+    needle-mask density (fraction of D != 0), per-image max |D| classes
+    (<= 15: two contraction phases; 16..127: three; above: the exact int64
+    path).  Large sets are sampled evenly (at most `max_images` images)."""
     import torch
+    sets = images if isinstance(images, (list, tuple)) else [images]
+    total = sum(int(x.shape[0]) for x in sets)
+    parts = []
+    for x in sets:
+        n_all = int(x.shape[0])
+        take = n_all if total <= max_images else max(1, round(n_all * max_images / total))
+        if take < n_all:
+            idx = torch.linspace(0, n_all - 1, take, device=x.device).round().long()
+            x = x.index_select(0, idx)
+        parts.append(x)
+    images = torch.cat(parts) if len(parts) > 1 else parts[0]
     x = images.to(torch.int64)
     d = x[:, :, 1:] - x[:, :, :-1]
     mx = d.abs().amax(dim=(1, 2))
     n = images.shape[0]
     hist = torch.bincount(images.clamp(max=16).flatten().to(torch.int64), minlength=17).cpu().tolist()
     return {
+        "images_sampled": int(n),
         "count_histogram_0_to_16plus": hist,
         "max_count": int(images.max()),
         "mask_density": float((d != 0).float().mean()),
         "max_abs_delta_share": {"le_15": float((mx <= 15).sum()) / n,
                                 "16_to_127": float(((mx > 15) & (mx <= 127)).sum()) / n,
                                 "gt_127": float((mx > 127).sum()) / n},
+    }
+
+
+def _dev_f32(a):
+    import numpy as np
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to("cuda")
+
+
+def _dev_u32(a):
+    import numpy as np
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to("cuda")
+
+
+def _host_u32(t):
+    import numpy as np
+    return t.cpu().numpy().view(np.uint32)
+
+
+def batch_oracle_sample(scenes, plan, ctx, per_mesh: int, seed: int = 12345):
+    """The oracle on a bounded sample of the batched workload.
+
+    Generation: `per_mesh` seeded oriented points of every mesh (the oracle's
+    per-image cost is O(T) for the mesh's own T), compared with the plan's
+    images outside flagged pixels; the oracle's work counters of the sample
+    give the algorithmic generation work per mesh.  Ranking: 32 needles over a
+    haystack of the median mesh's size made of oracle images; rank parity on
+    the three smallest meshes, whose every image the oracle generates (shuffled
+    true-match maps, so ranks are not trivially 0).  The CPU rate is the
+    measured per-image and per-pair costs scaled to the whole workload."""
+    import numpy as np
+    import torch
+    import oracle
+
+    rng = np.random.default_rng(seed)
+    cores = oracle.threads(0)
+    t_gen_total = 0.0
+    sampled, flagged, mism = 0, 0, 0
+    w_min = np.zeros(len(scenes))
+    w_all = np.zeros(len(scenes))
+    sample_s = 0.0
+    keep = None
+    for k, sc in enumerate(scenes):
+        V, T = sc.positions.shape[0], sc.triangles.shape[0]
+        sel = np.sort(rng.choice(V, min(V, per_mesh), replace=False))
+        t0 = time.perf_counter()
+        im, fl, wk = oracle.rici_rowrange(sc.positions, sc.triangles, sc.op_positions[sel], sc.op_normals[sel],
+                                          sc.support_radius, nthreads=cores)
+        dt = time.perf_counter() - t0
+        sample_s += dt
+        t_gen_total += V * dt / len(sel)
+        g = _host_u32(plan.images[k].index_select(0, torch.from_numpy(sel).to("cuda")))
+        mism += int(((g != im) & ~fl).sum())
+        flagged += int(fl.sum())
+        sampled += len(sel)
+        w = wk.astype(np.float64)
+        # algorithmic work left after exact culling: 39 ops per triangle that
+        # reaches the support cylinder (projection + slab test), 40 per slice
+        # that does, 1 per pixel update; and the same if every triangle were
+        # visited (the paper's O(T) per image)
+        w_min[k] = V * (39.0 * w[:, 3] + 40.0 * w[:, 4] + w[:, 2]).mean()
+        w_all[k] = V * (39.0 * T + 40.0 * w[:, 1] + w[:, 2]).mean()
+        if keep is None or abs(V - np.median([s.positions.shape[0] for s in scenes])) < abs(
+                keep[0] - np.median([s.positions.shape[0] for s in scenes])):
+            keep = (V, im)
+    # rank cost per (needle, haystack image) pair on a median-size haystack
+    Vm, imgs = keep
+    hay = np.resize(imgs, (Vm, 64, 64))
+    nn = 32
+    t0 = time.perf_counter()
+    oracle.rank(np.resize(imgs, (nn, 64, 64)), hay, np.arange(nn, dtype=np.uint32) % Vm, nthreads=cores)
+    t_pair = (time.perf_counter() - t0) / (nn * Vm)
+    sizes = [(s.positions.shape[0], s.triangles.shape[0]) for s in scenes]
+    n_img = sum(v for v, _ in sizes)
+    pairs = float(sum(v * v for v, _ in sizes))
+    t_rank_total = t_pair * pairs
+    # rank parity on the smallest meshes, oracle images against GPU images
+    small = sorted(range(len(scenes)), key=lambda k: sizes[k][0])[:3]
+    rank_checked, rank_mism, dist_mism, img_diff = 0, 0, 0, 0
+    for k in small:
+        sc = scenes[k]
+        V = sc.positions.shape[0]
+        oim, ofl, _ = oracle.rici_rowrange(sc.positions, sc.triangles, sc.op_positions, sc.op_normals,
+                                           sc.support_radius, nthreads=cores)
+        gim = plan.images[k]
+        img_diff += int((_host_u32(gim) != oim).sum())
+        tmap = rng.permutation(V).astype(np.uint32)
+        ork, ods = oracle.rank(oim, oim, tmap, nthreads=cores)
+        grk, gds = ctx.distance_rank(gim, gim, _dev_u32(tmap))
+        ctx.sync()
+        rank_checked += V
+        rank_mism += int((_host_u32(grk) != ork).sum())
+        dist_mism += int((gds.cpu().numpy() != ods).sum())
+    cpu = {
+        "value": n_img / (t_gen_total + t_rank_total),
+        "unit": "RICIs/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"generation of {sampled} images ({per_mesh} per mesh, all {len(scenes)} meshes; "
+                  f"{sample_s:.1f} s) scaled by each mesh's vertex count, plus the rank of {nn} needles against "
+                  f"{Vm} oracle images ({t_pair * 1e9:.1f} ns per pair) scaled to the {pairs:.3g} pairs of the "
+                  f"workload; {cores} threads",
+        "extrapolated_s": {"generation": t_gen_total, "rank": t_rank_total},
+        "host": host_cpu(),
+        "parity": {"images": sampled, "flagged_pixels": flagged, "mismatches_outside_flags": mism,
+                   "rank_meshes": [int(k) for k in small], "ranks_checked": rank_checked,
+                   "rank_mismatches": rank_mism, "true_distance_mismatches": dist_mism,
+                   "small_mesh_pixels_differing_from_oracle": img_diff},
+    }
+    return cpu, w_min, w_all
+
+
+def batch_headline(args, ctx):
+    """The default step: the batched plan over the 256 meshes, with the plain
+    per-mesh path, their equality, the oracle sample and the rooflines."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2007_02306_amd import Context
+    from paper_2007_02306_amd.tune import Tuner
+
+    t0 = time.perf_counter()
+    scenes = synth.config4_batch(meshes=args.batch_meshes)
+    synth_s = time.perf_counter() - t0
+    jobs, sizes = [], []
+    for sc in scenes:
+        jobs.append(dict(positions=_dev_f32(sc.positions), triangles=_dev_u32(sc.triangles),
+                         op_positions=_dev_f32(sc.op_positions), op_normals=_dev_f32(sc.op_normals),
+                         true_index=_dev_u32(sc.true_index)))
+        sizes.append((sc.positions.shape[0], sc.triangles.shape[0]))
+    n_img = sum(v for v, _ in sizes)
+    n_tri = sum(t for _, t in sizes)
+    pairs = sum(v * v for v, _ in sizes)
+    gen_pairs = sum(v * t for v, t in sizes)
+    print(f"# batch: {len(scenes)} meshes, {n_img} images, {n_tri} triangles ({synth_s:.1f} s)", file=sys.stderr,
+          flush=True)
+
+    tuner = Tuner(ctx, cache_path=None)
+    t0 = time.perf_counter()
+    knobs = tuner.tune_batch(jobs, R_SUPPORT)
+    tune_s = time.perf_counter() - t0
+    plan = tuner.batch(jobs, R_SUPPORT)
+    plain_ctx = Context(0)
+
+    # plain per-mesh path (default knobs), writing into the plan's buffers
+    def plain():
+        for k, j in enumerate(jobs):
+            img = plan.images[k]
+            plain_ctx.generate(j["positions"], j["triangles"], j["op_positions"], j["op_normals"], R_SUPPORT,
+                               out=img)
+            plain_ctx.distance_rank(img, img, j["true_index"], out_rank=plan.rank[k],
+                                    out_true_distance=plan.true_distance[k])
+
+    plain()
+    torch.cuda.synchronize()
+    plain_times = []
+    for _ in range(args.plain_reps):
+        t0 = time.perf_counter()
+        plain()
+        torch.cuda.synchronize()
+        plain_times.append(time.perf_counter() - t0)
+    print(f"# batch: plain {np.mean(plain_times):.3f} s", file=sys.stderr, flush=True)
+
+    # the timed region: graph replays of the plan
+    for _ in range(args.warmup):
+        plan.run()
+    ctx.sync()
+    torch.cuda.synchronize()
+    gen_ms, search_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run()
+        gen_ms.append(plan.kernel_ms("gen"))
+        search_ms.append(plan.kernel_ms("search"))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.sync()
+    ms_step = elapsed * 1e3 / args.steps
+    print(f"# batch: {ms_step:.1f} ms per step", file=sys.stderr, flush=True)
+
+    # batched == plain, every image, rank and true distance (plain into spare buffers)
+    vmax = max(v for v, _ in sizes)
+    tmp_img = torch.empty((vmax, 64, 64), dtype=torch.int32, device="cuda")
+    tmp_rank = torch.empty(vmax, dtype=torch.int32, device="cuda")
+    tmp_dist = torch.empty(vmax, dtype=torch.int64, device="cuda")
+    bad_img = bad_rank = bad_dist = 0
+    for k, j in enumerate(jobs):
+        v = sizes[k][0]
+        img, rk, ds = tmp_img[:v], tmp_rank[:v], tmp_dist[:v]
+        plain_ctx.generate(j["positions"], j["triangles"], j["op_positions"], j["op_normals"], R_SUPPORT, out=img)
+        plain_ctx.distance_rank(img, img, j["true_index"], out_rank=rk, out_true_distance=ds)
+        bad_img += int((img != plan.images[k]).sum())
+        bad_rank += int((rk != plan.rank[k]).sum())
+        bad_dist += int((ds != plan.true_distance[k]).sum())
+    plain_ctx.sync()
+    del tmp_img, tmp_rank, tmp_dist
+    equality = {"images_compared": n_img, "pixels_differing": bad_img, "ranks_differing": bad_rank,
+                "true_distances_differing": bad_dist}
+
+    dist = value_distributions(plan.images)
+    cpu, w_min, w_all = (None, None, None)
+    if not args.no_cpu_baseline:
+        cpu, w_min, w_all = batch_oracle_sample(scenes, plan, ctx, args.cpu_per_mesh)
+
+    g_ms, s_ms = float(np.mean(gen_ms)), float(np.mean(search_ms))
+    search_ops = float(pairs) * OPS_PER_PAIR
+    s_ach = search_ops / (s_ms * 1e-3) / 1e12
+    roof_search = {"bound": "mfma", "achieved": s_ach, "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
+                   "frac": s_ach / PEAK_INT8_TOPS, "traffic": measured_traffic("k_search_batched", "batch"),
+                   "kernel": "k_search_batched", "avg_ms": s_ms, "launches": len(search_ms),
+                   "ops_per_launch": search_ops,
+                   "ops_basis": "16128 int8 ops per (needle, haystack) pair, sum of V_k^2 over the meshes",
+                   "counters": measured_busy("k_search_batched", "batch")}
+    roof_gen = None
+    if w_min is not None:
+        g_ops = float(w_min.sum())
+        g_ach = g_ops / (g_ms * 1e-3) / 1e12
+        roof_gen = {"bound": "alu", "achieved": g_ach, "peak": PEAK_ALU_TOPS, "unit": "TFLOP/s",
+                    "frac": g_ach / PEAK_ALU_TOPS, "traffic": measured_traffic("k_gen_batched", "batch"),
+                    "kernel": "k_gen_batched", "avg_ms": g_ms, "launches": len(gen_ms),
+                    "ops_per_launch": g_ops,
+                    "ops_basis": "oracle work counters on the sample: 39 per triangle and 40 per slice that reach "
+                                 "the support cylinder, 1 per pixel update (the work left after exact culling)",
+                    "rate_if_every_triangle_were_visited": float(w_all.sum()) / (g_ms * 1e-3) / 1e12,
+                    "counters": measured_busy("k_gen_batched", "batch")}
+    dominant_search = s_ms >= g_ms
+    roofline = roof_search if dominant_search or roof_gen is None else roof_gen
+    other = roof_gen if roofline is roof_search else roof_search
+    value = n_img / (ms_step * 1e-3)
+    plain_s = float(np.mean(plain_times))
+    out = {
+        "value": value,
+        "ms_per_step": ms_step,
+        "config": {"workload": f"{len(scenes)} seeded meshes (superquadrics and tori, triangles log-uniform in "
+                               f"[1k, 200k], own frames), {n_img} oriented points over {n_tri} triangles, R=0.3, "
+                               "64x64 u32 RICIs, each mesh's RICIs ranked against its own RICIs, batched plan "
+                               "(one HIP graph of persistent kernels)",
+                   "meshes": len(scenes), "images": n_img, "triangles": n_tri, "distance_pairs": pairs,
+                   "image_triangle_pairs": gen_pairs},
+        "rates": {"rici_per_s": value, "distance_pairs_per_s": pairs / (ms_step * 1e-3), "ranks_per_s": value,
+                  "image_triangle_pairs_per_s": gen_pairs / (ms_step * 1e-3),
+                  "gen_kernel_rici_per_s": n_img / (g_ms * 1e-3),
+                  "search_kernel_distance_pairs_per_s": pairs / (s_ms * 1e-3)},
+        "kernels": {"k_gen_batched_avg_ms": g_ms, "k_search_batched_avg_ms": s_ms,
+                    "rest_of_step_ms": ms_step - g_ms - s_ms},
+        "roofline": roofline,
+        "roofline_other": other,
+        "batched_vs_plain": {"plain_s": plain_s, "batched_s": ms_step * 1e-3, "speedup": plain_s / (ms_step * 1e-3),
+                             "plain_rici_per_s": n_img / plain_s, "plan_scratch_gb": plan.scratch_bytes / 1e9,
+                             "batched_equals_plain": equality,
+                             "autotuned": {"gen_images_per_group": knobs[0], "search_tile_m": knobs[1],
+                                           "gen_sort_triangles": knobs[2], "tune_s": tune_s,
+                                           "candidates_ms": {f"{g}x{m}x{o}": ms
+                                                             for _, (g, m, o), ms in tuner.measurements}},
+                             "plain_knobs": {"gen_images_per_group": plain_ctx.get_tuning("gen_images_per_group"),
+                                             "search_tile_m": plain_ctx.get_tuning("search_tile_m"),
+                                             "gen_sort_triangles": plain_ctx.get_tuning("gen_sort_triangles")}},
+        "value_distributions": dist,
+        "cpu_baseline": cpu,
+    }
+    plan.close()
+    plain_ctx.close()
+    del jobs
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_union12(scene, n_img, n_needles, gpu_images=None):
+    """The oracle, as it stands, on a bounded sample of the union-of-12 step:
+    generation of `n_img` seeded images and ranking of `n_needles` needles over
+    a full-size haystack of oracle images; scaled to RICIs per second; and the
+    parity verdict of the GPU's images on the sample."""
+    import numpy as np
+    import oracle
+
+    rng = np.random.default_rng(12345)
+    n = scene.num_haystack
+    sel = np.sort(rng.choice(n, min(n_img, n), replace=False))
+    cores = oracle.threads(0)
+    t0 = time.perf_counter()
+    imgs, flags, work = oracle.rici_rowrange(scene.positions, scene.triangles, scene.op_positions[sel],
+                                             scene.op_normals[sel], scene.support_radius, nthreads=cores)
+    t_gen = (time.perf_counter() - t0) / len(sel)
+    hay = np.resize(imgs, (n, 64, 64))          # full-size haystack of oracle images
+    nsel = np.arange(min(n_needles, len(sel)))
+    t0 = time.perf_counter()
+    oracle.rank(imgs[nsel], hay, nsel.astype(np.uint32), nthreads=cores)
+    t_rank = (time.perf_counter() - t0) / len(nsel)
+    out = {
+        "value": 1.0 / (t_gen + t_rank),
+        "unit": "RICIs/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"generation of {len(sel)} of {n} images + rank of {len(nsel)} needles against {n} "
+                  f"haystack images; {t_gen * 1e3:.2f} ms/image + {t_rank * 1e3:.2f} ms/needle on {cores} threads",
+        "host": host_cpu(),
+    }
+    if gpu_images is not None:
+        g = gpu_images[sel]
+        diff = (g != imgs)
+        out["parity"] = {"images": int(len(sel)), "pixels": int(diff.size), "flagged_pixels": int(flags.sum()),
+                         "mismatches_outside_flags": int((diff & ~flags.astype(bool)).sum())}
+    return out, work
+
+
+def union12_step(ctx, steps: int, warmup: int, cpu: bool, args=None):
+    """The plain describe-and-rank step on the union of 12 superquadrics
+    (23 352 oriented points over 46 656 triangles, all-vs-all ranks), with HIP
+    events around every library kernel."""
+    import numpy as np
+    import torch
+    import synth
+
+    scene = synth.config2_union12()
+    N, T = scene.num_haystack, scene.triangles.shape[0]
+    pos, tri = _dev_f32(scene.positions), _dev_u32(scene.triangles)
+    opp, opn = _dev_f32(scene.op_positions), _dev_f32(scene.op_normals)
+    tidx = _dev_u32(scene.true_index)
+    images = torch.empty((N, 64, 64), dtype=torch.int32, device="cuda")
+    rank = torch.empty(N, dtype=torch.int32, device="cuda")
+    dist = torch.empty(N, dtype=torch.int64, device="cuda")
+
+    def step():
+        ctx.generate(pos, tri, opp, opn, scene.support_radius, out=images)
+        ctx.distance_rank(images, images, tidx, out_rank=rank, out_true_distance=dist)
+
+    for _ in range(warmup):
+        step()
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.sync()
+    ctx.timing(False)
+    kernels = {}
+    for k in ["gen_prep", "gen", "delta_needle", "delta_haystack", "true_distance", "search", "fallback"]:
+        ms, n = ctx.timing_get(k)
+        kernels[k] = {"avg_ms": ms / n if n else None, "launches": n}
+    ms_step = elapsed * 1e3 / steps
+    search_ms = kernels["search"]["avg_ms"]
+    search_ops = float(N) * N * OPS_PER_PAIR
+    s_ach = search_ops / (search_ms * 1e-3) / 1e12
+    roof_search = {"bound": "mfma", "achieved": s_ach, "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
+                   "frac": s_ach / PEAK_INT8_TOPS, "traffic": measured_traffic("k_search"),
+                   "counters": measured_busy("k_search"), "kernel": "k_search", "ops_per_launch": search_ops}
+    cpu_rec, work = None, None
+    if cpu:
+        cpu_rec, work = cpu_baseline_union12(scene, args.cpu_images, args.cpu_needles,
+                                             gpu_images=_host_u32(images))
+    gen_ms = kernels["gen"]["avg_ms"]
+    roof_gen = None
+    if work is not None:
+        w = np.asarray(work, dtype=np.float64)
+        g_ops = N * (39.0 * w[:, 3] + 40.0 * w[:, 4] + w[:, 2]).mean()
+        g_ach = g_ops / (gen_ms * 1e-3) / 1e12
+        roof_gen = {"bound": "alu", "achieved": g_ach, "peak": PEAK_ALU_TOPS, "unit": "TFLOP/s",
+                    "frac": g_ach / PEAK_ALU_TOPS, "traffic": measured_traffic("k_gen"),
+                    "counters": measured_busy("k_gen"), "kernel": "k_gen", "ops_per_launch": g_ops,
+                    "ops_basis": "oracle work counters on the CPU-baseline sample: 39 per triangle and 40 per "
+                                 "slice that reach the support cylinder, 1 per pixel update",
+                    "rate_if_every_triangle_were_visited":
+                        N * (39.0 * T + 40.0 * w[:, 1] + w[:, 2]).mean() / (gen_ms * 1e-3) / 1e12}
+    value = N / (ms_step * 1e-3)
+    return {
+        "value": value, "ms_per_step": ms_step, "steps": steps,
+        "config": {"workload": "union of 12 seeded superquadrics, 23352 oriented points x 46656 triangles, R=0.3, "
+                               "64x64 u32 RICIs, all-vs-all CRD rank (23352 x 23352), plain entry points",
+                   "images": N, "triangles": T, "distance_pairs": N * N},
+        "rates": {"rici_per_s": value, "distance_pairs_per_s": float(N) * N / (ms_step * 1e-3),
+                  "gen_only_rici_per_s": N / (gen_ms * 1e-3) if gen_ms else None,
+                  "search_only_distance_pairs_per_s": float(N) * N / (search_ms * 1e-3) if search_ms else None},
+        "roofline": roof_search, "roofline_gen": roof_gen, "kernels": kernels,
+        "value_distributions": value_distributions(images),
+        "cpu_baseline": cpu_rec,
     }
 
 
@@ -224,8 +566,7 @@ def per_config(ctx, reps: int = 3):
     import synth
 
     dev = torch.device("cuda:0")
-    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
-    i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(dev)
+    f32, i32 = _dev_f32, _dev_u32
     out = {}
     for name, make in (("icosphere", synth.config1_icosphere), ("clutter", synth.config3_clutter)):
         sc = make()
@@ -290,93 +631,6 @@ def per_config(ctx, reps: int = 3):
     return out
 
 
-def batched_vs_plain(ctx, meshes: int, seed: int = 4, reps: int = 3):
-    """Describe-and-rank of `meshes` seeded meshes (log-uniform 1k-200k
-    triangles, own frame, t(i) = i): one graph-replayed batched plan versus the
-    plain per-mesh calls, on the same device buffers; both timed end to end."""
-    import numpy as np
-    import torch
-    import synth
-
-    rng = np.random.default_rng(seed)
-    dev = torch.device("cuda:0")
-    jobs, sizes = [], []
-    for _ in range(meshes):
-        t = int(round(np.exp(rng.uniform(np.log(1_000), np.log(200_000)))))
-        m, _ = synth.configs.random_object(rng, t)
-        pos = m.positions.astype(np.float32)
-        nrm = synth.vertex_normals(pos, m.triangles)
-        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
-        i = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(dev)
-        jobs.append(dict(positions=f(pos), triangles=i(m.triangles), op_positions=f(pos), op_normals=f(nrm),
-                         true_index=i(np.arange(pos.shape[0], dtype=np.uint32))))
-        sizes.append((pos.shape[0], m.triangles.shape[0]))
-    # batched form: knobs picked by the autotuner on a subset of the meshes
-    # (not timed); plain form: a separate handle with the default knobs
-    from paper_2007_02306_amd import Context
-    from paper_2007_02306_amd.tune import Tuner
-    tuner = Tuner(ctx, cache_path=None)
-    t0 = time.perf_counter()
-    knobs = tuner.tune_batch(jobs, 0.3)
-    tune_s = time.perf_counter() - t0
-    plan = tuner.batch(jobs, 0.3)
-    plain_ctx = Context(0)
-
-    def plain():
-        for k, j in enumerate(jobs):
-            img = plan.images[k]
-            plain_ctx.generate(j["positions"], j["triangles"], j["op_positions"], j["op_normals"], 0.3, out=img)
-            plain_ctx.distance_rank(img, img, j["true_index"], out_rank=plan.rank[k],
-                                    out_true_distance=plan.true_distance[k])
-
-    def timeit(fn):
-        fn()
-        torch.cuda.synchronize()
-        best = None
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            best = dt if best is None else min(best, dt)
-        return best
-
-    def snapshot():
-        """Per-image sums of the counts (int64), ranks and true distances of
-        every mesh, as left in the plan's output buffers by the last run."""
-        torch.cuda.synchronize()
-        out = []
-        for k in range(len(jobs)):
-            im = plan.images[k]
-            out.append((im.reshape(im.shape[0], -1).sum(dim=1, dtype=torch.int64).cpu(),
-                        plan.rank[k].cpu().clone(), plan.true_distance[k].cpu().clone()))
-        return out
-
-    t_plain = timeit(plain)
-    ref = snapshot()
-    t_batch = timeit(plan.run)
-    got = snapshot()
-    ctx.sync()
-    plain_ctx.sync()
-    check = {"per_image_count_sums_equal": all(torch.equal(a[0], b[0]) for a, b in zip(ref, got)),
-             "ranks_equal": all(torch.equal(a[1], b[1]) for a, b in zip(ref, got)),
-             "true_distances_equal": all(torch.equal(a[2], b[2]) for a, b in zip(ref, got))}
-    n_img = sum(v for v, _ in sizes)
-    pairs = sum(v * v for v, _ in sizes)
-    out = {"meshes": meshes, "images": n_img, "triangles": sum(t for _, t in sizes), "distance_pairs": pairs,
-           "plain_s": t_plain, "batched_s": t_batch, "speedup": t_plain / t_batch,
-           "batched_rici_per_s": n_img / t_batch, "plain_rici_per_s": n_img / t_plain,
-           "plan_scratch_gb": plan.scratch_bytes / 1e9,
-           "batched_equals_plain": check,
-           "autotuned": {"gen_images_per_group": knobs[0], "search_tile_m": knobs[1], "tune_s": tune_s,
-                         "candidates_ms": {f"{g}x{m}": ms for _, (g, m), ms in tuner.measurements}},
-           "plain_knobs": {"gen_images_per_group": plain_ctx.get_tuning("gen_images_per_group"),
-                           "search_tile_m": plain_ctx.get_tuning("search_tile_m")}}
-    plan.close()
-    plain_ctx.close()
-    return out
-
-
 def serving(args):
     """Poisson request sweep against a device-resident database of clutter-scene
     RICIs: p50/p99 latency and throughput per arrival rate."""
@@ -386,7 +640,6 @@ def serving(args):
     from paper_2007_02306_amd import Context
     from paper_2007_02306_amd.serve import DescriptorDB, Request, Server, serve_poisson
 
-    dev = torch.device("cuda:0")
     ctx = Context(0)
     rng = np.random.default_rng(5)
     chunks, objects, base = [], [], 0
@@ -395,9 +648,8 @@ def serving(args):
         mesh, canon, offsets, _ = synth.configs.clutter_scene(rng, 4, 1_000, 100_000, log_uniform=True)
         pos = mesh.positions.astype(np.float32)
         nrm = synth.vertex_normals(pos, mesh.triangles)
-        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
-        i = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(dev)
-        chunks.append(ctx.generate(f(pos), i(mesh.triangles), f(pos), f(nrm), 0.3))
+        chunks.append(ctx.generate(_dev_f32(pos), _dev_u32(mesh.triangles), _dev_f32(pos), _dev_f32(nrm),
+                                   R_SUPPORT))
         for o, m in enumerate(canon):
             objects.append((m, base + offsets[o]))
         base += pos.shape[0]
@@ -420,14 +672,16 @@ def serving(args):
             out.append(Request(k, pos, m.triangles, nrm, ids, (off + ids).astype(np.uint32)))
         return out
 
-    # single-request service time (alone, sequential)
+    # single-request service rate (alone, one after another)
     srv = Server(db, max_active=1, slices=16)
-    alone = make_requests(6, 1)
+    alone = make_requests(12, 1)
+    srv.submit(alone[0])
+    srv.drain()
     t0 = time.perf_counter()
-    for r in alone:
+    for r in alone[1:]:
         srv.submit(r)
         srv.drain()
-    mu = len(alone) / (time.perf_counter() - t0)
+    mu = (len(alone) - 1) / (time.perf_counter() - t0)
     srv.close()
     sweep = []
     for mult in (0.25, 0.5, 1.0, 2.0, 4.0):
@@ -439,19 +693,23 @@ def serving(args):
         lat = np.array([r.latency for r in done]) * 1e3
         sweep.append({"rate_x_mu": mult, "rate_hz": mult * mu, "requests": len(done),
                       "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                      "throughput_rps": len(done) / wall, "scan_steps": srv.steps})
+                      "max_ms": float(lat.max()), "throughput_rps": len(done) / wall, "scan_steps": srv.steps})
         print(f"# serving x{mult}: {sweep[-1]}", file=sys.stderr, flush=True)
         srv.close()
     out = {"metric": "serving latency and throughput (describe + rank against a device-resident RICI database)",
-           "value": max(p["throughput_rps"] for p in sweep), "unit": "requests/s", "n_gpus": 1,
-           "higher_is_better": True, "data": "synthetic (seeded clutter scenes; no dataset)",
+           "value": max(p["throughput_rps"] for p in sweep), "unit": "requests/s",
            "config": {"workload": f"database of {images.shape[0]} clutter-scene RICIs, requests of up to 1024 "
                                   "needles from one canonical object of 1k-100k triangles, R=0.3",
-                      "db_images": int(images.shape[0]), "db_tiles": db.tiles, "db_build_s": build_s},
-           "single_request_rate_hz": mu, "sweep": sweep}
-    print(json.dumps(out), flush=True)
+                      "db_images": int(images.shape[0]), "db_tiles": db.tiles, "db_build_s": build_s,
+                      "requests_per_rate": args.requests},
+           "single_request_rate_hz": mu,
+           "continuous_batching_gain": max(p["throughput_rps"] for p in sweep) / mu,
+           "sweep": sweep}
     db.close()
     ctx.close()
+    del images
+    torch.cuda.empty_cache()
+    return out
 
 
 def clutterbox(args):
@@ -485,6 +743,10 @@ def clutterbox(args):
     ctx.close()
 
 
+METRIC = "RICIs generated/sec + needle x haystack distances/sec, batched vs plain, bit-exact"
+DTYPE = "f64 geometry decisions, u32 counts, int8->int32 MFMA distances"
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -492,10 +754,7 @@ def main():
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    import synth
     from paper_2007_02306_amd import Context
 
     assert torch.cuda.is_available(), "bench.py needs the MI355X"
@@ -503,131 +762,38 @@ def main():
         copy_calibration()
         return
     if args.workload == "serving":
-        serving(args)
+        print(json.dumps(serving(args)), flush=True)
         return
     if args.workload == "clutterbox":
         clutterbox(args)
         return
-    dev = torch.device("cuda:0")
-    scene = synth.config2_union12()
-    N, T = scene.num_haystack, scene.triangles.shape[0]
-
-    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
-    i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(dev)
-    pos, tri = f32(scene.positions), i32(scene.triangles)
-    opp, opn = f32(scene.op_positions), f32(scene.op_normals)
-    tidx = i32(scene.true_index)
-    images = torch.empty((N, 64, 64), dtype=torch.int32, device=dev)
-    rank = torch.empty(N, dtype=torch.int32, device=dev)
-    dist = torch.empty(N, dtype=torch.int64, device=dev)
-
+    common = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": DTYPE,
+              "data": "synthetic (seeded superquadrics and tori; no dataset)"}
     ctx = Context(0)
+    if args.workload == "union12":
+        u = union12_step(ctx, args.steps, args.warmup, cpu=not args.no_cpu_baseline, args=args)
+        out = dict(common, value=u.pop("value"), unit="RICIs/s (described and ranked against the full haystack)",
+                   ms_per_step=u.pop("ms_per_step"), config=u.pop("config"), roofline=u.pop("roofline"),
+                   cpu_baseline=u.pop("cpu_baseline"), **u)
+        print(json.dumps(out), flush=True)
+        ctx.close()
+        return
 
-    def step():
-        ctx.generate(pos, tri, opp, opn, scene.support_radius, out=images)
-        ctx.distance_rank(images, images, tidx, out_rank=rank, out_true_distance=dist)
-
-    for _ in range(args.warmup):
-        step()
-    ctx.sync()
-    torch.cuda.synchronize()
-    ctx.timing(True)
-    ctx.timing_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ctx.sync()
-    ctx.timing(False)
-
-    kernels = {}
-    for k in ["gen_prep", "gen", "delta_needle", "delta_haystack", "true_distance", "search", "fallback"]:
-        ms, n = ctx.timing_get(k)
-        kernels[k] = {"avg_ms": ms / n if n else None, "launches": n}
-    ms_step = elapsed * 1e3 / args.steps
-
-    # roofline of the search contraction: exact algorithmic int8 ops per launch
-    search_ms = kernels["search"]["avg_ms"]
-    search_ops = float(N) * N * OPS_PER_PAIR
-    search_achieved = search_ops / (search_ms * 1e-3) / 1e12
-    roof_search = {"bound": "mfma", "achieved": search_achieved, "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
-                   "frac": search_achieved / PEAK_INT8_TOPS, "traffic": measured_traffic("k_search"),
-                   "counters": measured_busy("k_search"), "kernel": "k_search",
-                   "ops_per_launch": search_ops}
-
-    cpu = None
-    work = None
-    if not args.no_cpu_baseline:
-        # ranks of a seeded sample of needles against the GPU images with a
-        # shuffled true-match map (non-trivial ranks) for the parity verdict
-        rs = np.random.default_rng(7)
-        nidx = np.sort(rs.choice(N, 32, replace=False))
-        tmap = rs.permutation(N)[:32].astype(np.uint32)
-        rk, _ = ctx.distance_rank(images[torch.from_numpy(nidx).to(dev)].contiguous(), images,
-                                  i32(tmap))
-        ctx.sync()
-        host_images = images.cpu().numpy().view(np.uint32)
-        cpu, work, _ = cpu_baseline(scene, args.cpu_images, args.cpu_needles, gpu_images=host_images,
-                                    gpu_rank=(rk.cpu().numpy().view(np.uint32), nidx, tmap))
-    dist = value_distributions(images)
-
-    gen_ms = kernels["gen"]["avg_ms"]
-    roof_gen = None
-    if work is not None:
-        # algorithmic ALU ops per image: 39 per triangle (projection of three
-        # vertices + slab test), 40 per row slice, 1 per pixel update; slices and
-        # updates per image averaged over the oracle's sample
-        w = np.asarray(work, dtype=np.float64)
-        per_img = 39.0 * T + 40.0 * w[:, 1].mean() + w[:, 2].mean()
-        gen_ops = per_img * N
-        gen_achieved = gen_ops / (gen_ms * 1e-3) / 1e12
-        roof_gen = {"bound": "alu", "achieved": gen_achieved, "peak": PEAK_ALU_TOPS, "unit": "TFLOP/s",
-                    "frac": gen_achieved / PEAK_ALU_TOPS, "traffic": measured_traffic("k_gen"),
-                    "counters": measured_busy("k_gen"), "kernel": "k_gen", "ops_per_launch": gen_ops,
-                    "ops_basis": "oracle work counters on the CPU-baseline sample",
-                    "note": "the algorithmic count credits every (image, triangle) pair, as the method visits "
-                            "all triangles per image; the kernel's exact bounding-sphere culls skip most of them, "
-                            "so frac can exceed 1; counters.valu_busy is the hardware issue utilisation"}
-
-    batched = batched_vs_plain(ctx, args.batch_meshes) if args.batch_meshes > 0 else None
-    others = per_config(ctx) if args.other_configs else None
-
-    dominant = "search" if (search_ms or 0) >= (gen_ms or 0) else "gen"
-    roofline = roof_search if dominant == "search" or roof_gen is None else roof_gen
-    value = N / (ms_step * 1e-3)
-    out = {
-        "metric": "RICIs generated/sec + needle x haystack distances/sec, batched vs plain, bit-exact",
-        "value": value,
-        "unit": "RICIs/s (described and ranked against the full haystack)",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64 geometry decisions, u32 counts, int8->int32 MFMA distances",
-        "data": "synthetic (seeded superquadrics; no dataset)",
-        "config": {"workload": "union of 12 seeded superquadrics, 23352 oriented points x 46656 triangles, "
-                               "R=0.3, 64x64 u32 RICIs, all-vs-all CRD rank (23352 x 23352)",
-                   "images": N, "triangles": T, "distance_pairs": N * N},
-        "rates": {"rici_per_s": value, "distance_pairs_per_s": float(N) * N / (ms_step * 1e-3),
-                  "ranks_per_s": value,
-                  "gen_only_rici_per_s": N / (gen_ms * 1e-3) if gen_ms else None,
-                  "image_triangle_pairs_per_s": float(N) * T / (gen_ms * 1e-3) if gen_ms else None,
-                  "search_only_distance_pairs_per_s": float(N) * N / (search_ms * 1e-3) if search_ms else None},
-        "value_distributions": dist,
-        "roofline": roofline,
-        "roofline_other": roof_gen if roofline is roof_search else roof_search,
-        "kernels": kernels,
-        "batched_vs_plain": batched,
-        "other_configs": others,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    b = batch_headline(args, ctx)
+    out = dict(common, value=b.pop("value"), unit="RICIs/s (described and ranked against their mesh's RICIs)",
+               ms_per_step=b.pop("ms_per_step"), config=b.pop("config"), roofline=b.pop("roofline"),
+               cpu_baseline=b.pop("cpu_baseline"), **b)
+    if args.other_configs:
+        others = per_config(ctx)
+        u = union12_step(ctx, 20, 3, cpu=False)
+        u.pop("value_distributions", None)
+        others["union12"] = u
+        out["other_configs"] = others
     ctx.close()
+    if args.serving:
+        out["serving"] = serving(args)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

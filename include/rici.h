@@ -186,6 +186,13 @@ int rici_batch_run(rici_batch b, void* stream);
 void rici_batch_destroy(rici_batch b);
 /* Bytes of device scratch the plan holds. */
 uint64_t rici_batch_scratch_bytes(rici_batch b);
+/* Measurement support: duration in ms of the persistent generation ("gen") or
+ * search ("search") kernel in the plan's most recent replay, from HIP events
+ * recorded inside the graph right around that kernel.  Waits for that replay to
+ * pass the kernel; 0 if the plan has no such work; RICI_ERR_UNSUPPORTED if the
+ * runtime refused event nodes in the graph (the plan runs without them).
+ * Undefined before the first rici_batch_run. */
+int rici_batch_kernel_ms(rici_batch b, const char* kernel, float* ms);
 
 /*
  * Device-resident descriptor database and incremental queries (serving).

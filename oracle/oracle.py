@@ -101,7 +101,8 @@ def threads(nthreads: int = 0) -> int:
 def rici_rowrange(positions, triangles, op_positions, op_normals, support_radius: float,
                   nthreads: int = 0, f64: bool = False):
     """Row-range oracle: returns (images u32 [N,64,64], flags bool [N,64,64],
-    work u64 [N,3] = (triangles visited, slices, pixel updates)).  Inputs are
+    work u64 [N,5] = (triangles visited, slices, pixel updates, triangles and
+    slices that come closer to the axis than R)).  Inputs are
     fp32 (the library's input type) unless `f64`, which passes positions,
     oriented points and the support radius in FP64."""
     dt = np.float64 if f64 else np.float32
@@ -109,7 +110,7 @@ def rici_rowrange(positions, triangles, op_positions, op_normals, support_radius
     n = opp.shape[0]
     images = np.zeros((n, NBINS, NBINS), dtype=np.uint32)
     flags = np.zeros((n, NBINS, NBINS), dtype=np.uint8)
-    work = np.zeros((n, 3), dtype=np.uint64)
+    work = np.zeros((n, 5), dtype=np.uint64)
     fn = load().oracle_rici_rowrange_f64 if f64 else load().oracle_rici_rowrange
     rc = fn(_ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], _ptr(opp), _ptr(opn), n, float(support_radius),
             _ptr(images), _ptr(flags), _ptr(work), int(nthreads))

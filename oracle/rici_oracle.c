@@ -151,7 +151,9 @@ typedef struct {
     double R;
     uint32_t* images;   /* [n][64][64] */
     uint8_t* flags;     /* [n][64][64] or NULL */
-    uint64_t* work;     /* [n][3]: triangles visited, slices, pixel updates */
+    uint64_t* work;     /* [n][5]: triangles visited, slices, pixel updates,
+                         * triangles and slices that reach inside the support
+                         * radius (the work left after exact culling) */
     int64_t first, last;
 } gen_job_t;
 
@@ -343,7 +345,7 @@ static void rici_one_image(const gen_job_t* J, int64_t img)
     const double R = J->R;
     uint32_t* out = J->images + (size_t)img * NBINS * NBINS;
     uint8_t* fl = J->flags ? J->flags + (size_t)img * NBINS * NBINS : NULL;
-    uint64_t slices = 0, updates = 0;
+    uint64_t slices = 0, updates = 0, tris_in = 0, slices_in = 0;
     memset(out, 0, sizeof(uint32_t) * NBINS * NBINS);
     if (fl) memset(fl, 0, NBINS * NBINS);
 
@@ -370,6 +372,7 @@ static void rici_one_image(const gen_job_t* J, int64_t img)
 
         /* Step 2: for each row plane in the triangle's beta extent, the radius
          * ranges of single and double intersections. */
+        int reaches = 0;
         for (int r = 0; r < NBINS; ++r) {
             const double beta = bin_height(R, r);
             uint8_t* fr = fl ? fl + (size_t)r * NBINS : NULL;
@@ -383,6 +386,12 @@ static void rici_one_image(const gen_job_t* J, int64_t img)
             if (slice_row(&T, beta, above, &s)) {
                 /* Step 3 of the triangle loop: increment the bins */
                 ++slices;
+                /* the slice comes closer to the axis than R: it meets the
+                 * support cylinder */
+                if ((s.dbl ? s.cdist : s.lo) < R) {
+                    ++slices_in;
+                    reaches = 1;
+                }
                 updates += slice_counts(&s, R, out + (size_t)r * NBINS);
                 slice_flags(&s, R, fr);
             }
@@ -420,11 +429,14 @@ static void rici_one_image(const gen_job_t* J, int64_t img)
                     if (base[c] != alt[c]) fr[c] = 1;
             }
         }
+        tris_in += reaches;
     }
     if (J->work) {
-        J->work[3 * img + 0] = J->nt;
-        J->work[3 * img + 1] = slices;
-        J->work[3 * img + 2] = updates;
+        J->work[5 * img + 0] = J->nt;
+        J->work[5 * img + 1] = slices;
+        J->work[5 * img + 2] = updates;
+        J->work[5 * img + 3] = tris_in;
+        J->work[5 * img + 4] = slices_in;
     }
 }
 

@@ -17,6 +17,8 @@ import ctypes
 from ._lib import EXPORTS, LIB_PATH, MeshJob, RiciError, check, load  # noqa: F401
 
 NBINS = 64
+NOALLOC_MAX_TRIANGLES = 1 << 20          # RICI_NOALLOC_MAX_TRIANGLES
+NOALLOC_WORKSPACE_BYTES = 67_371_008     # the static generation workspace per GPU
 
 __all__ = ["Context", "Batch", "RiciError", "NBINS", "load", "EXPORTS", "LIB_PATH"]
 
@@ -105,6 +107,25 @@ class Context:
                 raise ValueError("out must have one image per oriented point")
         check(self._lib.rici_generate(self._h, _ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], _ptr(opp),
                                       _ptr(opn), n, float(support_radius), _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def generate_noalloc(self, positions, triangles, op_positions, op_normals, support_radius: float, out,
+                         stream=None):
+        """rici_generate_noalloc: like generate() into a caller tensor `out`, with
+        the library's static per-GPU workspace (at most NOALLOC_MAX_TRIANGLES
+        triangles; calls that overlap on one GPU race)."""
+        torch = _torch()
+        dev = self.device
+        pos = _dev(positions, "positions", torch.float32, (3,), dev)
+        tri = _dev(triangles, "triangles", torch.int32, (3,), dev)
+        opp = _dev(op_positions, "op_positions", torch.float32, (3,), dev)
+        opn = _dev(op_normals, "op_normals", torch.float32, (3,), dev)
+        _dev(out, "out", torch.int32, (NBINS, NBINS), dev)
+        if opp.shape != opn.shape or out.shape[0] != opp.shape[0]:
+            raise ValueError("op_positions, op_normals and out must agree in length")
+        check(self._lib.rici_generate_noalloc(self._h, _ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], _ptr(opp),
+                                              _ptr(opn), opp.shape[0], float(support_radius), _ptr(out),
+                                              _stream_ptr(stream)))
         return out
 
     def distance_rank(self, needles, haystack, true_index, out_rank=None, out_true_distance=None, stream=None):
@@ -222,6 +243,13 @@ class Batch:
 
     def run(self, stream=None):
         check(self._ctx._lib.rici_batch_run(self._h, _stream_ptr(stream)))
+
+    def kernel_ms(self, kernel: str) -> float:
+        """Duration of the persistent "gen" or "search" kernel in the most recent
+        run (HIP events recorded inside the graph; waits for that run)."""
+        ms = ctypes.c_float()
+        check(self._ctx._lib.rici_batch_kernel_ms(self._h, kernel.encode(), ctypes.byref(ms)))
+        return float(ms.value)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -19,6 +19,7 @@ EXPORTS = [
     "rici_generate", "rici_generate_noalloc", "rici_distance_rank", "rici_distance_matrix",
     "rici_timing_enable", "rici_timing_reset", "rici_timing_get",
     "rici_batch_create", "rici_batch_run", "rici_batch_destroy", "rici_batch_scratch_bytes",
+    "rici_batch_kernel_ms",
     "rici_db_create", "rici_db_tiles", "rici_db_scratch_bytes", "rici_db_destroy",
     "rici_query_create", "rici_query_footprint", "rici_query_destroy", "rici_db_scan",
     "rici_set_tuning", "rici_get_tuning",
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH):
         lib.rici_batch_destroy.restype = None
         lib.rici_batch_scratch_bytes.argtypes = [P]
         lib.rici_batch_scratch_bytes.restype = ctypes.c_uint64
+        lib.rici_batch_kernel_ms.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(F32)]
+        lib.rici_batch_kernel_ms.restype = I32
         U64 = ctypes.c_uint64
         lib.rici_db_create.argtypes = [P, P, U32, P, ctypes.POINTER(P)]
         lib.rici_db_create.restype = I32

@@ -619,6 +619,10 @@ struct rici_batch_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int search_variant = 0;
+    // recorded inside the graph around the two persistent kernels:
+    // [0, 1] generation, [2, 3] search
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool has_gen = false, has_search = false, timing_ok = false;
 };
 
 namespace {
@@ -655,6 +659,8 @@ void destroy_plan(rici_batch_ctx* b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->scratch) (void)hipFree(b->scratch);
+    for (hipEvent_t e : b->ev)
+        if (e) (void)hipEventDestroy(e);
     delete b;
 }
 
@@ -817,31 +823,75 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
         return hip_fail(e, "rici_batch_create: kernel attributes");
     }
 
-    // ---- record the launch sequence as a graph
+    for (hipEvent_t& ev : b->ev) {
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            ev = nullptr;
+            destroy_plan(b);
+            return hip_fail(e, "rici_batch_create: hipEventCreate");
+        }
+    }
+    b->has_gen = items > 0;
+    b->has_search = T.tiles > 0;
+
+    // ---- record the launch sequence as a graph: five captured segments
+    // (generation preparation, persistent generation kernel, search
+    // preparation, persistent search kernel, exact fallback) chained as child
+    // graphs, with event records right around the two persistent kernels
     hipStream_t cs = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) {
         destroy_plan(b);
         return hip_fail(e, "hipStreamCreate");
     }
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    hipGraph_t seg[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipError_t le = hipSuccess;
-    if (e == hipSuccess) {
-        le = rici::launch_gen_batched(d_gjobs, (uint32_t)gj.size(), blocks, chunks, items, support_radius, d_counters,
-                                      h->d_err, gen_grid, gen_group, cs);
-        if (le == hipSuccess)
+    for (int k = 0; k < 5 && e == hipSuccess && le == hipSuccess; ++k) {
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) break;
+        if (k < 2)
+            le = rici::launch_gen_batched(d_gjobs, (uint32_t)gj.size(), blocks, chunks, items, support_radius,
+                                          d_counters, h->d_err, gen_grid, gen_group, cs, k + 1);
+        else
             le = rici::launch_search_batched(d_sjobs, (uint32_t)sj.size(), T, d_counters + 1, grid, variant,
-                                                h->early_exit, cs);
-        hipGraph_t graph = nullptr;
-        e = hipStreamEndCapture(cs, &graph);
-        b->graph = graph;
+                                             h->early_exit, cs, k - 1);
+        hipError_t ee = hipStreamEndCapture(cs, &seg[k]);
+        if (e == hipSuccess) e = ee;
     }
     (void)hipStreamDestroy(cs);
     if (e == hipSuccess && le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphCreate(&b->graph, 0);
+    hipGraphNode_t prev = nullptr;
+    bool events_ok = true;
+    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+        size_t nodes = 0;
+        e = hipGraphGetNodes(seg[k], nullptr, &nodes);
+        if (e == hipSuccess && nodes > 0) {
+            hipGraphNode_t node = nullptr;
+            e = hipGraphAddChildGraphNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, seg[k]);
+            if (e == hipSuccess) prev = node;
+        }
+        // events before and after segments 1 (generation kernel) and 3 (search kernel)
+        const int ev = k == 0 ? 0 : k == 1 ? 1 : k == 2 ? 2 : k == 3 ? 3 : -1;
+        if (e == hipSuccess && ev >= 0 && events_ok) {
+            hipGraphNode_t node = nullptr;
+            hipError_t ee = hipGraphAddEventRecordNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                                       b->ev[ev]);
+            if (ee == hipSuccess) {
+                prev = node;
+            } else {
+                (void)hipGetLastError();   // no in-graph timing on this runtime; the plan still runs
+                events_ok = false;
+            }
+        }
+    }
+    for (hipGraph_t g2 : seg)
+        if (g2) (void)hipGraphDestroy(g2);
+    b->timing_ok = events_ok;
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         destroy_plan(b);
-        return hip_fail(e, "rici_batch_create: graph capture");
+        return hip_fail(e, "rici_batch_create: graph construction");
     }
     *out = b;
     return RICI_OK;
@@ -868,6 +918,31 @@ void rici_batch_destroy(rici_batch b)
 }
 
 uint64_t rici_batch_scratch_bytes(rici_batch b) { return b ? (uint64_t)b->scratch_bytes : 0u; }
+
+int rici_batch_kernel_ms(rici_batch b, const char* kernel, float* ms)
+{
+    if (!b || !kernel || !ms) return fail(RICI_ERR_INVALID, "rici_batch_kernel_ms: NULL argument");
+    int k;
+    bool present;
+    if (strcmp(kernel, "gen") == 0) {
+        k = 0;
+        present = b->has_gen;
+    } else if (strcmp(kernel, "search") == 0) {
+        k = 2;
+        present = b->has_search;
+    } else {
+        return fail(RICI_ERR_INVALID, "rici_batch_kernel_ms: unknown kernel '%s' (gen, search)", kernel);
+    }
+    *ms = 0.0f;
+    if (!present) return RICI_OK;
+    if (!b->timing_ok) return fail(RICI_ERR_UNSUPPORTED, "rici_batch_kernel_ms: no event nodes in this plan's graph");
+    DeviceGuard g(b->h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = hipEventSynchronize(b->ev[k + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, b->ev[k], b->ev[k + 1]);
+    if (e != hipSuccess) return hip_fail(e, "rici_batch_kernel_ms");
+    return RICI_OK;
+}
 
 }  // extern "C"
 

@@ -806,22 +806,25 @@ hipError_t gen_batched_grid(int group, int cus, uint32_t* grid)
 
 hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total_blocks, uint64_t total_chunks,
                               uint32_t total_items, float R, uint32_t* counter, uint32_t* err, uint32_t grid,
-                              int group, hipStream_t s)
+                              int group, hipStream_t s, int part)
 {
     if (njobs == 0) return hipSuccess;
-    if (total_blocks > 0) {
-        hipLaunchKernelGGL(k_gen_prep_batched, dim3((uint32_t)total_blocks), dim3(1024), 0, s, jobs, njobs, err);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_gen_clusters_batched, dim3((uint32_t)((total_chunks + 3) / 4)), dim3(256), 0, s, jobs,
-                           njobs, total_chunks);
+    hipError_t e = hipSuccess;
+    if (part == 0 || part == 1) {
+        if (total_blocks > 0) {
+            hipLaunchKernelGGL(k_gen_prep_batched, dim3((uint32_t)total_blocks), dim3(1024), 0, s, jobs, njobs, err);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_gen_clusters_batched, dim3((uint32_t)((total_chunks + 3) / 4)), dim3(256), 0, s,
+                               jobs, njobs, total_chunks);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, counter, 1u, 0u);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, counter, 1u, 0u);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (total_items == 0) return hipSuccess;
+    if (part == 1 || total_items == 0) return hipSuccess;
     if (group == 2)
         hipLaunchKernelGGL(k_gen_batched<2>, dim3(grid), dim3(kWaves * 64), 0, s, jobs, njobs, total_items, R, counter,
                            err);

@@ -52,9 +52,11 @@ uint32_t gen_group_images(int group);
 // workgroups of the persistent generation kernel that fit the device at once
 hipError_t gen_batched_grid(int group, int cus, uint32_t* grid);
 // prep + clusters + persistent generation over `njobs` jobs stored largest first
+// part: 0 everything; 1 the launches before the persistent kernel (triangle
+// preparation, cluster spheres, work counter); 2 the persistent kernel alone
 hipError_t launch_gen_batched(const GenJob* jobs, uint32_t njobs, uint64_t total_blocks, uint64_t total_chunks,
                               uint32_t total_items, float R, uint32_t* counter, uint32_t* err, uint32_t grid,
-                              int group, hipStream_t s);
+                              int group, hipStream_t s, int part = 0);
 
 // -------------------------------------------------------------------- search
 // Column-delta planes in "fragment-major" order: for every group of 16 images
@@ -132,8 +134,11 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
                              const SearchPrep& p, hipStream_t s, const uint32_t* known_maxabs = nullptr);
 // every prep, rank and fallback step of `njobs` jobs (stored largest first),
 // with a persistent search kernel of `grid` workgroups
+// part: 0 everything; 1 the launches before the persistent kernel (delta
+// planes, statistics, true-match distances, work counters); 2 the persistent
+// search kernel alone; 3 the launches after it (exact fallback)
 hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,
-                                 uint32_t grid, int variant, int early_exit, hipStream_t s);
+                                 uint32_t grid, int variant, int early_exit, hipStream_t s, int part = 0);
 size_t haystack_slots(uint32_t nh);   // slots allocated for a haystack of nh images
 hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                                 const uint32_t* true_idx, const int64_t* sumsq, const uint32_t* nmax,

@@ -1042,7 +1042,7 @@ hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t*
 }
 
 hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,
-                                 uint32_t grid, int variant, int early_exit, hipStream_t s)
+                                 uint32_t grid, int variant, int early_exit, hipStream_t s, int part)
 {
     if (njobs == 0) return hipSuccess;
 #define RICI_LAUNCH(...)                                   \
@@ -1051,35 +1051,41 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
         hipError_t e_ = hipGetLastError();                 \
         if (e_ != hipSuccess) return e_;                   \
     } while (0)
-    if (T.needle_groups)
-        RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
-    if (T.hay_slots)
-        RICI_LAUNCH(k_hay_init_batched, dim3((uint32_t)((T.hay_slots + 255) / 256)), dim3(256), 0, s, jobs, njobs,
-                    T.hay_slots);
-    if (T.hay_images)
-        RICI_LAUNCH(k_hay_stats_batched, dim3((uint32_t)((T.hay_images + 3) / 4)), dim3(256), 0, s, jobs, njobs,
-                    T.hay_images);
-    RICI_LAUNCH(k_hay_assign_batched, dim3(njobs), dim3(1024), 0, s, jobs);
-    if (T.hay_groups)
-        RICI_LAUNCH(k_hay_prep_batched, dim3((uint32_t)T.hay_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
-    if (T.needles)
-        RICI_LAUNCH(k_true_distance_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
-                    T.needles);
-    RICI_LAUNCH(k_zero_counters8, dim3(1), dim3(64), 0, s, counter);
-    if (T.tiles && variant == 1 && early_exit)
-        RICI_LAUNCH((k_search_batched<CfgS, true>), dim3(grid), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, jobs,
-                    njobs, (uint32_t)T.tiles, counter);
-    else if (T.tiles && variant == 1)
-        RICI_LAUNCH((k_search_batched<CfgS, false>), dim3(grid), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, jobs,
-                    njobs, (uint32_t)T.tiles, counter);
-    else if (T.tiles && early_exit)
-        RICI_LAUNCH((k_search_batched<Cfg, true>), dim3(grid), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, jobs,
-                    njobs, (uint32_t)T.tiles, counter);
-    else if (T.tiles)
-        RICI_LAUNCH((k_search_batched<Cfg, false>), dim3(grid), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, jobs,
-                    njobs, (uint32_t)T.tiles, counter);
-    RICI_LAUNCH(k_slow_lists_batched, dim3(njobs), dim3(1024), 0, s, jobs);
-    RICI_LAUNCH(k_fallback_batched, dim3(512), dim3(256), 0, s, jobs, njobs);
+    if (part == 0 || part == 1) {
+        if (T.needle_groups)
+            RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
+        if (T.hay_slots)
+            RICI_LAUNCH(k_hay_init_batched, dim3((uint32_t)((T.hay_slots + 255) / 256)), dim3(256), 0, s, jobs, njobs,
+                        T.hay_slots);
+        if (T.hay_images)
+            RICI_LAUNCH(k_hay_stats_batched, dim3((uint32_t)((T.hay_images + 3) / 4)), dim3(256), 0, s, jobs, njobs,
+                        T.hay_images);
+        RICI_LAUNCH(k_hay_assign_batched, dim3(njobs), dim3(1024), 0, s, jobs);
+        if (T.hay_groups)
+            RICI_LAUNCH(k_hay_prep_batched, dim3((uint32_t)T.hay_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
+        if (T.needles)
+            RICI_LAUNCH(k_true_distance_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
+                        T.needles);
+        RICI_LAUNCH(k_zero_counters8, dim3(1), dim3(64), 0, s, counter);
+    }
+    if (part == 0 || part == 2) {
+        if (T.tiles && variant == 1 && early_exit)
+            RICI_LAUNCH((k_search_batched<CfgS, true>), dim3(grid), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, jobs,
+                        njobs, (uint32_t)T.tiles, counter);
+        else if (T.tiles && variant == 1)
+            RICI_LAUNCH((k_search_batched<CfgS, false>), dim3(grid), dim3(CfgS::kThreads), (size_t)CfgS::kLds, s, jobs,
+                        njobs, (uint32_t)T.tiles, counter);
+        else if (T.tiles && early_exit)
+            RICI_LAUNCH((k_search_batched<Cfg, true>), dim3(grid), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, jobs,
+                        njobs, (uint32_t)T.tiles, counter);
+        else if (T.tiles)
+            RICI_LAUNCH((k_search_batched<Cfg, false>), dim3(grid), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, jobs,
+                        njobs, (uint32_t)T.tiles, counter);
+    }
+    if (part == 0 || part == 3) {
+        RICI_LAUNCH(k_slow_lists_batched, dim3(njobs), dim3(1024), 0, s, jobs);
+        RICI_LAUNCH(k_fallback_batched, dim3(512), dim3(256), 0, s, jobs, njobs);
+    }
 #undef RICI_LAUNCH
     return hipSuccess;
 }

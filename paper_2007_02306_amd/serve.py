@@ -5,7 +5,9 @@ A request brings one mesh, the oriented points to describe (its needles) and
 the database index of each needle's true match.  Its life:
 
   queued    waiting for a slot and for its HBM footprint to fit the budget;
-  describe  on the describe stream: RICIs of the needles (rici_generate), then
+  describe  on the describe stream: RICIs of the needles (rici_generate_noalloc:
+            the library's static workspace, so no allocation or device-wide
+            synchronisation in the loop), then
             rici_query_create (needle delta planes, exact true-match distances,
             exact counts of out-of-range images);
   scanning  joins the circular database scan at the next step once its
@@ -27,7 +29,8 @@ import ctypes
 import time
 from dataclasses import dataclass, field
 
-from . import Context, NBINS, _dev, _ptr, check
+from . import NOALLOC_MAX_TRIANGLES, NOALLOC_WORKSPACE_BYTES, Context, NBINS, _dev, _ptr, check
+from . import roctx
 
 
 def _torch():
@@ -118,7 +121,8 @@ class Server:
     """Admission by HBM footprint, continuous batching of the database scan.
 
     budget_bytes: device memory the in-flight requests may hold (their
-    tensors, scratch and query workspaces).  max_active: at most this many
+    tensors and query workspaces), plus the static generation workspace of the
+    describe step, charged once.  max_active: at most this many
     requests scan at once (<= RICI_SCAN_MAX_QUERIES).  slices: the database is
     scanned in this many slices (one slice per step)."""
 
@@ -139,7 +143,11 @@ class Server:
         self.scanning: list[Request] = []
         self.finishing: list[Request] = []
         self.done: list[Request] = []
-        self.used = 0
+        # describe calls all use the GPU's static generation workspace; they are
+        # serialised on the describe stream, so it is charged once
+        self.used = NOALLOC_WORKSPACE_BYTES
+        if self.used >= self.budget:
+            raise ValueError("budget_bytes does not cover the describe workspace")
         self.cursor = 0
         self.steps_inflight: list = []
         self.max_inflight = int(max_inflight_steps)
@@ -153,13 +161,14 @@ class Server:
         v = int(req.positions.shape[0])
         images = q * NBINS * NBINS * 4
         inputs = v * 12 * 2 + t * 12 + q * (12 * 2 + 4 * 3 + 8)
-        soup = t * 80
-        return images + inputs + soup + self.db.query_footprint(q)
+        return images + inputs + self.db.query_footprint(q)
 
     def submit(self, req: Request, now: float | None = None):
         req.arrival = time.perf_counter() if now is None else now
+        if int(req.triangles.shape[0]) > NOALLOC_MAX_TRIANGLES:
+            raise ValueError(f"request {req.rid}: more than {NOALLOC_MAX_TRIANGLES} triangles")
         req._footprint = self.footprint(req)
-        if req._footprint > self.budget:
+        if req._footprint > self.budget - NOALLOC_WORKSPACE_BYTES:
             raise ValueError(f"request {req.rid} needs {req._footprint} bytes, above the whole budget")
         self.queue.append(req)
 
@@ -175,7 +184,7 @@ class Server:
             self.used += req._footprint
             req.admitted = time.perf_counter()
             dev = torch.device("cuda", self.db.ctx.device)
-            with torch.cuda.stream(self.describe_stream):
+            with roctx.range(f"admit+describe r{req.rid}"), torch.cuda.stream(self.describe_stream):
                 t = lambda a, dt: _to_dev(a, dt, dev)
                 pos = t(req.positions, torch.float32)
                 tri = t(req.triangles, torch.int32)
@@ -189,8 +198,8 @@ class Server:
                 rank = torch.empty(q, dtype=torch.int32, device=dev)
                 dist = torch.empty(q, dtype=torch.int64, device=dev)
                 ws = torch.empty(self.db.query_footprint(q), dtype=torch.uint8, device=dev)
-                self.describe_ctx.generate(pos, tri, opp, opn, req.support_radius, out=images,
-                                           stream=self.describe_stream)
+                self.describe_ctx.generate_noalloc(pos, tri, opp, opn, req.support_radius, images,
+                                                   stream=self.describe_stream)
                 h = ctypes.c_void_p()
                 lib = self.db.ctx._lib
                 check(lib.rici_query_create(self.describe_ctx._h, self.db._h, _ptr(images), q, _ptr(ti), _ptr(rank),
@@ -224,8 +233,9 @@ class Server:
         k = self.cursor
         begin, count = self.bounds[k], self.bounds[k + 1] - self.bounds[k]
         arr = (ctypes.c_void_p * len(self.scanning))(*[r._query.value for r in self.scanning])
-        check(self.scan_ctx._lib.rici_db_scan(self.scan_ctx._h, self.db._h, arr, len(self.scanning), begin, count,
-                                              ctypes.c_void_p(self.scan_stream.cuda_stream)))
+        with roctx.range(f"scan slice {k} x{len(self.scanning)}"):
+            check(self.scan_ctx._lib.rici_db_scan(self.scan_ctx._h, self.db._h, arr, len(self.scanning), begin,
+                                                  count, ctypes.c_void_p(self.scan_stream.cuda_stream)))
         ev = torch.cuda.Event()
         ev.record(self.scan_stream)
         self.steps_inflight.append(ev)
@@ -248,6 +258,7 @@ class Server:
         still = []
         for req in self.finishing:
             if req._done.query():
+                roctx.push(f"finish r{req.rid}")
                 req.finished = time.perf_counter()
                 req.rank = req._dev["rank"].cpu().numpy().view("uint32")
                 req.true_distance = req._dev["dist"].cpu().numpy()
@@ -259,6 +270,7 @@ class Server:
                 req._state = "done"
                 self.used -= req._footprint
                 self.done.append(req)
+                roctx.pop()
             else:
                 still.append(req)
         self.finishing = still

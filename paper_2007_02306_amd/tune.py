@@ -188,8 +188,9 @@ class Tuner:
         return f"batch|j{_log2_bucket(len(jobs), 20)}|t{_log2_bucket(tris, 40)}|n{_log2_bucket(pts, 40)}"
 
     def tune_batch(self, jobs, R: float, sample_jobs: int = 16):
-        """(gen_images_per_group, search_tile_m) for a batched plan, timed as
-        whole plan replays on an evenly spaced subset of the jobs (by size)."""
+        """(gen_images_per_group, search_tile_m, gen_sort_triangles) for a
+        batched plan, timed as whole plan replays on an evenly spaced subset of
+        the jobs (by size)."""
         key = self.batch_class(jobs)
         v = self._get(key)
         if v is not None:
@@ -199,26 +200,31 @@ class Tuner:
         if len(order) > sample_jobs:
             order = [order[round(i * (len(order) - 1) / (sample_jobs - 1))] for i in range(sample_jobs)]
         sub = [jobs[k] for k in order]
-        old = (self.ctx.get_tuning("gen_images_per_group"), self.ctx.get_tuning("search_tile_m"))
+        old = (self.ctx.get_tuning("gen_images_per_group"), self.ctx.get_tuning("search_tile_m"),
+               self.ctx.get_tuning("gen_sort_triangles"))
         best, best_ms = None, None
         for g in GEN_CHOICES:
             for m in SEARCH_CHOICES:
-                self.ctx.set_tuning("gen_images_per_group", g)
-                self.ctx.set_tuning("search_tile_m", m)
-                plan = self.ctx.batch(sub, R)
-                ms = self._time("batch", plan.run)
-                plan.close()
-                self.measurements.append((key, (g, m), ms))
-                if best_ms is None or ms < best_ms:
-                    best, best_ms = (g, m), ms
-                torch.cuda.synchronize()
+                for srt in SORT_CHOICES:
+                    self.ctx.set_tuning("gen_images_per_group", g)
+                    self.ctx.set_tuning("search_tile_m", m)
+                    self.ctx.set_tuning("gen_sort_triangles", srt)
+                    plan = self.ctx.batch(sub, R)
+                    ms = self._time("batch", plan.run)
+                    plan.close()
+                    self.measurements.append((key, (g, m, srt), ms))
+                    if best_ms is None or ms < best_ms:
+                        best, best_ms = (g, m, srt), ms
+                    torch.cuda.synchronize()
         self.ctx.set_tuning("gen_images_per_group", old[0])
         self.ctx.set_tuning("search_tile_m", old[1])
+        self.ctx.set_tuning("gen_sort_triangles", old[2])
         self._put(key, list(best))
         return best
 
     def batch(self, jobs, R: float):
-        g, m = self.tune_batch(jobs, R)
+        g, m, srt = self.tune_batch(jobs, R)
         self.ctx.set_tuning("gen_images_per_group", g)
         self.ctx.set_tuning("search_tile_m", m)
+        self.ctx.set_tuning("gen_sort_triangles", srt)
         return self.ctx.batch(jobs, R)

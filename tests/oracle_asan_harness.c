@@ -45,7 +45,7 @@ int main(int argc, char** argv)
     const size_t px = (size_t)n * 64 * 64;
     uint32_t* img = malloc(px * sizeof(uint32_t));
     uint8_t* fl = malloc(px);
-    uint64_t* wk = malloc((size_t)n * 3 * sizeof(uint64_t));
+    uint64_t* wk = malloc((size_t)n * 5 * sizeof(uint64_t));
     uint32_t* img64 = malloc(px * sizeof(uint32_t));
     uint8_t* fl64 = malloc(px);
     uint32_t* brute = malloc(px * sizeof(uint32_t));

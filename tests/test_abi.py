@@ -53,3 +53,16 @@ def test_null_handle_is_rejected():
     assert lib.rici_distance_rank(None, None, 1, None, 1, None, None, None, None) == -1
     assert lib.rici_sync(None, None) == -1
     assert b"NULL handle" in lib.rici_last_error()
+
+
+def test_noalloc_constants_match_the_header():
+    """The binding's limit and the serving budget's workspace charge follow the
+    header's triangle limit: 16 B spheres + 48 B vertex records per triangle and
+    16 B per 64-triangle cluster, each region rounded up to 256 B."""
+    text = open(HEADER).read()
+    m = re.search(r"#define RICI_NOALLOC_MAX_TRIANGLES \(1u << (\d+)\)", text)
+    assert m
+    n = 1 << int(m.group(1))
+    up = lambda x: (x + 255) // 256 * 256
+    assert rici.NOALLOC_MAX_TRIANGLES == n
+    assert rici.NOALLOC_WORKSPACE_BYTES == up(16 * n) + up((n + 63) // 64 * 16) + up(48 * n)

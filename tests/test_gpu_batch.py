@@ -212,3 +212,26 @@ def test_batch_empty_and_bad_jobs(ctx):
     b.close()
     with pytest.raises(RiciError):
         ctx.batch([], -1.0)
+
+
+def test_batch_kernel_times_from_graph_events(ctx):
+    """The event records inside the plan's graph bracket the two persistent
+    kernels: both durations are positive and together below the replay's wall
+    time."""
+    import time
+    import torch
+    meshes = _meshes(9, 6, 2000, 20000)
+    jobs = [dict(positions=dev_f32(p), triangles=dev_u32(t), op_positions=dev_f32(p), op_normals=dev_f32(n),
+                 true_index=dev_u32(ti)) for p, t, n, ti in meshes]
+    b = ctx.batch(jobs, 0.3)
+    b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    g = b.kernel_ms("gen")
+    s = b.kernel_ms("search")
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    say(f"  gen {g:.3f} ms, search {s:.3f} ms, replay {wall:.3f} ms")
+    assert g > 0 and s > 0 and g + s < wall
+    b.close()

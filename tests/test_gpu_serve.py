@@ -13,6 +13,8 @@ import oracle
 import synth
 from gpu_util import dev_u32, host_u32, say
 
+from paper_2007_02306_amd import NOALLOC_WORKSPACE_BYTES  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 R = 0.3
@@ -110,7 +112,7 @@ def test_server_alone_and_in_mix(setup):
     for rid in range(4):
         srv.submit(_request(rid, objects, np.random.default_rng(100 + rid)))
     srv.drain()
-    assert len(srv.done) == 4 and srv.used == 0
+    assert len(srv.done) == 4 and srv.used == NOALLOC_WORKSPACE_BYTES   # only the describe workspace left
     for req in srv.done:
         assert np.array_equal(req.rank, alone[req.rid].rank), f"request {req.rid} differs in the mix"
         assert np.array_equal(req.true_distance, alone[req.rid].true_distance)
@@ -125,7 +127,8 @@ def test_server_admission_by_footprint(setup):
     probe = Server(db, slices=3)
     need = max(probe.footprint(r) for r in reqs)
     probe.close()
-    srv = Server(db, budget_bytes=need + need // 2, max_active=8, slices=3)   # room for one at a time
+    # room for the describe workspace and one request at a time
+    srv = Server(db, budget_bytes=NOALLOC_WORKSPACE_BYTES + need + need // 2, max_active=8, slices=3)
     for r in reqs:
         srv.submit(r)
     peak = 0
@@ -134,8 +137,11 @@ def test_server_admission_by_footprint(setup):
         assert srv.used <= srv.budget
     assert peak == 1 and len(srv.done) == 3
     with pytest.raises(ValueError):
-        big = Server(db, budget_bytes=1024)
-        big.submit(reqs[0])
+        Server(db, budget_bytes=1024)               # not even the describe workspace fits
+    small = Server(db, budget_bytes=NOALLOC_WORKSPACE_BYTES + 1024)
+    with pytest.raises(ValueError):
+        small.submit(reqs[0])
+    small.close()
     srv.close()
 
 

@@ -12,7 +12,8 @@ bands is pinned by an invariant: an FP64 rigid motion of a degenerate scene
 changes the rounding of every quantity but not the exact counts, so the
 counts of every pixel unflagged before and after must agree.
 
-The work counters (slices S and pixel updates U, which set the generation
+The work counters (slices S and pixel updates U, and the triangles and slices
+that come closer to the axis than the support radius, which set the generation
 kernel's algorithmic work) are pinned by closed forms.
 
 Canonical frame throughout: oriented point at the origin with normal +z and
@@ -326,6 +327,57 @@ def test_work_counters_planar_square():
     assert wk[0, 0] == 2 and wk[0, 1] == 2 * len(rows)
     assert wk[0, 2] == U
     assert per_add > U          # counting each +2 twice would be caught
+    # every slice lies within R = 1 of the axis
+    assert wk[0, 3] == 2 and wk[0, 4] == 2 * len(rows)
+
+
+@pytest.mark.parametrize("x0,x1", [(0.8, 1.4), (1.2, 1.5), (0.3, 0.9)])
+def test_work_counters_inside_the_support_radius(x0, x1):
+    """Square in the plane y = 0 with x in (x0, x1) > 0, heights (b0, b1),
+    split on the diagonal from (x0, b0) to (x1, b1).  At height beta the
+    diagonal sits at xd; the upper-left slice runs from x0 to xd (nearest
+    point x0), the lower-right one from xd to x1 (nearest point xd).  A slice
+    counts as inside when its nearest point is closer to the axis than R = 1;
+    a triangle when any of its slices is."""
+    b0, b1 = np.float64(np.float32(-0.31)), np.float64(np.float32(0.23))
+    x0, x1 = np.float64(np.float32(x0)), np.float64(np.float32(x1))
+    v = np.array([[x0, 0, b0], [x1, 0, b0], [x1, 0, b1], [x0, 0, b1]], np.float32)
+    t = np.array([[0, 1, 2], [0, 2, 3]], np.uint32)
+    _, fl, wk = _run(v, tri=t)
+    rows = [r for r in range(NB) if b0 < beta(r) < b1]
+    xd = [x0 + (beta(r) - b0) / (b1 - b0) * (x1 - x0) for r in rows]
+    s_in = sum(int(x0 < 1.0) + int(x < 1.0) for x in xd)
+    t_in = int(x0 < 1.0) + int(any(x < 1.0 for x in xd))
+    assert wk[0, 1] == 2 * len(rows)
+    assert wk[0, 3] == t_in and wk[0, 4] == s_in
+    if x0 >= 1.0:
+        assert wk[0, 2] == 0 and s_in == 0
+    assert 0 < s_in < 2 * len(rows) or x0 >= 1.0 or x1 < 1.0
+
+
+@pytest.mark.parametrize("y,inside", [(0.9, True), (1.05, False), (0.99, True)])
+def test_work_counters_chord_uses_its_foot_point(y, inside):
+    """A square in the plane y = const spanning x in (-0.3, 0.3): every slice
+    straddles the axis's foot point, so its nearest point is at distance y
+    although both ends lie farther out (sqrt(y^2 + 0.09) > 1 for y >= 0.96)."""
+    v = np.array([[-0.3, y, -0.31], [0.3, y, -0.31], [0.3, y, 0.23], [-0.3, y, 0.23]], np.float32)
+    t = np.array([[0, 1, 2], [0, 2, 3]], np.uint32)
+    _, fl, wk = _run(v, tri=t)
+    V = v.astype(np.float64)
+    b0, b1, yy, xa = V[0, 2], V[2, 2], V[0, 1], V[1, 0]
+    rows = [r for r in range(NB) if b0 < beta(r) < b1]
+    # per row: the slice that straddles x = 0 comes as close as y; the other
+    # one ends at the diagonal's crossing xd, its nearest point
+    s_in = 0
+    for r in rows:
+        xd = -xa + (beta(r) - b0) / (b1 - b0) * 2 * xa
+        s_in += int(yy < 1.0) + int(np.hypot(xd, yy) < 1.0)
+    assert wk[0, 1] == 2 * len(rows)
+    assert wk[0, 4] == s_in
+    if inside:
+        assert wk[0, 3] == 2 and s_in >= len(rows)
+    else:
+        assert wk[0, 3] == 0 and s_in == 0 and wk[0, 2] == 0
 
 
 def test_work_counters_bin_radius_boundaries():

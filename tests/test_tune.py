@@ -54,11 +54,13 @@ class FakeCtx:
 
         class Plan:
             def run(self):
-                ctx._last["batch"] = ctx.batch_ms[(knobs["gen_images_per_group"], knobs["search_tile_m"])]
+                ctx._last["batch"] = ctx.batch_ms[(knobs["gen_images_per_group"], knobs["search_tile_m"],
+                                                   knobs["gen_sort_triangles"])]
 
             def close(self):
                 pass
-        self.calls.append(("batch", knobs["gen_images_per_group"], knobs["search_tile_m"], len(jobs)))
+        self.calls.append(("batch", knobs["gen_images_per_group"], knobs["search_tile_m"],
+                           knobs["gen_sort_triangles"], len(jobs)))
         return Plan()
 
 
@@ -119,13 +121,15 @@ def test_search_classes_and_choice(tmp_path):
     assert ctx.calls[-1] == ("rank", 128, 1000)
 
 
-def test_batch_tunes_both_knobs_on_a_subset():
-    ms = {(2, 256): 4.0, (2, 128): 5.0, (4, 256): 3.0, (4, 128): 6.0}
+def test_batch_tunes_all_three_knobs_on_a_subset():
+    ms = {(2, 256, 0): 4.0, (2, 128, 0): 5.0, (4, 256, 0): 3.0, (4, 128, 0): 6.0,
+          (2, 256, 1): 4.1, (2, 128, 1): 5.1, (4, 256, 1): 2.9, (4, 128, 1): 6.1}
     ctx = FakeCtx({}, {}, ms)
     t = Tuner(ctx, None, arch="gfx-test")
     jobs = [dict(triangles=torch.zeros(10 * (k + 1), 3), op_positions=torch.zeros(k + 1, 3)) for k in range(40)]
-    assert t.tune_batch(jobs, 0.3, sample_jobs=8) == (4, 256)
-    sizes = [c[3] for c in ctx.calls if c[0] == "batch"]
-    assert sizes == [8] * 4
+    assert t.tune_batch(jobs, 0.3, sample_jobs=8) == (4, 256, 1)
+    sizes = [c[4] for c in ctx.calls if c[0] == "batch"]
+    assert sizes == [8] * 8
+    assert ctx.knobs["gen_sort_triangles"] == 2             # restored after tuning
     t.batch(jobs, 0.3)
-    assert ctx.calls[-1] == ("batch", 4, 256, 40)
+    assert ctx.calls[-1] == ("batch", 4, 256, 1, 40)
