@@ -360,6 +360,17 @@ __device__ __forceinline__ void tile_coords(uint32_t logical, uint32_t tiles_m, 
     tn = (logical % in_group) / gsz;
 }
 
+// Inclusive prefix sum of x over the lane's row of 16 lanes (DPP row shifts,
+// zero shifted in): lane 15 of each row ends with the row's total.
+__device__ __forceinline__ uint32_t row16_prefix_sum(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);   // row_shr:8
+    return x;
+}
+
 // Row bases of the planes a tile streams in each phase (phase 2 reads the
 // needle plane of phase 0).
 struct StageSrc { const int8_t *a0, *a1, *b0, *b1, *b2; };
@@ -627,35 +638,48 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         colok[nb] = col_l[(wn * C::kNBK + nb) * 16 + cl] != 0;
         col[nb] = (!ranks && colok[nb]) ? A.hperm[slot] : 0u;   // original haystack index (matrix mode)
     }
-    // rank mode: the kWN waves sharing a needle row add their counts in LDS
-    // (zeroed in the prologue), then one global atomic per row of the tile
+    if (ranks) {
+        // Per lane, the counts of its four rows of block mb (each at most
+        // kNBK) packed one per byte; a DPP prefix sum over the lane's row of 16
+        // lanes (the lanes holding those rows' 16 columns) leaves the block
+        // rows' counts in lane 15 of it, at most 16 * kNBK < 256 per byte.
+        // The kWN waves sharing a needle row add them in LDS (zeroed in the
+        // prologue), then one global atomic per row of the tile.
+        static_assert(16 * C::kNBK < 256, "row counts must fit a byte");
 #pragma unroll
-    for (int mb = 0; mb < C::kMB; ++mb) {
-        // the four thresholds of this lane's rows in the block (INT_MIN past the needles)
-        const v4i t4 = ranks ? *reinterpret_cast<const v4i*>(thr_l + (wm * C::kMB + mb) * 16 + 4 * rq)
-                             : v4i{0, 0, 0, 0};
+        for (int mb = 0; mb < C::kMB; ++mb) {
+            // the four thresholds of this lane's rows in the block (INT_MIN past the needles)
+            const v4i t4 = *reinterpret_cast<const v4i*>(thr_l + (wm * C::kMB + mb) * 16 + 4 * rq);
+            uint32_t packed = 0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int lrow = (wm * C::kMB + mb) * 16 + 4 * rq + v;   // row within the tile
-            const uint32_t row = ga0 * 16 + (uint32_t)lrow;
-            const bool rowok = row < A.nn;
-            if (A.matrix) {
-                if (rowok && A.nmax[row] <= kSlow) {
+            for (int v = 0; v < 4; ++v) {
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; ++nb) cnt += (colok[nb] && acc[mb][nb][v] < t4[v]) ? 1u : 0u;
+                packed |= cnt << (8 * v);
+            }
+            packed = row16_prefix_sum(packed);
+            if (cl == 15) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t cnt = (packed >> (8 * v)) & 0xFFu;
+                    const int lrow = (wm * C::kMB + mb) * 16 + 4 * rq + v;   // row within the tile
+                    if (cnt && ga0 * 16 + (uint32_t)lrow < A.nn) atomicAdd(rowcnt + lrow, cnt);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int mb = 0; mb < C::kMB; ++mb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t row = ga0 * 16 + (uint32_t)((wm * C::kMB + mb) * 16 + 4 * rq + v);
+                if (row < A.nn && A.nmax[row] <= kSlow) {
                     const int64_t base = A.sumsq[row];
 #pragma unroll
                     for (int nb = 0; nb < C::kNBK; ++nb)
                         if (colok[nb]) A.matrix[(size_t)row * A.nh + col[nb]] = base + (int64_t)acc[mb][nb][v];
                 }
-            } else {
-                const int32_t t = t4[v];
-                uint32_t cnt = 0;
-#pragma unroll
-                for (int nb = 0; nb < C::kNBK; ++nb) cnt += (colok[nb] && acc[mb][nb][v] < t) ? 1u : 0u;
-                cnt += __shfl_xor(cnt, 1, 64);
-                cnt += __shfl_xor(cnt, 2, 64);
-                cnt += __shfl_xor(cnt, 4, 64);
-                cnt += __shfl_xor(cnt, 8, 64);
-                if (cl == 0 && rowok && cnt) atomicAdd(rowcnt + lrow, cnt);
             }
         }
     }
