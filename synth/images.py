@@ -16,17 +16,24 @@ NB = 64
 
 
 def step_images(rng: np.random.Generator, n: int, density: float = 0.08, delta_scale: int = 2,
-                max_delta: int | None = None) -> np.ndarray:
+                max_delta: int | None = None, chunk: int = 16384) -> np.ndarray:
     """uint32 [n, 64, 64] images with sparse column steps of size up to
-    `delta_scale` (or exactly up to `max_delta` when given)."""
+    `delta_scale` (or exactly up to `max_delta` when given).  Generated in
+    chunks of `chunk` images with narrow integer types, so that haystacks of
+    hundreds of thousands of images take seconds."""
     hi = max_delta if max_delta is not None else delta_scale
-    steps = rng.integers(-hi, hi + 1, size=(n, NB, NB)).astype(np.int64)
-    keep = rng.random((n, NB, NB)) < density
-    steps = np.where(keep, steps, 0)
-    base = rng.integers(0, 4, size=(n, NB, 1)).astype(np.int64)
-    rows = base + np.cumsum(steps, axis=-1)
-    rows -= np.minimum(rows.min(axis=-1, keepdims=True), 0)   # keep counts >= 0
-    return rows.astype(np.uint32)
+    sdt = np.int8 if hi <= 127 else np.int16
+    out = np.empty((n, NB, NB), dtype=np.uint32)
+    for a in range(0, n, chunk):
+        m = min(chunk, n - a)
+        steps = rng.integers(-hi, hi + 1, size=(m, NB, NB), dtype=sdt)
+        steps[rng.random((m, NB, NB), dtype=np.float32) >= density] = 0
+        base = rng.integers(0, 4, size=(m, NB, 1), dtype=np.int32)
+        rows = np.cumsum(steps, axis=-1, dtype=np.int32)
+        rows += base
+        rows -= np.minimum(rows.min(axis=-1, keepdims=True), 0)   # keep counts >= 0
+        out[a:a + m] = rows
+    return out
 
 
 def perturb(rng: np.random.Generator, images: np.ndarray, frac: float = 0.02, amount: int = 2) -> np.ndarray:

@@ -1,0 +1,118 @@
+"""Rank parity at the full sizes of the clutter scene and of the serving
+database (Sec. 4.1 step 6c: rank = number of haystack images strictly closer
+than the true match under the distance of Eq. 6-7).
+
+The haystacks are seeded step images (synth.images) with the shapes of those
+workloads: 345 758 images (the clutter scene's haystack) and 1 048 576 images
+(the serving database; its haystack planes pass 4 GiB, so plane offsets beyond
+32 bits are exercised).  They are built as row rotations of a smaller seeded
+set, which keeps the generation to seconds; rotated rows are different images
+under the distance.  Needles are perturbed copies of haystack images (small
+ranks) and unrelated images with a random true index (ranks in the middle of
+the haystack).  Every rank and true distance must equal the oracle's."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev_u32, host_u32, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2007_02306_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _haystack(seed: int, unique: int, copies: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    base = synth.step_images(rng, unique, density=0.12, delta_scale=2)
+    # a few images with larger steps, so that tiles of every arithmetic kind
+    # (|D| <= 15, 16..127, and the exact path above 127) are present
+    base[7::997] = synth.step_images(rng, len(base[7::997]), density=0.05, max_delta=60)
+    base[11::4999] = synth.step_images(rng, len(base[11::4999]), density=0.02, max_delta=200)
+    out = np.empty((unique * copies, 64, 64), dtype=np.uint32)
+    for k in range(copies):
+        r = (5 * k) % 64                                # rows rotated by r
+        blk = out[k * unique:(k + 1) * unique]
+        blk[:, r:] = base[:, :64 - r]
+        blk[:, :r] = base[:, 64 - r:]
+    return out
+
+
+def _needles(seed: int, hay: np.ndarray, n: int):
+    rng = np.random.default_rng(seed)
+    nh = hay.shape[0]
+    src = np.sort(rng.choice(nh, n, replace=False))
+    src[-2:] = [nh - 2, nh - 1]                     # sources at the very end of the haystack
+    # perturbations from light (rank 0) to heavy (other images come closer)
+    needles = np.stack([synth.perturb(rng, hay[k:k + 1], frac=f, amount=3)[0]
+                        for k, f in zip(src, np.linspace(0.02, 0.9, n))])
+    t = src.astype(np.uint32)
+    half = n // 2
+    needles[:half] = synth.step_images(rng, half, density=0.12, delta_scale=2)
+    t[:half] = rng.integers(0, nh, half).astype(np.uint32)     # an arbitrary "true match"
+    return needles, t
+
+
+@pytest.mark.timeout(900)
+def test_clutter_scene_size_ranks(ctx):
+    hay = _haystack(31, 43_220, 8)[:345_758]
+    say(f"  haystack {hay.shape[0]} images")
+    needles, t = _needles(32, hay, 16)
+    rk, ds = ctx.distance_rank(dev_u32(needles), dev_u32(hay), dev_u32(t))
+    ctx.sync()
+    g_rk, g_ds = host_u32(rk), ds.cpu().numpy()
+    o_rk, o_ds = oracle.rank(needles, hay, t)
+    say(f"  ranks {o_rk.tolist()}")
+    assert np.array_equal(g_ds, o_ds)
+    assert np.array_equal(g_rk, o_rk)
+    assert o_rk[:8].min() > 1000 and o_rk[8:].max() < 1000     # both kinds of rank occur
+
+
+@pytest.mark.timeout(900)
+def test_million_image_database_scan_and_rank(ctx):
+    import ctypes
+    import torch
+    from paper_2007_02306_amd import _ptr, check
+    from paper_2007_02306_amd.serve import DescriptorDB
+    hay = _haystack(41, 65_536, 16)
+    nh = hay.shape[0]
+    say(f"  database {nh} images ({3 * nh * 4096 / 2**30:.1f} GiB of haystack planes)")
+    needles, t = _needles(42, hay, 8)
+    o_rk, o_ds = oracle.rank(needles, hay, t)
+    say(f"  ranks {o_rk.tolist()}")
+    dh = dev_u32(hay)
+    dn, dt = dev_u32(needles), dev_u32(t)
+    # the plain rank entry point
+    rk, ds = ctx.distance_rank(dn, dh, dt)
+    ctx.sync()
+    assert np.array_equal(ds.cpu().numpy(), o_ds)
+    assert np.array_equal(host_u32(rk), o_rk)
+    # the serving path: a query scanned over the database in 7 uneven slices
+    db = DescriptorDB(ctx, dh)
+    lib = ctx._lib
+    q = ctypes.c_void_p()
+    rank = torch.empty(8, dtype=torch.int32, device="cuda")
+    dist = torch.empty(8, dtype=torch.int64, device="cuda")
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    check(lib.rici_query_create(ctx._h, db._h, _ptr(dn), 8, _ptr(dt), _ptr(rank), _ptr(dist), None, 0, s,
+                                ctypes.byref(q)))
+    tiles = db.tiles
+    cuts = sorted(set([0, tiles] + [int(x) for x in np.random.default_rng(5).integers(1, tiles, 6)]))
+    arr = (ctypes.c_void_p * 1)(q.value)
+    start = tiles // 3                                  # start mid-way and wrap around
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        check(lib.rici_db_scan(ctx._h, db._h, arr, 1, (start + a) % tiles, b - a, s))
+    ctx.sync()
+    assert np.array_equal(dist.cpu().numpy(), o_ds)
+    assert np.array_equal(host_u32(rank), o_rk)
+    lib.rici_query_destroy(q)
+    db.close()
