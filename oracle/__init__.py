@@ -17,4 +17,8 @@ from .oracle import (  # noqa: F401
     distance_matrix,
     rank,
     threads,
+    spin_images,
+    pearson,
+    pearson_matrix,
+    pearson_rank,
 )

@@ -65,6 +65,14 @@ def load():
             lib.oracle_distance_matrix.restype = I32
             lib.oracle_threads.argtypes = [I32]
             lib.oracle_threads.restype = I32
+            lib.oracle_spin_images.argtypes = [P, I64, P, P, U32, F32, P, P, P, I32]
+            lib.oracle_spin_images.restype = I32
+            lib.oracle_pearson.argtypes = [P, P]
+            lib.oracle_pearson.restype = F64
+            lib.oracle_pearson_rank.argtypes = [P, U32, P, U32, P, F64, P, P, P, P, I32]
+            lib.oracle_pearson_rank.restype = I32
+            lib.oracle_pearson_matrix.argtypes = [P, U32, P, U32, P, I32]
+            lib.oracle_pearson_matrix.restype = I32
             _lib = lib
     return _lib
 
@@ -175,3 +183,57 @@ def rank(needles, haystack, true_index, nthreads: int = 0):
                             int(nthreads))
     _check(rc, "true_index")
     return rk, ds
+
+
+# ------------------------------------------------------------------ spin images
+
+def spin_images(samples, op_positions, op_normals, support_radius: float, nthreads: int = 0):
+    """Spin Images (Sec. 2.1 with the Sec. 3.1.1 projection; readings S1-S2):
+    returns (images f64 [N,64,64], counts u32 [N,64,64] of non-zero weights
+    per pixel, flags bool [N,64,64] of pixels a sample near the support
+    boundary reaches)."""
+    smp = _c(samples, np.float32).reshape(-1, 3)
+    opp = _c(op_positions, np.float32).reshape(-1, 3)
+    opn = _c(op_normals, np.float32).reshape(-1, 3)
+    n = opp.shape[0]
+    images = np.zeros((n, NBINS, NBINS), dtype=np.float64)
+    counts = np.zeros((n, NBINS, NBINS), dtype=np.uint32)
+    flags = np.zeros((n, NBINS, NBINS), dtype=np.uint8)
+    rc = load().oracle_spin_images(_ptr(smp), smp.shape[0], _ptr(opp), _ptr(opn), n, float(support_radius),
+                                   _ptr(images), _ptr(counts), _ptr(flags), int(nthreads))
+    _check(rc, "sample")
+    return images, counts, flags.astype(bool)
+
+
+def pearson(a, b) -> float:
+    """Pearson correlation of two images (reading S3: 0 for a constant image)."""
+    x = _c(a, np.float32).reshape(NBINS * NBINS)
+    y = _c(b, np.float32).reshape(NBINS * NBINS)
+    return float(load().oracle_pearson(_ptr(x), _ptr(y)))
+
+
+def pearson_matrix(needles, haystack, nthreads: int = 0) -> np.ndarray:
+    nd = _c(needles, np.float32).reshape(-1, NBINS, NBINS)
+    hs = _c(haystack, np.float32).reshape(-1, NBINS, NBINS)
+    out = np.zeros((nd.shape[0], hs.shape[0]), dtype=np.float64)
+    load().oracle_pearson_matrix(_ptr(nd), nd.shape[0], _ptr(hs), hs.shape[0], _ptr(out), int(nthreads))
+    return out
+
+
+def pearson_rank(needles, haystack, true_index, band: float = 0.0, nthreads: int = 0):
+    """Rank of the true match under correlation (reading S4).  Returns (rank,
+    lo, hi, rho_true): lo / hi count h != true with rho above rho_true + band /
+    rho_true - band, the range of ranks allowed to an implementation whose
+    correlations are within band / 2 of these."""
+    nd = _c(needles, np.float32).reshape(-1, NBINS, NBINS)
+    hs = _c(haystack, np.float32).reshape(-1, NBINS, NBINS)
+    ti = _c(true_index, np.uint32).reshape(-1)
+    if ti.shape[0] != nd.shape[0]:
+        raise ValueError("true_index must have one entry per needle")
+    n = nd.shape[0]
+    rk, lo, hi = (np.zeros(n, dtype=np.uint32) for _ in range(3))
+    rt = np.zeros(n, dtype=np.float64)
+    rc = load().oracle_pearson_rank(_ptr(nd), n, _ptr(hs), hs.shape[0], _ptr(ti), float(band), _ptr(rk), _ptr(lo),
+                                    _ptr(hi), _ptr(rt), int(nthreads))
+    _check(rc, "true_index")
+    return rk, lo, hi, rt

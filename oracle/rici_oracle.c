@@ -20,6 +20,9 @@
  *              differences over the needle's non-zero deltas, in int64.
  *   rank     : 0-based rank of the true match, ties taking the best rank
  *              (Sec. 4.1, clutterbox step 6c, and the tie rule of Sec. 4.2).
+ *   spin     : Spin Images from point samples (Sec. 2.1, with the projection
+ *              of Sec. 3.1.1), their Pearson correlation and the rank of the
+ *              true match under it (readings S1 - S4 below).
  *
  * Readings of the paper used here (each one is also listed in the design notes):
  *   R1  Eq. 1, second line: the second rotation normalises the *rotated*
@@ -826,3 +829,208 @@ int oracle_distance_matrix(const uint32_t* needles, uint32_t nn, const uint32_t*
 }
 
 int oracle_threads(int nthreads) { return resolve_threads(nthreads); }
+
+/* ================================================================ spin images
+ *
+ * Spin Image (Sec. 2.1), built from point samples of the scene with the
+ * projection of Sec. 3.1.1 (which the paper states applies to SI construction
+ * as well), and compared by the Pearson correlation coefficient.
+ *
+ * Readings (also in the design notes):
+ *   S1  Support volume: a sample counts when 0 <= alpha < R and
+ *       -R/2 <= beta < R/2 (the square plane of Sec. 2.1, width and height R,
+ *       half-open like the bins).  No support-angle filter (Sec. 4.2: the
+ *       paper's SI results apply none).
+ *   S2  Bilinear interpolation between bin centres: with u = alpha / d - 1/2
+ *       and v = (beta + R/2) / d - 1/2 (d = R/64), a sample adds
+ *       (1 - fu)(1 - fv), fu (1 - fv), (1 - fu) fv, fu fv to the bins
+ *       (floor v, floor u), (floor v, floor u + 1), (floor v + 1, floor u),
+ *       (floor v + 1, floor u + 1), fu and fv being the fractional parts;
+ *       bins outside the 64 x 64 grid receive nothing.  Row = beta, column =
+ *       alpha, as for the RICI.
+ *   S3  The Pearson coefficient of two images over their 4096 pixels; it is
+ *       undefined for a constant image, which is given correlation 0.
+ *   S4  Rank of the true match under correlation (higher is closer):
+ *       #{h : rho(n, h) > rho(n, h_true)}, ties taking the best rank.
+ *
+ * Flags: a sample within EPS (plus the projection's rounding bound) of the
+ * support boundary (alpha = R, beta = +-R/2) might be counted or not by an
+ * implementation with other rounding; the pixels it would reach are flagged.
+ * counts[] receives how many non-zero weights each pixel summed (it sets the
+ * accumulation error bound of an fp32 implementation).
+ */
+
+typedef void (*item_fn)(const void* ctx, int64_t i);
+typedef struct { const void* ctx; item_fn fn; int64_t first, last; } par_range_t;
+
+static void* par_worker(void* arg)
+{
+    par_range_t* P = (par_range_t*)arg;
+    for (int64_t i = P->first; i < P->last; ++i) P->fn(P->ctx, i);
+    return NULL;
+}
+
+/* fn(ctx, i) for i in [0, n) over `nthreads` threads (0: all cores) */
+static void parallel_for(const void* ctx, item_fn fn, int64_t n, int nthreads)
+{
+    int nt = resolve_threads(nthreads);
+    if (nt > 512) nt = 512;
+    if ((int64_t)nt > n) nt = n > 0 ? (int)n : 1;
+    pthread_t th[512];
+    par_range_t rg[512];
+    for (int k = 0; k < nt; ++k) {
+        rg[k].ctx = ctx;
+        rg[k].fn = fn;
+        rg[k].first = n * k / nt;
+        rg[k].last = n * (k + 1) / nt;
+        if (pthread_create(&th[k], NULL, par_worker, &rg[k]) != 0) {
+            par_worker(&rg[k]);
+            th[k] = 0;
+        }
+    }
+    for (int k = 0; k < nt; ++k) if (th[k]) pthread_join(th[k], NULL);
+}
+
+typedef struct {
+    const double* samples; int64_t ns;
+    const double* op_pos; const double* op_nrm;
+    double R;
+    double* images; uint32_t* counts; uint8_t* flags;
+} si_job_t;
+
+static void si_one_image(const void* ctx, int64_t img)
+{
+    const si_job_t* J = (const si_job_t*)ctx;
+    const double R = J->R, d = R / NBINS;
+    double* out = J->images + (size_t)img * NBINS * NBINS;
+    uint32_t* cnt = J->counts ? J->counts + (size_t)img * NBINS * NBINS : NULL;
+    uint8_t* fl = J->flags ? J->flags + (size_t)img * NBINS * NBINS : NULL;
+    memset(out, 0, sizeof(double) * NBINS * NBINS);
+    if (cnt) memset(cnt, 0, sizeof(uint32_t) * NBINS * NBINS);
+    if (fl) memset(fl, 0, NBINS * NBINS);
+    frame_t f;
+    make_frame(J->op_pos + 3 * img, J->op_nrm + 3 * img, &f);
+    if (f.zero_normal && fl) memset(fl, 1, NBINS * NBINS);
+    for (int64_t s = 0; s < J->ns; ++s) {
+        const double* p = J->samples + 3 * s;
+        double x, y, z;
+        project(&f, p[0], p[1], p[2], &x, &y, &z);                 /* Eq. 2 - 4 */
+        const double alpha = sqrt(x * x + y * y), beta = z;        /* Eq. 5 */
+        const double mag = fabs(p[0] - f.sv[0]) + fabs(p[1] - f.sv[1]) + fabs(p[2] - f.sv[2]);
+        const double band = EPS + 64.0 * U64 * (mag + R);
+        const int inside = alpha < R && beta >= -0.5 * R && beta < 0.5 * R;          /* S1 */
+        const int near = fabs(alpha - R) <= band || fabs(beta + 0.5 * R) <= band || fabs(beta - 0.5 * R) <= band;
+        if (!inside && !near) continue;
+        const double u = alpha / d - 0.5, v = (beta + 0.5 * R) / d - 0.5;             /* S2 */
+        const double cu = floor(u), rv = floor(v);
+        const double fu = u - cu, fv = v - rv;
+        const int c0 = (int)cu, r0 = (int)rv;
+        const double w[4] = { (1.0 - fu) * (1.0 - fv), fu * (1.0 - fv), (1.0 - fu) * fv, fu * fv };
+        const int rr[4] = { r0, r0, r0 + 1, r0 + 1 }, cc[4] = { c0, c0 + 1, c0, c0 + 1 };
+        for (int k = 0; k < 4; ++k) {
+            if (rr[k] < 0 || rr[k] >= NBINS || cc[k] < 0 || cc[k] >= NBINS) continue;
+            const size_t px = (size_t)rr[k] * NBINS + (size_t)cc[k];
+            if (inside) {
+                out[px] += w[k];
+                if (cnt && w[k] != 0.0) ++cnt[px];
+            }
+            if (near && fl) fl[px] = 1;
+        }
+    }
+}
+
+/* Spin Images of n oriented points over ns fp32 point samples [ns][3];
+ * images [n][64][64] FP64; counts / flags may be NULL. */
+int oracle_spin_images(const float* samples, int64_t ns, const float* op_pos, const float* op_nrm, uint32_t n,
+                       float R, double* images, uint32_t* counts, uint8_t* flags, int nthreads)
+{
+    double* p = widen(samples, (size_t)ns * 3);
+    double* o = widen(op_pos, (size_t)n * 3);
+    double* m = widen(op_nrm, (size_t)n * 3);
+    int rc = -2;
+    if (p && o && m) {
+        si_job_t J = { p, ns, o, m, (double)R, images, counts, flags };
+        parallel_for(&J, si_one_image, n, nthreads);
+        rc = 0;
+    }
+    free(p); free(o); free(m);
+    return rc;
+}
+
+/* S3: Pearson correlation of two fp32 images, FP64, two passes (means, then
+ * the centred sums). */
+double oracle_pearson(const float* a, const float* b)
+{
+    const int N = NBINS * NBINS;
+    double ma = 0.0, mb = 0.0;
+    for (int i = 0; i < N; ++i) { ma += a[i]; mb += b[i]; }
+    ma /= N;
+    mb /= N;
+    double sab = 0.0, saa = 0.0, sbb = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double x = a[i] - ma, y = b[i] - mb;
+        sab += x * y;
+        saa += x * x;
+        sbb += y * y;
+    }
+    if (saa == 0.0 || sbb == 0.0) return 0.0;
+    return sab / sqrt(saa * sbb);
+}
+
+typedef struct {
+    const float* needles; const float* hay; uint32_t nh;
+    const uint32_t* true_idx; double band;
+    uint32_t* rank; uint32_t* lo; uint32_t* hi; double* rho_true;
+    double* matrix;
+} pearson_job_t;
+
+static void pearson_rank_one(const void* ctx, int64_t i)
+{
+    const pearson_job_t* J = (const pearson_job_t*)ctx;
+    const float* a = J->needles + (size_t)i * NBINS * NBINS;
+    const uint32_t t = J->true_idx[i];
+    const double rt = oracle_pearson(a, J->hay + (size_t)t * NBINS * NBINS);
+    uint32_t r = 0, lo = 0, hi = 0;
+    for (uint32_t h = 0; h < J->nh; ++h) {
+        const double rho = oracle_pearson(a, J->hay + (size_t)h * NBINS * NBINS);
+        r += rho > rt;                                                  /* S4 */
+        if (h != t) {
+            lo += rho > rt + J->band;
+            hi += rho > rt - J->band;
+        }
+    }
+    J->rank[i] = r;
+    if (J->lo) J->lo[i] = lo;
+    if (J->hi) J->hi[i] = hi;
+    if (J->rho_true) J->rho_true[i] = rt;
+}
+
+/* rank[i] = #{h : rho(n_i, h) > rho(n_i, h_true)}; lo / hi (may be NULL): the
+ * same count over h != h_true with the threshold raised / lowered by `band`
+ * (the range of ranks an implementation whose correlations are within band/2
+ * of these may return).  -1 on a bad index. */
+int oracle_pearson_rank(const float* needles, uint32_t nn, const float* hay, uint32_t nh, const uint32_t* true_idx,
+                        double band, uint32_t* rank, uint32_t* lo, uint32_t* hi, double* rho_true, int nthreads)
+{
+    for (uint32_t i = 0; i < nn; ++i) if (true_idx[i] >= nh) return -1;
+    pearson_job_t J = { needles, hay, nh, true_idx, band, rank, lo, hi, rho_true, NULL };
+    parallel_for(&J, pearson_rank_one, nn, nthreads);
+    return 0;
+}
+
+static void pearson_row(const void* ctx, int64_t i)
+{
+    const pearson_job_t* J = (const pearson_job_t*)ctx;
+    for (uint32_t h = 0; h < J->nh; ++h)
+        J->matrix[(size_t)i * J->nh + h] = oracle_pearson(J->needles + (size_t)i * NBINS * NBINS,
+                                                          J->hay + (size_t)h * NBINS * NBINS);
+}
+
+/* out[i][j] = rho(needle_i, haystack_j), FP64 */
+int oracle_pearson_matrix(const float* needles, uint32_t nn, const float* hay, uint32_t nh, double* out,
+                          int nthreads)
+{
+    pearson_job_t J = { needles, hay, nh, NULL, 0.0, NULL, NULL, NULL, NULL, out };
+    parallel_for(&J, pearson_row, nn, nthreads);
+    return 0;
+}

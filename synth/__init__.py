@@ -18,6 +18,7 @@ from .meshes import (  # noqa: F401
     random_rotation,
     transform,
     concat,
+    sample_surface,
 )
 from .images import step_images, perturb  # noqa: F401
 from .configs import (  # noqa: F401

@@ -218,3 +218,28 @@ def concat(meshes: list[Mesh]) -> Mesh:
         tri.append(np.asarray(m.triangles, dtype=np.int64) + off)
         off += m.num_vertices
     return Mesh(np.concatenate(pos, axis=0), np.concatenate(tri, axis=0).astype(np.uint32))
+
+
+def sample_surface(positions: np.ndarray, triangles: np.ndarray, rng: np.random.Generator,
+                   per_triangle: float = 10.0) -> np.ndarray:
+    """Uniform random point samples of a mesh surface, fp32 [S, 3] with
+    S = round(per_triangle * T): each sample picks a triangle with probability
+    proportional to its area, then a uniform point in it (barycentric
+    coordinates 1 - sqrt(r1), sqrt(r1) (1 - r2), sqrt(r1) r2).  The point cloud
+    that Spin Images are built from."""
+    p = np.asarray(positions, dtype=np.float64)
+    t = np.asarray(triangles, dtype=np.int64)
+    if t.shape[0] == 0:
+        return np.zeros((0, 3), dtype=np.float32)
+    a, b, c = p[t[:, 0]], p[t[:, 1]], p[t[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    total = area.sum()
+    n = int(round(per_triangle * t.shape[0]))
+    if n == 0 or total <= 0.0:
+        return np.zeros((0, 3), dtype=np.float32)
+    pick = rng.choice(t.shape[0], size=n, p=area / total)
+    r1 = np.sqrt(rng.random(n))
+    r2 = rng.random(n)
+    w0, w1, w2 = 1.0 - r1, r1 * (1.0 - r2), r1 * r2
+    pts = w0[:, None] * a[pick] + w1[:, None] * b[pick] + w2[:, None] * c[pick]
+    return pts.astype(np.float32)
