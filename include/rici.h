@@ -54,7 +54,10 @@ typedef enum {
 
 /* Device-side error bits reported through rici_sync / rici_device_errors. */
 #define RICI_DEVERR_INDEX 1u       /* a triangle index >= num_vertices */
-#define RICI_DEVERR_NONFINITE 2u   /* a non-finite position, normal    */
+#define RICI_DEVERR_NONFINITE 2u   /* a non-finite position, normal or sample  */
+#define RICI_DEVERR_QUEUE 4u       /* rici_spin_rank: more pairs near a true match's
+                                      correlation than its settle queue holds; ranks
+                                      of that call may be too low                   */
 
 /* Create a handle bound to HIP device `device` (must be gfx950).  */
 int rici_create(rici_handle* out, int device);
@@ -152,6 +155,51 @@ int rici_distance_matrix(rici_handle h,
                          int64_t* out, void* stream);
 
 /*
+ * Spin Images and their Pearson search (Sec. 2.1; the paper's comparison
+ * descriptor, built with the same projection, Sec. 3.1.1).
+ *
+ * rici_spin_generate -- one Spin Image per oriented point from a point cloud.
+ *   samples       [num_samples][3] fp32 point samples of the scene surface.
+ *   op_positions, op_normals  [num_points][3] fp32 oriented points (a zero
+ *                 normal selects +z).
+ *   support_radius  R, finite and > 0.
+ *   out_images    [num_points][64][64] fp32, overwritten (16-byte aligned).
+ * A sample counts when 0 <= alpha < R and -R/2 <= beta < R/2 (Eq. 1-5 in
+ * FP64, no support-angle filter); it adds bilinear weights between bin centres
+ * (alpha = (c + 1/2) R/64, beta = -R/2 + (r + 1/2) R/64) to its four nearest
+ * bins, dropping bins outside the grid.  Pixel sums are fp32 in arbitrary
+ * order: each pixel is within n 2^-24 of its exact sum times that sum, n being
+ * the number of contributions it received.
+ *
+ * rici_spin_rank -- rank of the true match under the Pearson correlation
+ * coefficient rho over the 4096 pixels (0 for a constant image, where it is
+ * undefined); higher is closer:
+ *   rank[i] = #{ j : rho(n_i, h_j) > rho(n_i, h_true[i]) }  (ties: best rank).
+ *   needles [num_needles][64][64], haystack [num_haystack][64][64] fp32 (may be
+ *   the same memory); true_index [num_needles] uint32 (an entry >= num_haystack
+ *   gives rank num_haystack and correlation +inf); out_rank [num_needles];
+ *   out_true_correlation [num_needles] double or NULL.
+ * The contraction runs in fp32 on the matrix cores; pairs within its error
+ * bound of the true match's correlation are settled by the FP64 correlation,
+ * which also gives out_true_correlation, so ranks are those of the FP64
+ * correlations.  If more pairs need settling than the call's queue holds
+ * (at least 2^20 or 1024 per needle), rici_sync reports RICI_DEVERR_QUEUE.
+ *
+ * rici_spin_correlation_matrix -- out[i][j] = rho(n_i, h_j) as fp32 from the
+ * same contraction (row-major [num_needles][num_haystack]); within 2.5e-4 of
+ * the FP64 value.
+ */
+int rici_spin_generate(rici_handle h, const float* samples, uint32_t num_samples,
+                       const float* op_positions, const float* op_normals, uint32_t num_points,
+                       float support_radius, float* out_images, void* stream);
+int rici_spin_rank(rici_handle h, const float* needles, uint32_t num_needles,
+                   const float* haystack, uint32_t num_haystack, const uint32_t* true_index,
+                   uint32_t* out_rank, double* out_true_correlation, void* stream);
+int rici_spin_correlation_matrix(rici_handle h, const float* needles, uint32_t num_needles,
+                                 const float* haystack, uint32_t num_haystack, float* out,
+                                 void* stream);
+
+/*
  * Batched describe-and-rank over many meshes (one plan, replayed as a HIP graph).
  *
  * Each job is one mesh with its own oriented points; its RICIs are written to
@@ -246,7 +294,8 @@ int rici_db_scan(rici_handle h, rici_db db, const rici_query* queries, uint32_t 
  * launches is bracketed by HIP events on its stream; rici_timing_get sums the
  * elapsed times of the completed launches of the named kernel ("gen",
  * "gen_prep", "delta_needle", "delta_haystack", "true_distance", "search",
- * "fallback", "matrix").  Reading synchronises the handle's device.
+ * "fallback", "matrix", "spin_gen", "spin_zprep", "spin_true", "spin_search",
+ * "spin_settle", "spin_matrix").  Reading synchronises the handle's device.
  */
 int rici_timing_enable(rici_handle h, int on);
 int rici_timing_reset(rici_handle h);

@@ -128,6 +128,58 @@ class Context:
                                               _stream_ptr(stream)))
         return out
 
+    # ------------------------------------------------------ spin images
+    def spin_generate(self, samples, op_positions, op_normals, support_radius: float, out=None, stream=None):
+        """Spin Images of the oriented points over the point samples: float32 [N, 64, 64]."""
+        torch = _torch()
+        dev = self.device
+        smp = _dev(samples, "samples", torch.float32, (3,), dev)
+        opp = _dev(op_positions, "op_positions", torch.float32, (3,), dev)
+        opn = _dev(op_normals, "op_normals", torch.float32, (3,), dev)
+        if opp.shape != opn.shape:
+            raise ValueError("op_positions and op_normals differ in shape")
+        n = opp.shape[0]
+        if out is None:
+            out = torch.empty((n, NBINS, NBINS), dtype=torch.float32, device=opp.device)
+        else:
+            _dev(out, "out", torch.float32, (NBINS, NBINS), dev)
+            if out.shape[0] != n:
+                raise ValueError("out must have one image per oriented point")
+        check(self._lib.rici_spin_generate(self._h, _ptr(smp), smp.shape[0], _ptr(opp), _ptr(opn), n,
+                                           float(support_radius), _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def spin_rank(self, needles, haystack, true_index, out_rank=None, out_true_correlation=None, stream=None):
+        """Rank of the true match under Pearson correlation: (rank int32 [Nn]
+        holding uint32, true correlation float64 [Nn])."""
+        torch = _torch()
+        dev = self.device
+        nd = _dev(needles, "needles", torch.float32, (NBINS, NBINS), dev)
+        hs = _dev(haystack, "haystack", torch.float32, (NBINS, NBINS), dev)
+        ti = _dev(true_index, "true_index", torch.int32, None, dev)
+        n = nd.shape[0]
+        if ti.numel() != n:
+            raise ValueError("true_index must have one entry per needle")
+        if out_rank is None:
+            out_rank = torch.empty(n, dtype=torch.int32, device=nd.device)
+        if out_true_correlation is None:
+            out_true_correlation = torch.empty(n, dtype=torch.float64, device=nd.device)
+        check(self._lib.rici_spin_rank(self._h, _ptr(nd), n, _ptr(hs), hs.shape[0], _ptr(ti), _ptr(out_rank),
+                                       _ptr(out_true_correlation), _stream_ptr(stream)))
+        return out_rank, out_true_correlation
+
+    def spin_correlation_matrix(self, needles, haystack, out=None, stream=None):
+        """Pearson correlations float32 [Nn, Nh] from the fp32 contraction."""
+        torch = _torch()
+        dev = self.device
+        nd = _dev(needles, "needles", torch.float32, (NBINS, NBINS), dev)
+        hs = _dev(haystack, "haystack", torch.float32, (NBINS, NBINS), dev)
+        if out is None:
+            out = torch.empty((nd.shape[0], hs.shape[0]), dtype=torch.float32, device=nd.device)
+        check(self._lib.rici_spin_correlation_matrix(self._h, _ptr(nd), nd.shape[0], _ptr(hs), hs.shape[0],
+                                                     _ptr(out), _stream_ptr(stream)))
+        return out
+
     def distance_rank(self, needles, haystack, true_index, out_rank=None, out_true_distance=None, stream=None):
         """(rank int32 [Nn], true-match CRD int64 [Nn]) of each needle's true match."""
         torch = _torch()

@@ -23,6 +23,7 @@ EXPORTS = [
     "rici_db_create", "rici_db_tiles", "rici_db_scratch_bytes", "rici_db_destroy",
     "rici_query_create", "rici_query_footprint", "rici_query_destroy", "rici_db_scan",
     "rici_set_tuning", "rici_get_tuning",
+    "rici_spin_generate", "rici_spin_rank", "rici_spin_correlation_matrix",
 ]
 
 
@@ -78,6 +79,12 @@ def load(path: str = LIB_PATH):
         lib.rici_generate.restype = I32
         lib.rici_generate_noalloc.argtypes = [P, P, U32, P, U32, P, P, U32, F32, P, P]
         lib.rici_generate_noalloc.restype = I32
+        lib.rici_spin_generate.argtypes = [P, P, U32, P, P, U32, F32, P, P]
+        lib.rici_spin_generate.restype = I32
+        lib.rici_spin_rank.argtypes = [P, P, U32, P, U32, P, P, P, P]
+        lib.rici_spin_rank.restype = I32
+        lib.rici_spin_correlation_matrix.argtypes = [P, P, U32, P, U32, P, P]
+        lib.rici_spin_correlation_matrix.restype = I32
         lib.rici_distance_rank.argtypes = [P, P, U32, P, U32, P, P, P, P]
         lib.rici_distance_rank.restype = I32
         lib.rici_distance_matrix.argtypes = [P, P, U32, P, U32, P, P]

@@ -248,9 +248,10 @@ int rici_sync(rici_handle h, void* stream)
     if (word) {
         e = hipMemset(h->d_err, 0, sizeof(uint32_t));
         if (e != hipSuccess) return hip_fail(e, "hipMemset(error word)");
-        return fail(RICI_ERR_DEVICE, "device reported bad input:%s%s",
+        return fail(RICI_ERR_DEVICE, "device reported:%s%s%s",
                     (word & RICI_DEVERR_INDEX) ? " triangle index out of range" : "",
-                    (word & RICI_DEVERR_NONFINITE) ? " non-finite coordinate" : "");
+                    (word & RICI_DEVERR_NONFINITE) ? " non-finite coordinate" : "",
+                    (word & RICI_DEVERR_QUEUE) ? " correlation settle queue full (ranks too low)" : "");
     }
     return RICI_OK;
 }
@@ -512,6 +513,161 @@ int rici_distance_matrix(rici_handle h, const uint32_t* needles, uint32_t num_ne
                                      nullptr, out, S.lists, s);
     });
     if (e != hipSuccess) return hip_fail(e, "fallback launch");
+    return RICI_OK;
+}
+
+// ------------------------------------------------------------ spin images
+
+int rici_spin_generate(rici_handle h, const float* samples, uint32_t num_samples, const float* op_positions,
+                       const float* op_normals, uint32_t num_points, float support_radius, float* out_images,
+                       void* stream)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_spin_generate: NULL handle");
+    if (!(isfinite(support_radius) && support_radius > 0.0f))
+        return fail(RICI_ERR_INVALID, "rici_spin_generate: support_radius must be finite and > 0");
+    if (num_points >= (1u << 31) || num_samples >= (1u << 31))
+        return fail(RICI_ERR_UNSUPPORTED, "rici_spin_generate: more than 2^31 points or samples");
+    if (num_points == 0) return RICI_OK;
+    if (!op_positions || !op_normals || !out_images)
+        return fail(RICI_ERR_INVALID, "rici_spin_generate: NULL oriented-point or output pointer");
+    if (num_samples > 0 && !samples) return fail(RICI_ERR_INVALID, "rici_spin_generate: NULL samples");
+    if (misaligned(out_images)) return fail(RICI_ERR_INVALID, "rici_spin_generate: out_images is not 16-byte aligned");
+    const size_t ob = (size_t)num_points * rici::NPIX * sizeof(float);
+    if (overlaps(out_images, ob, samples, (size_t)num_samples * 12) ||
+        overlaps(out_images, ob, op_positions, (size_t)num_points * 12) ||
+        overlaps(out_images, ob, op_normals, (size_t)num_points * 12))
+        return fail(RICI_ERR_INVALID, "rici_spin_generate: output overlaps an input");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = timed(h, "spin_gen", s, [&] {
+        return rici::launch_spin_gen(samples, num_samples, op_positions, op_normals, num_points, support_radius,
+                                     out_images, h->d_err, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "spin_gen launch");
+    return RICI_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct SpinScratch {
+    rici::SpinPrep np, hp;
+    double* rho_t = nullptr;
+    uint2* queue = nullptr;
+    uint32_t* queue_count = nullptr;
+    uint32_t queue_cap = 0;
+};
+
+int check_spin_args(const char* fn, const float* needles, uint32_t nn, const float* hay, uint32_t nh)
+{
+    if (nn > 0 && !needles) return fail(RICI_ERR_INVALID, "%s: NULL needles", fn);
+    if (nh == 0 && nn > 0) return fail(RICI_ERR_INVALID, "%s: empty haystack", fn);
+    if (nh > 0 && !hay) return fail(RICI_ERR_INVALID, "%s: NULL haystack", fn);
+    if (nn >= (1u << 31) || nh >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "%s: more than 2^31 images", fn);
+    return RICI_OK;
+}
+
+// z planes and statistics of both sets (one set when the needles are the
+// haystack), true correlations and the queue of pairs near the threshold
+int spin_prep(rici_ctx* h, const float* needles, uint32_t nn, const float* hay, uint32_t nh, bool ranks,
+              SpinScratch& S, hipStream_t s)
+{
+    const bool same = needles == hay && nn == nh;
+    const size_t sa = rici::spin_slots(nn), sb = same ? 0 : rici::spin_slots(nh);
+    const uint64_t pairs = (uint64_t)nn * nh;
+    const uint64_t want = std::max<uint64_t>((uint64_t)1 << 20, (uint64_t)1024 * nn);
+    S.queue_cap = ranks ? (uint32_t)std::min<uint64_t>(std::min<uint64_t>(pairs, want), (uint64_t)1 << 30) : 0u;
+    const size_t za = align256(sa * rici::NPIX * sizeof(float)), zb = align256(sb * rici::NPIX * sizeof(float));
+    const size_t st_a = align256(sa * 2 * sizeof(double)), st_b = align256(sb * 2 * sizeof(double));
+    const size_t rt = ranks ? align256((size_t)nn * sizeof(double)) : 0;
+    const size_t qb = align256((size_t)S.queue_cap * sizeof(uint2)), qc = ranks ? 256 : 0;
+    int rc = ensure_ws(h, za + zb + st_a + st_b + rt + qb + qc);
+    if (rc) return rc;
+    char* p = (char*)h->ws;
+    S.np.z = (float*)p; p += za;
+    S.np.mean = (double*)p; S.np.norm = S.np.mean + sa; p += st_a;
+    if (same) {
+        S.hp = S.np;
+    } else {
+        S.hp.z = (float*)p; p += zb;
+        S.hp.mean = (double*)p; S.hp.norm = S.hp.mean + sb; p += st_b;
+    }
+    S.rho_t = ranks ? (double*)p : nullptr; p += rt;
+    S.queue = ranks ? (uint2*)p : nullptr; p += qb;
+    S.queue_count = ranks ? (uint32_t*)p : nullptr;
+    hipError_t e = timed(h, "spin_zprep", s, [&] {
+        hipError_t e1 = rici::launch_spin_zprep(needles, nn, S.np.z, S.np.mean, S.np.norm, s);
+        if (e1 == hipSuccess && !same) e1 = rici::launch_spin_zprep(hay, nh, S.hp.z, S.hp.mean, S.hp.norm, s);
+        return e1;
+    });
+    if (e != hipSuccess) return hip_fail(e, "spin_zprep launch");
+    return RICI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rici_spin_rank(rici_handle h, const float* needles, uint32_t num_needles, const float* haystack,
+                   uint32_t num_haystack, const uint32_t* true_index, uint32_t* out_rank,
+                   double* out_true_correlation, void* stream)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_spin_rank: NULL handle");
+    int rc = check_spin_args("rici_spin_rank", needles, num_needles, haystack, num_haystack);
+    if (rc) return rc;
+    if (num_needles == 0) return RICI_OK;
+    if (!true_index || !out_rank) return fail(RICI_ERR_INVALID, "rici_spin_rank: NULL true_index or out_rank");
+    const size_t nb = num_needles;
+    const size_t img_n = nb * rici::NPIX * 4, img_h = (size_t)num_haystack * rici::NPIX * 4;
+    if (overlaps(out_rank, nb * 4, needles, img_n) || overlaps(out_rank, nb * 4, haystack, img_h) ||
+        overlaps(out_rank, nb * 4, true_index, nb * 4) ||
+        (out_true_correlation && (overlaps(out_true_correlation, nb * 8, needles, img_n) ||
+                                  overlaps(out_true_correlation, nb * 8, haystack, img_h) ||
+                                  overlaps(out_true_correlation, nb * 8, out_rank, nb * 4) ||
+                                  overlaps(out_true_correlation, nb * 8, true_index, nb * 4))))
+        return fail(RICI_ERR_INVALID, "rici_spin_rank: an output overlaps another array");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    SpinScratch S;
+    rc = spin_prep(h, needles, num_needles, haystack, num_haystack, true, S, s);
+    if (rc) return rc;
+    double* rho_t = out_true_correlation ? out_true_correlation : S.rho_t;
+    const char* names[3] = {"spin_true", "spin_search", "spin_settle"};
+    for (int part = 1; part <= 3; ++part) {
+        hipError_t e = timed(h, names[part - 1], s, [&] {
+            return rici::launch_spin_rank(S.np, needles, num_needles, S.hp, haystack, num_haystack, true_index,
+                                          rho_t, out_rank, S.queue, S.queue_count, S.queue_cap, h->d_err, s, part);
+        });
+        if (e != hipSuccess) return hip_fail(e, "spin rank launch");
+    }
+    return RICI_OK;
+}
+
+int rici_spin_correlation_matrix(rici_handle h, const float* needles, uint32_t num_needles, const float* haystack,
+                                 uint32_t num_haystack, float* out, void* stream)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_spin_correlation_matrix: NULL handle");
+    int rc = check_spin_args("rici_spin_correlation_matrix", needles, num_needles, haystack, num_haystack);
+    if (rc) return rc;
+    if (num_needles == 0) return RICI_OK;
+    if (!out) return fail(RICI_ERR_INVALID, "rici_spin_correlation_matrix: NULL out");
+    const size_t ob = (size_t)num_needles * num_haystack * 4;
+    if (overlaps(out, ob, needles, (size_t)num_needles * rici::NPIX * 4) ||
+        overlaps(out, ob, haystack, (size_t)num_haystack * rici::NPIX * 4))
+        return fail(RICI_ERR_INVALID, "rici_spin_correlation_matrix: output overlaps an input");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    SpinScratch S;
+    rc = spin_prep(h, needles, num_needles, haystack, num_haystack, false, S, s);
+    if (rc) return rc;
+    hipError_t e = timed(h, "spin_matrix", s, [&] {
+        return rici::launch_spin_matrix(S.np, num_needles, S.hp, num_haystack, out, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "spin_matrix launch");
     return RICI_OK;
 }
 

@@ -558,15 +558,9 @@ __device__ void gen_images(GenLds<G>& L, const GenJob& J, uint32_t img0, float R
             } else {
                 const double inv_d = (double)(2 * NB) / (double)Rf;
                 f.sx = sp[0]; f.sy = sp[1]; f.sz = sp[2];
-                const double nx = sn[0], ny = sn[1], nz = sn[2];
-                // Eq. 1: [N_ax, N_ay] = Normalize[S_nx, S_ny]; identity if both vanish
-                double nax = 1.0, nay = 0.0, nbx = 0.0, nbz = 1.0;
-                const double la = sqrt(nx * nx + ny * ny);
-                if (la > 0.0) { nax = nx / la; nay = ny / la; }
-                // the second rotation normalises the normal's x after the first one
-                const double rx = nax * nx + nay * ny;
-                const double lb = sqrt(rx * rx + nz * nz);
-                if (lb > 0.0) { nbx = rx / lb; nbz = nz / lb; }
+                // Eq. 1 (identity for a vanishing pair)
+                const Rotation q = frame_rotation(sn[0], sn[1], sn[2]);
+                const double nax = q.nax, nay = q.nay, nbx = q.nbx, nbz = q.nbz;
                 f.nax = nax; f.nay = nay;
                 f.nax_d = nax * inv_d; f.nay_d = nay * inv_d;
                 f.nbx_d = nbx * inv_d; f.nbz_d = nbz * inv_d;

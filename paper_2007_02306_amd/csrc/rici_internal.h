@@ -9,6 +9,25 @@ namespace rici {
 constexpr int NB = 64;              // bins per image side (64 x 64 images)
 constexpr int NPIX = NB * NB;       // pixels per image
 
+// ------------------------------------------------------------ projection
+// Eq. 1 in FP64 for one oriented point: the first rotation (about z) takes
+// the normal's (x, y) onto +x, the second (about y) normalises the normal's x
+// after the first rotation against its z, so that the normal ends on +z.  A
+// pair that normalises from (0, 0) gives the identity rotation.  Shared by the
+// RICI and the Spin Image generators.
+struct Rotation { double nax, nay, nbx, nbz; };
+
+__device__ __forceinline__ Rotation frame_rotation(double nx, double ny, double nz)
+{
+    Rotation q = {1.0, 0.0, 0.0, 1.0};
+    const double la = sqrt(nx * nx + ny * ny);
+    if (la > 0.0) { q.nax = nx / la; q.nay = ny / la; }
+    const double rx = q.nax * nx + q.nay * ny;
+    const double lb = sqrt(rx * rx + nz * nz);
+    if (lb > 0.0) { q.nbx = rx / lb; q.nbz = nz / lb; }
+    return q;
+}
+
 // ---------------------------------------------------------------- generation
 // Scratch per triangle: a conservative bounding sphere (cx, cy, cz, radius) and
 // the three vertices as float4 (w unused).
@@ -150,6 +169,25 @@ hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp
 hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                            const uint32_t* nmax, const uint32_t* hmax, const int64_t* dstar,
                            uint32_t* rank, int64_t* matrix, uint32_t* lists, hipStream_t s);
+
+// ---------------------------------------------------------- spin images
+// Correlation planes of one image set: z = (x - mean) / norm in fp32,
+// fragment-major for v_mfma_f32_16x16x4_f32, spin_slots(n) images; FP64 mean
+// and centred norm per image.
+struct SpinPrep { float* z; double* mean; double* norm; };
+size_t spin_slots(uint32_t n);          // images per plane set (n rounded up to the tile)
+double spin_band();                     // fp32 contraction error bound used by the rank
+hipError_t launch_spin_gen(const float* samples, uint32_t ns, const float* op_pos, const float* op_nrm, uint32_t n,
+                           float R, float* out, uint32_t* err, hipStream_t s);
+hipError_t launch_spin_zprep(const float* images, uint32_t n, float* z, double* mean, double* norm, hipStream_t s);
+// rank[i] = #{h : rho(n_i, h) > rho(n_i, h_true)}; queue: scratch for pairs
+// near the threshold (queue_cap entries; overflow sets bit 4 of *err)
+hipError_t launch_spin_rank(const SpinPrep& np, const float* needles, uint32_t nn, const SpinPrep& hp,
+                            const float* hay, uint32_t nh, const uint32_t* true_idx, double* rho_t, uint32_t* rank,
+                            uint2* queue, uint32_t* queue_count, uint32_t queue_cap, uint32_t* err, hipStream_t s,
+                            int part = 0);   // 0 all; 1 true correlations; 2 contraction; 3 settle the queue
+hipError_t launch_spin_matrix(const SpinPrep& np, uint32_t nn, const SpinPrep& hp, uint32_t nh, float* out,
+                              hipStream_t s);
 
 size_t search_groups(uint32_t n);   // fragment groups allocated for n images
 size_t search_lds_bytes();          // dynamic LDS of the search kernel
