@@ -21,4 +21,6 @@ from .oracle import (  # noqa: F401
     pearson,
     pearson_matrix,
     pearson_rank,
+    clutter_areas,
+    triangle_area_in_volume,
 )

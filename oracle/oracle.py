@@ -73,6 +73,10 @@ def load():
             lib.oracle_pearson_rank.restype = I32
             lib.oracle_pearson_matrix.argtypes = [P, U32, P, U32, P, I32]
             lib.oracle_pearson_matrix.restype = I32
+            lib.oracle_clutter_areas.argtypes = [P, U32, P, U32, U32, U32, P, P, U32, F32, P, P, I32]
+            lib.oracle_clutter_areas.restype = I32
+            lib.oracle_triangle_area_in_volume.argtypes = [P, P, P, F64]
+            lib.oracle_triangle_area_in_volume.restype = F64
             _lib = lib
     return _lib
 
@@ -237,3 +241,29 @@ def pearson_rank(needles, haystack, true_index, band: float = 0.0, nthreads: int
                                     _ptr(hi), _ptr(rt), int(nthreads))
     _check(rc, "true_index")
     return rk, lo, hi, rt
+
+
+# ---------------------------------------------------------------- clutter
+
+def clutter_areas(positions, triangles, object_first: int, object_count: int, op_positions, op_normals,
+                  support_radius: float, nthreads: int = 0):
+    """Surface areas inside each oriented point's support volume (reading C1):
+    (A_all, A_object) float64 [N]; the object is triangles object_first ..
+    object_first + object_count - 1.  Eq. 8: clutter = (A_all - A_object) /
+    A_all."""
+    pos, tri, opp, opn = _mesh_args(positions, triangles, op_positions, op_normals, np.float32)
+    n = opp.shape[0]
+    a_all = np.zeros(n, dtype=np.float64)
+    a_obj = np.zeros(n, dtype=np.float64)
+    rc = load().oracle_clutter_areas(_ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0], int(object_first),
+                                     int(object_count), _ptr(opp), _ptr(opn), n, float(support_radius),
+                                     _ptr(a_all), _ptr(a_obj), int(nthreads))
+    _check(rc, "triangle index")
+    return a_all, a_obj
+
+
+def triangle_area_in_volume(p0, p1, p2, support_radius: float) -> float:
+    """Area of one triangle, given in the frame of the axis (z) and the Spin
+    Vertex (origin), inside the support volume."""
+    a, b, c = (_c(np.asarray(x, np.float64), np.float64).reshape(3) for x in (p0, p1, p2))
+    return float(load().oracle_triangle_area_in_volume(_ptr(a), _ptr(b), _ptr(c), float(support_radius)))

@@ -1034,3 +1034,229 @@ int oracle_pearson_matrix(const float* needles, uint32_t nn, const float* hay, u
     parallel_for(&J, pearson_row, nn, nthreads);
     return 0;
 }
+
+/* =================================================================== clutter
+ *
+ * Clutter around an oriented point (Eq. 8): (A_all - A_object) / A_all, the
+ * areas of the whole scene's surface and of the object's surface inside the
+ * support volume.  Reading C1: the support volume is the descriptor's, the
+ * cylinder alpha <= R, |beta| <= R/2 about the Central Axis (Sec. 2.1); a
+ * point whose volume holds no surface has clutter 0.
+ *
+ * Area of a triangle inside the volume, in the frame of Eq. 1-4 (axis = z,
+ * Spin Vertex at the origin).  The triangle's plane gets orthonormal
+ * coordinates (s, t): e1 horizontal, e2 = m x e1 (m its unit normal).  Since
+ * e1 and the horizontal part of e2 are orthogonal, a point's squared distance
+ * from the axis is s^2 + (a2 + k t)^2 (k = e2 . w2, a2 the plane's own offset
+ * along w2 = z x e1) and its height is h0 m_z + t e2_z.  At each t the volume
+ * therefore cuts the line of constant t in |s| <= w(t) = sqrt(R^2 - (a2 +
+ * k t)^2), inside the slab's t-range; the triangle cuts it in [lo(t), hi(t)],
+ * linear between its vertices.  The area is the integral over t of the
+ * overlap, split where the choice of ends can change: the vertices' t, the
+ * slab's ends, tangency (a2 + k t = +-R) and edge-boundary crossings (roots of
+ * s(t)^2 + (a2 + k t)^2 = R^2 along each edge).  On each piece the integrand
+ * is a difference of linear functions and +-w, integrated exactly; the
+ * integral of w is written so that it does not cancel when k is small.
+ */
+
+static double chord_w(double R, double d)
+{
+    double q = R * R - d * d;
+    return q > 0.0 ? sqrt(q) : 0.0;
+}
+
+/* integral over [t1, t2] of sqrt(R^2 - (a2 + k t)^2), with |a2 + k t| <= R there */
+static double int_w(double R, double a2, double k, double t1, double t2)
+{
+    const double dt = t2 - t1;
+    if (!(dt > 0.0)) return 0.0;
+    double d1 = a2 + k * t1, d2 = a2 + k * t2;
+    d1 = fmax(-R, fmin(R, d1));
+    d2 = fmax(-R, fmin(R, d2));
+    const double w1 = chord_w(R, d1), w2 = chord_w(R, d2);
+    if (k == 0.0) return w1 * dt;
+    /* antiderivative in d: F(d) = (d w + R^2 asin(d / R)) / 2, divided by k.
+     * d2 w2 - d1 w1 = (d2 - d1) [w2 - d1 (d1 + d2) / (w1 + w2)] and
+     * d2 - d1 = k dt, so the first half needs no division by k. */
+    double part1 = 0.0;
+    if (w1 + w2 > 0.0) part1 = 0.5 * dt * (w2 - d1 * (d1 + d2) / (w1 + w2));
+    const double x1 = d1 / R, x2 = d2 / R;
+    const double s1 = chord_w(1.0, x1), s2 = chord_w(1.0, x2);
+    double part2;
+    if (x1 * x2 >= 0.0 && fabs(x2 - x1) < 0.5 && s1 + s2 > 0.0) {
+        /* asin x2 - asin x1 = asin(x2 s1 - x1 s2) and x2 s1 - x1 s2 =
+         * (x2 - x1) g with g = s1 + x1 (x1 + x2) / (s1 + s2); x2 - x1 = k dt / R */
+        const double g = s1 + x1 * (x1 + x2) / (s1 + s2);
+        const double delta = (x2 - x1) * g;
+        const double ratio = fabs(delta) < 1e-8 ? 1.0 + delta * delta / 6.0 : asin(delta) / delta;
+        part2 = 0.5 * R * R * ratio * g * dt / R;
+    } else {
+        part2 = 0.5 * R * R * (asin(x2) - asin(x1)) / k;
+    }
+    return part1 + part2;
+}
+
+typedef struct { double s0, t0, s1, t1; } edge_st_t;
+
+/* s on an edge at t (t within the edge's t-range, edge not horizontal in t) */
+static double edge_s(const edge_st_t* e, double t)
+{
+    return e->s0 + (e->s1 - e->s0) * ((t - e->t0) / (e->t1 - e->t0));
+}
+
+static int cmp_double(const void* a, const void* b)
+{
+    const double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+/* area of triangle (P0, P1, P2), frame coordinates, inside the support volume */
+static double tri_area_in_volume(double R, const double* P0, const double* P1, const double* P2)
+{
+    double u[3], v[3], n[3];
+    sub3(P1, P0, u);
+    sub3(P2, P0, v);
+    cross3(u, v, n);
+    const double nl = sqrt(dot3(n, n));
+    if (!(nl > 0.0)) return 0.0;
+    const double m[3] = { n[0] / nl, n[1] / nl, n[2] / nl };
+    double e1[3];
+    const double hl = sqrt(m[0] * m[0] + m[1] * m[1]);
+    if (hl > 1e-300) { e1[0] = m[1] / hl; e1[1] = -m[0] / hl; e1[2] = 0.0; }
+    else { e1[0] = 1.0; e1[1] = 0.0; e1[2] = 0.0; }
+    double e2[3];
+    cross3(m, e1, e2);
+    const double w2v[3] = { -e1[1], e1[0], 0.0 };          /* z x e1 */
+    const double h0 = dot3(P0, m);
+    const double a2 = h0 * dot3(m, w2v), k = dot3(e2, w2v);
+    const double zc = h0 * m[2], ez = e2[2];
+    /* slab: -R/2 <= zc + t ez <= R/2 */
+    double tlo = -INFINITY, thi = INFINITY;
+    if (ez != 0.0) {
+        double ta = (-0.5 * R - zc) / ez, tb = (0.5 * R - zc) / ez;
+        tlo = fmin(ta, tb);
+        thi = fmax(ta, tb);
+    } else if (fabs(zc) > 0.5 * R) {
+        return 0.0;
+    }
+    /* the distance condition: |a2 + k t| <= R */
+    if (k != 0.0) {
+        double ta = (-R - a2) / k, tb = (R - a2) / k;
+        tlo = fmax(tlo, fmin(ta, tb));
+        thi = fmin(thi, fmax(ta, tb));
+    } else if (fabs(a2) > R) {
+        return 0.0;
+    }
+    const double* P[3] = { P0, P1, P2 };
+    double s[3], t[3];
+    for (int i = 0; i < 3; ++i) { s[i] = dot3(P[i], e1); t[i] = dot3(P[i], e2); }
+    /* vertices sorted by t */
+    int ia = 0, ib = 1, ic = 2, tmp;
+    if (t[ib] < t[ia]) { tmp = ia; ia = ib; ib = tmp; }
+    if (t[ic] < t[ib]) { tmp = ib; ib = ic; ic = tmp; }
+    if (t[ib] < t[ia]) { tmp = ia; ia = ib; ib = tmp; }
+    tlo = fmax(tlo, t[ia]);
+    thi = fmin(thi, t[ic]);
+    if (!(thi > tlo)) return 0.0;
+    const edge_st_t eac = { s[ia], t[ia], s[ic], t[ic] };
+    const edge_st_t eab = { s[ia], t[ia], s[ib], t[ib] };
+    const edge_st_t ebc = { s[ib], t[ib], s[ic], t[ic] };
+    double bp[16];
+    int nb = 0;
+    bp[nb++] = tlo;
+    bp[nb++] = thi;
+    bp[nb++] = t[ib];
+    const edge_st_t* edges[3] = { &eac, &eab, &ebc };
+    for (int j = 0; j < 3; ++j) {
+        const edge_st_t* e = edges[j];
+        if (!(e->t1 > e->t0)) continue;
+        /* s(t) = p + q t; (p + q t)^2 + (a2 + k t)^2 = R^2 */
+        const double q = (e->s1 - e->s0) / (e->t1 - e->t0), p = e->s0 - q * e->t0;
+        const double A = q * q + k * k, B = 2.0 * (p * q + a2 * k), C = p * p + a2 * a2 - R * R;
+        if (A == 0.0) continue;
+        const double disc = B * B - 4.0 * A * C;
+        if (disc < 0.0) continue;
+        const double sq = sqrt(disc);
+        const double r1 = (-B - sq) / (2.0 * A), r2 = (-B + sq) / (2.0 * A);
+        if (r1 > e->t0 && r1 < e->t1) bp[nb++] = r1;
+        if (r2 > e->t0 && r2 < e->t1) bp[nb++] = r2;
+    }
+    qsort(bp, (size_t)nb, sizeof(double), cmp_double);
+    double area = 0.0;
+    for (int i = 0; i + 1 < nb; ++i) {
+        const double ua = fmax(bp[i], tlo), ub = fmin(bp[i + 1], thi);
+        if (!(ub > ua)) continue;
+        const double tm = 0.5 * (ua + ub);
+        const edge_st_t* other = tm <= t[ib] ? &eab : &ebc;
+        if (!(other->t1 > other->t0) || !(eac.t1 > eac.t0)) continue;
+        double sa_u = edge_s(&eac, ua), sa_v = edge_s(&eac, ub), sa_m = edge_s(&eac, tm);
+        double so_u = edge_s(other, ua), so_v = edge_s(other, ub), so_m = edge_s(other, tm);
+        const int ac_low = sa_m <= so_m;
+        const double lo_u = ac_low ? sa_u : so_u, lo_v = ac_low ? sa_v : so_v, lo_m = fmin(sa_m, so_m);
+        const double hi_u = ac_low ? so_u : sa_u, hi_v = ac_low ? so_v : sa_v, hi_m = fmax(sa_m, so_m);
+        const double wm = chord_w(R, a2 + k * tm);
+        const double top = fmin(hi_m, wm), bot = fmax(lo_m, -wm);
+        if (!(top > bot)) continue;
+        const double len = ub - ua;
+        const double iw = (hi_m > wm || lo_m < -wm) ? int_w(R, a2, k, ua, ub) : 0.0;
+        const double upper = hi_m < wm ? 0.5 * (hi_u + hi_v) * len : iw;
+        const double lower = lo_m > -wm ? 0.5 * (lo_u + lo_v) * len : -iw;
+        area += upper - lower;
+    }
+    return area;
+}
+
+typedef struct {
+    const double* pos; const uint32_t* tri; uint32_t nt;
+    uint32_t obj_first, obj_count;
+    const double* op_pos; const double* op_nrm;
+    double R;
+    double* a_all; double* a_obj;
+} clutter_job_t;
+
+static void clutter_one(const void* ctx, int64_t img)
+{
+    const clutter_job_t* J = (const clutter_job_t*)ctx;
+    frame_t f;
+    make_frame(J->op_pos + 3 * img, J->op_nrm + 3 * img, &f);
+    double all = 0.0, obj = 0.0;
+    for (uint32_t i = 0; i < J->nt; ++i) {
+        double Q[3][3];
+        for (int k = 0; k < 3; ++k) {
+            const double* p = J->pos + 3 * (size_t)J->tri[3 * (size_t)i + k];
+            project(&f, p[0], p[1], p[2], &Q[k][0], &Q[k][1], &Q[k][2]);
+        }
+        const double a = tri_area_in_volume(J->R, Q[0], Q[1], Q[2]);
+        all += a;
+        if (i >= J->obj_first && i - J->obj_first < J->obj_count) obj += a;
+    }
+    J->a_all[img] = all;
+    J->a_obj[img] = obj;
+}
+
+/* Areas of the scene's and of the object's surface inside each oriented
+ * point's support volume; triangles obj_first .. obj_first + obj_count - 1 are
+ * the object.  fp32 inputs converted exactly.  -1 on a bad index. */
+int oracle_clutter_areas(const float* pos, uint32_t nv, const uint32_t* tri, uint32_t nt, uint32_t obj_first,
+                         uint32_t obj_count, const float* op_pos, const float* op_nrm, uint32_t n, float R,
+                         double* a_all, double* a_obj, int nthreads)
+{
+    if (check_mesh(tri, nt, nv)) return -1;
+    double* p = widen(pos, (size_t)nv * 3);
+    double* o = widen(op_pos, (size_t)n * 3);
+    double* m = widen(op_nrm, (size_t)n * 3);
+    int rc = -2;
+    if (p && o && m) {
+        clutter_job_t J = { p, tri, nt, obj_first, obj_count, o, m, (double)R, a_all, a_obj };
+        parallel_for(&J, clutter_one, n, nthreads);
+        rc = 0;
+    }
+    free(p); free(o); free(m);
+    return rc;
+}
+
+/* area of one triangle given in frame coordinates (FP64), for the pins */
+double oracle_triangle_area_in_volume(const double* p0, const double* p1, const double* p2, double R)
+{
+    return tri_area_in_volume(R, p0, p1, p2);
+}
