@@ -1065,35 +1065,49 @@ static double chord_w(double R, double d)
     return q > 0.0 ? sqrt(q) : 0.0;
 }
 
-/* integral over [t1, t2] of sqrt(R^2 - (a2 + k t)^2), with |a2 + k t| <= R there */
+/* integral over [t1, t2] of sqrt(R^2 - (a2 + k t)^2), with |a2 + k t| <= R there.
+ * With x = (a2 + k t) / R and c = sqrt(1 - x^2) the antiderivative in x is
+ * R^2 (x c + asin x) / 2, so the integral is R (G(x2) - G(x1)) / (2 x') with
+ * x' = k / R.  Three forms keep it well conditioned:
+ *   - the ends within 1e-6 of each other in x (a plane near parallel to the
+ *     axis, or a tiny piece): 5-point Gauss-Legendre of the smooth root;
+ *   - both ends away from tangency (c >= 0.1): the difference of G written
+ *     without cancellation (x2 c2 - x1 c1 and asin x2 - asin x1 each as
+ *     (x2 - x1) times a bounded factor), so that the division by x' is exact;
+ *   - otherwise G directly, with asin x taken as atan2(x, c): near tangency
+ *     the errors of c and of the angle then cancel to first order. */
 static double int_w(double R, double a2, double k, double t1, double t2)
 {
     const double dt = t2 - t1;
     if (!(dt > 0.0)) return 0.0;
-    double d1 = a2 + k * t1, d2 = a2 + k * t2;
-    d1 = fmax(-R, fmin(R, d1));
-    d2 = fmax(-R, fmin(R, d2));
-    const double w1 = chord_w(R, d1), w2 = chord_w(R, d2);
-    if (k == 0.0) return w1 * dt;
-    /* antiderivative in d: F(d) = (d w + R^2 asin(d / R)) / 2, divided by k.
-     * d2 w2 - d1 w1 = (d2 - d1) [w2 - d1 (d1 + d2) / (w1 + w2)] and
-     * d2 - d1 = k dt, so the first half needs no division by k. */
-    double part1 = 0.0;
-    if (w1 + w2 > 0.0) part1 = 0.5 * dt * (w2 - d1 * (d1 + d2) / (w1 + w2));
-    const double x1 = d1 / R, x2 = d2 / R;
-    const double s1 = chord_w(1.0, x1), s2 = chord_w(1.0, x2);
-    double part2;
-    if (x1 * x2 >= 0.0 && fabs(x2 - x1) < 0.5 && s1 + s2 > 0.0) {
-        /* asin x2 - asin x1 = asin(x2 s1 - x1 s2) and x2 s1 - x1 s2 =
-         * (x2 - x1) g with g = s1 + x1 (x1 + x2) / (s1 + s2); x2 - x1 = k dt / R */
-        const double g = s1 + x1 * (x1 + x2) / (s1 + s2);
-        const double delta = (x2 - x1) * g;
-        const double ratio = fabs(delta) < 1e-8 ? 1.0 + delta * delta / 6.0 : asin(delta) / delta;
-        part2 = 0.5 * R * R * ratio * g * dt / R;
-    } else {
-        part2 = 0.5 * R * R * (asin(x2) - asin(x1)) / k;
+    if (k == 0.0) return chord_w(R, a2) * dt;
+    const double x1 = fmax(-1.0, fmin(1.0, (a2 + k * t1) / R));
+    const double x2 = fmax(-1.0, fmin(1.0, (a2 + k * t2) / R));
+    const double c1 = chord_w(1.0, x1), c2 = chord_w(1.0, x2);
+    if (fabs(x2 - x1) < 1e-6) {
+        static const double node[5] = { -0.9061798459386640, -0.5384693101056831, 0.0,
+                                        0.5384693101056831, 0.9061798459386640 };
+        static const double weight[5] = { 0.2369268850561891, 0.4786286704993665, 0.5688888888888889,
+                                          0.4786286704993665, 0.2369268850561891 };
+        double sum = 0.0;
+        for (int q = 0; q < 5; ++q) {
+            const double t = 0.5 * (t1 + t2) + 0.5 * dt * node[q];
+            sum += weight[q] * chord_w(R, fmax(-R, fmin(R, a2 + k * t)));
+        }
+        return 0.5 * dt * sum;
     }
-    return part1 + part2;
+    if (fmin(c1, c2) >= 0.1 && x1 * x2 >= 0.0 && fabs(x2 - x1) < 0.5) {
+        /* x2 c2 - x1 c1 = (x2 - x1) [c2 - x1 (x1 + x2) / (c1 + c2)];
+         * asin x2 - asin x1 = asin((x2 - x1) g), g = c1 + x1 (x1 + x2) / (c1 + c2);
+         * and (x2 - x1) / x' = dt */
+        const double f = c2 - x1 * (x1 + x2) / (c1 + c2);
+        const double g = c1 + x1 * (x1 + x2) / (c1 + c2);
+        const double y = (x2 - x1) * g;
+        const double ratio = fabs(y) < 1e-8 ? 1.0 + y * y / 6.0 : asin(y) / y;
+        return 0.5 * R * dt * (f + ratio * g);
+    }
+    const double G1 = x1 * c1 + atan2(x1, c1), G2 = x2 * c2 + atan2(x2, c2);
+    return 0.5 * R * R * (G2 - G1) / k;
 }
 
 typedef struct { double s0, t0, s1, t1; } edge_st_t;
