@@ -200,6 +200,27 @@ int rici_spin_correlation_matrix(rici_handle h, const float* needles, uint32_t n
                                  void* stream);
 
 /*
+ * rici_clutter_areas -- the areas behind Eq. 8's clutter measure,
+ *   clutter = (A_all - A_object) / A_all,
+ * for each oriented point: A_all = surface area of all triangles, A_object =
+ * of the object's triangles object_first .. object_first + object_count - 1,
+ * inside the point's support volume (the descriptor's cylinder: distance from
+ * the Central Axis <= R and |beta| <= R/2, Sec. 2.1).
+ *   positions [num_vertices][3], triangles [num_triangles][3] as for
+ *   rici_generate; op_positions, op_normals [num_points][3] fp32;
+ *   out_area_all, out_area_object [num_points] double.
+ * Each triangle's area inside the volume is integrated exactly over its
+ * in-plane height in FP64 (closed forms for the circular boundary), so the
+ * results are the exact areas up to FP64 rounding.
+ */
+int rici_clutter_areas(rici_handle h, const float* positions, uint32_t num_vertices,
+                       const uint32_t* triangles, uint32_t num_triangles,
+                       uint32_t object_first, uint32_t object_count,
+                       const float* op_positions, const float* op_normals, uint32_t num_points,
+                       float support_radius, double* out_area_all, double* out_area_object,
+                       void* stream);
+
+/*
  * Batched describe-and-rank over many meshes (one plan, replayed as a HIP graph).
  *
  * Each job is one mesh with its own oriented points; its RICIs are written to
@@ -295,7 +316,7 @@ int rici_db_scan(rici_handle h, rici_db db, const rici_query* queries, uint32_t 
  * elapsed times of the completed launches of the named kernel ("gen",
  * "gen_prep", "delta_needle", "delta_haystack", "true_distance", "search",
  * "fallback", "matrix", "spin_gen", "spin_zprep", "spin_true", "spin_search",
- * "spin_settle", "spin_matrix").  Reading synchronises the handle's device.
+ * "spin_settle", "spin_matrix", "clutter").  Reading synchronises the handle's device.
  */
 int rici_timing_enable(rici_handle h, int on);
 int rici_timing_reset(rici_handle h);

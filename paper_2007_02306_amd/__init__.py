@@ -128,6 +128,26 @@ class Context:
                                               _stream_ptr(stream)))
         return out
 
+    def clutter_areas(self, positions, triangles, object_first: int, object_count: int, op_positions, op_normals,
+                      support_radius: float, stream=None):
+        """(A_all, A_object) float64 [N]: surface areas inside each oriented
+        point's support volume; Eq. 8 clutter = (A_all - A_object) / A_all."""
+        torch = _torch()
+        dev = self.device
+        pos = _dev(positions, "positions", torch.float32, (3,), dev)
+        tri = _dev(triangles, "triangles", torch.int32, (3,), dev)
+        opp = _dev(op_positions, "op_positions", torch.float32, (3,), dev)
+        opn = _dev(op_normals, "op_normals", torch.float32, (3,), dev)
+        if opp.shape != opn.shape:
+            raise ValueError("op_positions and op_normals differ in shape")
+        n = opp.shape[0]
+        a_all = torch.empty(n, dtype=torch.float64, device=opp.device)
+        a_obj = torch.empty(n, dtype=torch.float64, device=opp.device)
+        check(self._lib.rici_clutter_areas(self._h, _ptr(pos), pos.shape[0], _ptr(tri), tri.shape[0],
+                                           int(object_first), int(object_count), _ptr(opp), _ptr(opn), n,
+                                           float(support_radius), _ptr(a_all), _ptr(a_obj), _stream_ptr(stream)))
+        return a_all, a_obj
+
     # ------------------------------------------------------ spin images
     def spin_generate(self, samples, op_positions, op_normals, support_radius: float, out=None, stream=None):
         """Spin Images of the oriented points over the point samples: float32 [N, 64, 64]."""

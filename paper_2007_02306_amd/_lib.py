@@ -24,6 +24,7 @@ EXPORTS = [
     "rici_query_create", "rici_query_footprint", "rici_query_destroy", "rici_db_scan",
     "rici_set_tuning", "rici_get_tuning",
     "rici_spin_generate", "rici_spin_rank", "rici_spin_correlation_matrix",
+    "rici_clutter_areas",
 ]
 
 
@@ -85,6 +86,8 @@ def load(path: str = LIB_PATH):
         lib.rici_spin_rank.restype = I32
         lib.rici_spin_correlation_matrix.argtypes = [P, P, U32, P, U32, P, P]
         lib.rici_spin_correlation_matrix.restype = I32
+        lib.rici_clutter_areas.argtypes = [P, P, U32, P, U32, U32, U32, P, P, U32, F32, P, P, P]
+        lib.rici_clutter_areas.restype = I32
         lib.rici_distance_rank.argtypes = [P, P, U32, P, U32, P, P, P, P]
         lib.rici_distance_rank.restype = I32
         lib.rici_distance_matrix.argtypes = [P, P, U32, P, U32, P, P]

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librici.so")
-SOURCES = ["rici_gen.hip", "rici_search.hip", "rici_spin.hip", "rici_api.hip"]
+SOURCES = ["rici_gen.hip", "rici_search.hip", "rici_spin.hip", "rici_clutter.hip", "rici_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -12,11 +12,15 @@ One trial:
      cluttered set {CD}, one RICI per vertex of the combined mesh, and rank
      every reference RICI against all of {CD}; its correct match is the same
      vertex of the placed reference, which comes first in the combined mesh;
-  5. the histogram of those ranks is the trial's result for level k.
+  5. the histogram of those ranks is the trial's result for level k;
+  6. with each rank, the clutter around the reference vertex (Eq. 8): the
+     share of the surface inside its support volume that is not the
+     reference object's, (A_all - A_object) / A_all (rici_clutter_areas).
 
 The paper reports, per level, the fraction of searches whose correct match is
-at rank 0; `summarise` does the same over many trials.  Objects here are
-synthetic stand-ins for a mesh collection (no dataset is used).
+at rank 0; `summarise` does the same over many trials, and splits it by the
+clutter around each searched vertex.  Objects here are synthetic stand-ins for
+a mesh collection (no dataset is used).
 """
 
 from __future__ import annotations
@@ -77,10 +81,18 @@ def run_trial(ctx, rng: np.random.Generator, levels=(1, 5, 10), tri_lo: int = 10
         t0 = time.perf_counter()
         cd = ctx.generate(f32(pos), i32(scene.triangles), f32(pos), f32(nrm), support_radius)
         rank, dist = ctx.distance_rank(rd, cd, true_index)
+        # Eq. 8 around each placed reference vertex; the reference's triangles
+        # come first in the combined mesh
+        d_pos, d_tri = f32(pos), i32(scene.triangles)
+        a_all, a_obj = ctx.clutter_areas(d_pos, d_tri, 0, ref.triangles.shape[0], d_pos[:v0].contiguous(),
+                                         f32(nrm[:v0]), support_radius)
         ctx.sync()
         wall = time.perf_counter() - t0
         ranks = rank.cpu().numpy().view(np.uint32).copy()
-        out[k] = {"ranks": ranks, "reference_vertices": int(v0), "scene_vertices": int(pos.shape[0]),
+        A, O = a_all.cpu().numpy(), a_obj.cpu().numpy()
+        clutter = np.where(A > 0, (A - O) / np.where(A > 0, A, 1.0), 0.0)
+        out[k] = {"ranks": ranks, "clutter": clutter, "area_all": A, "area_object": O,
+                  "reference_vertices": int(v0), "scene_vertices": int(pos.shape[0]),
                   "scene_triangles": int(scene.triangles.shape[0]), "gpu_s": wall}
         if keep:
             out[k].update(scene=(pos, scene.triangles, nrm), rd=rd.cpu().numpy().view(np.uint32).copy(),
@@ -104,4 +116,21 @@ def summarise(trials: list[dict]) -> dict:
                   "rank0_fraction_per_trial_sorted": np.sort(per_trial).round(4).tolist(),
                   "rank_histogram_0_to_10plus": hist.tolist(),
                   "median_rank": float(np.median(allr))}
+        if all("clutter" in t[k] for t in trials):
+            cl = np.concatenate([t[k]["clutter"] for t in trials])
+            res[k]["clutter_mean"] = float(cl.mean())
+            res[k]["rank0_fraction_by_clutter"] = by_clutter(allr, cl)
     return res
+
+
+def by_clutter(ranks: np.ndarray, clutter: np.ndarray, edges=(0.0, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9,
+                                                                  1.0)) -> list:
+    """Rank-0 fraction of the searches in each clutter bin [e_i, e_i+1)
+    (the last bin closed): [(lower edge, searches, rank-0 fraction)]."""
+    out = []
+    for i in range(len(edges) - 1):
+        lo, hi = edges[i], edges[i + 1]
+        sel = (clutter >= lo) & ((clutter < hi) if i + 2 < len(edges) else (clutter <= hi))
+        n = int(sel.sum())
+        out.append((lo, n, float((ranks[sel] == 0).mean()) if n else None))
+    return out

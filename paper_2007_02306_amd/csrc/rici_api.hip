@@ -516,6 +516,41 @@ int rici_distance_matrix(rici_handle h, const uint32_t* needles, uint32_t num_ne
     return RICI_OK;
 }
 
+// ---------------------------------------------------------------- clutter
+
+int rici_clutter_areas(rici_handle h, const float* positions, uint32_t num_vertices, const uint32_t* triangles,
+                       uint32_t num_triangles, uint32_t object_first, uint32_t object_count,
+                       const float* op_positions, const float* op_normals, uint32_t num_points,
+                       float support_radius, double* out_area_all, double* out_area_object, void* stream)
+{
+    if (!h) return fail(RICI_ERR_INVALID, "rici_clutter_areas: NULL handle");
+    if (!(isfinite(support_radius) && support_radius > 0.0f))
+        return fail(RICI_ERR_INVALID, "rici_clutter_areas: support_radius must be finite and > 0");
+    if (num_points >= (1u << 31)) return fail(RICI_ERR_UNSUPPORTED, "rici_clutter_areas: num_points >= 2^31");
+    if (num_points == 0) return RICI_OK;
+    if (!op_positions || !op_normals || !out_area_all || !out_area_object)
+        return fail(RICI_ERR_INVALID, "rici_clutter_areas: NULL oriented-point or output pointer");
+    if (num_triangles > 0 && (!triangles || !positions || num_vertices == 0))
+        return fail(RICI_ERR_INVALID, "rici_clutter_areas: NULL mesh pointer or no vertices");
+    const size_t ob = (size_t)num_points * 8;
+    if (overlaps(out_area_all, ob, out_area_object, ob) ||
+        overlaps(out_area_all, ob, positions, (size_t)num_vertices * 12) ||
+        overlaps(out_area_object, ob, positions, (size_t)num_vertices * 12) ||
+        overlaps(out_area_all, ob, triangles, (size_t)num_triangles * 12) ||
+        overlaps(out_area_object, ob, triangles, (size_t)num_triangles * 12))
+        return fail(RICI_ERR_INVALID, "rici_clutter_areas: an output overlaps another array");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = timed(h, "clutter", s, [&] {
+        return rici::launch_clutter(positions, num_vertices, triangles, num_triangles, object_first, object_count,
+                                    op_positions, op_normals, num_points, support_radius, out_area_all,
+                                    out_area_object, h->d_err, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "clutter launch");
+    return RICI_OK;
+}
+
 // ------------------------------------------------------------ spin images
 
 int rici_spin_generate(rici_handle h, const float* samples, uint32_t num_samples, const float* op_positions,

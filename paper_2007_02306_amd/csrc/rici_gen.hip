@@ -573,6 +573,10 @@ __device__ void gen_images(GenLds<G>& L, const GenJob& J, uint32_t img0, float R
                 const float margin = 1e-5f * (mag + Rf) + 1e-30f;
                 c[6] = 0.5f * Rf + margin;    // slab half height
                 c[7] = Rf + margin;           // cylinder radius
+                // a Spin Vertex or radius beyond 1e18 would overflow the FP32
+                // squares of the cull: every triangle then reaches the image
+                // (the exact FP64 stage handles any finite coordinates)
+                if (!(mag < 1e18f) || !(Rf < 1e18f)) c[6] = c[7] = INFINITY;
             }
         }
         if (!live) {
@@ -596,14 +600,17 @@ __device__ void gen_images(GenLds<G>& L, const GenJob& J, uint32_t img0, float R
 
     // Conservative FP32 sphere test against image g's support volume: the slab
     // |beta| <= R/2 and the cylinder alpha <= R, both with margins.  An infinite
-    // radius (a sphere too large for FP32 squares) reaches every live image.
+    // radius (a sphere too large for FP32 squares) reaches every live image,
+    // and an image whose own cull would overflow (infinite slab) is reached by
+    // every sphere.
     auto reaches = [&](const float4& sp, int g) -> bool {
         const float dx = sp.x - P[g][0], dy = sp.y - P[g][1], dz = sp.z - P[g][2];
         const float h = P[g][3] * dx + P[g][4] * dy + P[g][5] * dz;
         const float d2 = dx * dx + dy * dy + dz * dz;
         const float a2 = d2 - h * h;
         const float la = P[g][7] + sp.w;
-        return ((fabsf(h) <= P[g][6] + sp.w) & (a2 <= la * la)) | ((sp.w == INFINITY) & (P[g][6] > 0.f));
+        return ((fabsf(h) <= P[g][6] + sp.w) & (a2 <= la * la)) | ((sp.w == INFINITY) & (P[g][6] > 0.f)) |
+               (P[g][6] == INFINITY);
     };
 
     // Test one run of 64 triangles (spheres s, triangle t = run * 64 + lane)

@@ -115,8 +115,10 @@ struct SearchArgs {
     uint32_t* rank;
     int64_t* matrix;
     uint32_t tiles_m, tiles_n, per_xcd;
-    // rank mode only: leave a tile as soon as every partial distance of its
-    // last (monotone) phase has reached the needle's threshold
+    // rank mode only: leave a tile once no pair can still end below its
+    // needle's threshold: in the last phase a partial sum can fall by at most
+    // 128 * 63 per remaining row (r >= -128), so a tile stops when every
+    // partial sum exceeds its threshold by that slack
     uint32_t early_exit;
 };
 
@@ -188,6 +190,13 @@ hipError_t launch_spin_rank(const SpinPrep& np, const float* needles, uint32_t n
                             int part = 0);   // 0 all; 1 true correlations; 2 contraction; 3 settle the queue
 hipError_t launch_spin_matrix(const SpinPrep& np, uint32_t nn, const SpinPrep& hp, uint32_t nh, float* out,
                               hipStream_t s);
+
+// ------------------------------------------------------------- clutter
+// a_all / a_obj: surface area of all triangles / of triangles obj_first ..
+// obj_first + obj_count - 1 inside each oriented point's support volume
+hipError_t launch_clutter(const float* pos, uint32_t nv, const uint32_t* tri, uint32_t nt, uint32_t obj_first,
+                          uint32_t obj_count, const float* op_pos, const float* op_nrm, uint32_t n, float R,
+                          double* a_all, double* a_obj, uint32_t* err, hipStream_t s);
 
 size_t search_groups(uint32_t n);   // fragment groups allocated for n images
 size_t search_lds_bytes();          // dynamic LDS of the search kernel

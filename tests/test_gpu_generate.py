@@ -236,6 +236,28 @@ def test_power_of_two_scaling_bit_identical(ctx, k):
     assert np.array_equal(a, b)
 
 
+def test_far_oriented_points_see_small_triangles(ctx):
+    """Mixed magnitudes: the union of 12 shapes scaled by 2^59 (coordinates
+    below 1e18, so its triangles keep finite FP32 cull spheres) seen from
+    oriented points 2.5e19 away along their normals with R = 5.2e19, so that
+    the scene sits inside their support volumes.  The image side of the FP32
+    cull would overflow there (squares of 2.5e19 exceed the fp32 range); such images must take every
+    triangle, and the counts equal the oracle's outside flags."""
+    s = synth.config2_union12()
+    f = np.float32(2.0 ** 59)
+    pos = s.positions * f
+    rng = np.random.default_rng(17)
+    nrm = rng.normal(size=(256, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    opp = (nrm * 2.5e19 + rng.uniform(-1e17, 1e17, size=(256, 3))).astype(np.float32)
+    opn = (-nrm).astype(np.float32)               # the axis points back at the scene
+    R = 5.2e19
+    g = gpu_images(ctx, pos, s.triangles, opp, opn, R)
+    o, fl, _ = oracle.rici_rowrange(pos, s.triangles, opp, opn, R)
+    assert_images_match(g, o, fl, "far oriented points")
+    assert o.sum() > 0
+
+
 def test_repeatable(ctx):
     s = synth.config1_icosphere()
     a = gpu_images(ctx, s.positions, s.triangles, s.op_positions, s.op_normals, 1.0)
