@@ -517,7 +517,7 @@ def union12_step(ctx, steps: int, warmup: int, cpu: bool, args=None):
     ctx.sync()
     ctx.timing(False)
     kernels = {}
-    for k in ["gen_prep", "gen", "delta_needle", "delta_haystack", "true_distance", "search", "fallback"]:
+    for k in ["gen_prep", "gen", "delta_needle", "delta_haystack", "paired_prep", "true_distance", "search", "fallback"]:
         ms, n = ctx.timing_get(k)
         kernels[k] = {"avg_ms": ms / n if n else None, "launches": n}
     ms_step = elapsed * 1e3 / steps

@@ -30,6 +30,8 @@ struct rici_ctx {
     int gen_group = 2;              // images per generation workgroup: 2 or 4
     int gen_sort = 2;               // triangle order: 0 mesh, 1 Morton, 2 Morton for large meshes
     int early_exit = 0;             // search tiles may stop once no pair can count (rank mode)
+    int search_pairs = 1;           // a set ranked against itself: tile pairs share the cross term
+    int cus = 0;                    // compute units of the device
     std::vector<TimedLaunch> launches;
     std::vector<hipEvent_t> free_events;
 };
@@ -202,6 +204,7 @@ int rici_create(rici_handle* out, int device)
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     rici_ctx* h = new rici_ctx();
     h->device = device;
+    h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
     e = hipMalloc(&h->d_err, sizeof(uint32_t));
     if (e != hipSuccess) {
         delete h;
@@ -409,6 +412,82 @@ int search_scratch(rici_ctx* h, uint32_t nn, uint32_t nh, bool want_dstar, Searc
     S.lists = (uint32_t*)p;
     S.np.ngroups = (uint32_t)ga;
     S.hp.ngroups = (uint32_t)gb;
+    S.np.inv = S.hp.inv = nullptr;
+    return RICI_OK;
+}
+
+// Whether a rank call takes the paired path: one set ranked against itself,
+// square tiles, no early exit.
+bool use_pairs(const rici_ctx* h, const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh)
+{
+    return h->search_pairs && h->search_variant == 0 && !h->early_exit && needles == hay && nn == nh;
+}
+
+// The paired path of rici_distance_rank: needles and haystack in one slot
+// order, the tile pairs (I <= J) searched by a persistent kernel, each
+// workgroup holding one cross-term slot.
+int rank_paired(rici_ctx* h, const uint32_t* images, uint32_t n, const uint32_t* true_index, uint32_t* out_rank,
+                int64_t* out_true_distance, hipStream_t s)
+{
+    const size_t hslots = rici::haystack_slots(n), gb = hslots / rici::kGroup;
+    const uint32_t tiles = (uint32_t)(hslots / rici::search_tile_n());
+    const uint32_t items = rici::paired_items(tiles);
+    const uint32_t grid = std::min<uint32_t>((uint32_t)h->cus, items);
+    const size_t a_planes = align256(2 * gb * rici::kPlaneGroupBytes);
+    const size_t b_planes = align256(3 * gb * rici::kPlaneGroupBytes);
+    const size_t sumsq = align256((size_t)n * sizeof(int64_t));
+    const size_t slot_u32 = align256(hslots * sizeof(uint32_t));
+    const size_t img_u32 = align256((size_t)n * sizeof(uint32_t));
+    const size_t flags = align256((size_t)tiles * sizeof(uint32_t));
+    const size_t dstar = out_true_distance ? 0 : align256((size_t)n * sizeof(int64_t));
+    const size_t lists = align256((2 + 2 * (size_t)n) * sizeof(uint32_t));
+    const size_t counters = 256;
+    const size_t cross = (size_t)grid * rici::paired_slot_bytes();
+    // planes, sumsq, maxabs/perm/thr per slot, maxabs/inv per image, flags, ...
+    const size_t total = a_planes + b_planes + sumsq + 3 * slot_u32 + 2 * img_u32 + flags + dstar + lists + counters +
+                         cross;
+    int rc = ensure_ws(h, total);
+    if (rc) return rc;
+    char* p = (char*)h->ws;
+    rici::SearchPrep np = {}, hp = {};
+    np.planes = (int8_t*)p; p += a_planes;
+    hp.planes = (int8_t*)p; p += b_planes;
+    np.sumsq = (int64_t*)p; p += sumsq;
+    hp.maxabs = (uint32_t*)p; p += slot_u32;
+    hp.perm = (uint32_t*)p; p += slot_u32;
+    int32_t* thr = (int32_t*)p; p += slot_u32;
+    hp.maxabs_img = (uint32_t*)p; p += img_u32;
+    hp.inv = (uint32_t*)p; p += img_u32;
+    uint32_t* tile_flags = (uint32_t*)p; p += flags;
+    int64_t* ds = out_true_distance ? out_true_distance : (int64_t*)p; p += dstar;
+    uint32_t* lst = (uint32_t*)p; p += lists;
+    uint32_t* cnt = (uint32_t*)p; p += counters;
+    int32_t* cslots = (int32_t*)p;
+    np.maxabs = np.maxabs_img = hp.maxabs_img;   // per image (the needle pass writes no statistics)
+    np.ngroups = hp.ngroups = (uint32_t)gb;
+
+    hipError_t e = timed(h, "paired_prep", s,
+                         [&] { return rici::launch_paired_prep(images, n, np, hp, thr, tile_flags, s); });
+    if (e != hipSuccess) return hip_fail(e, "paired_prep launch");
+    e = timed(h, "true_distance", s, [&] {
+        return rici::launch_true_distance(images, n, images, n, true_index, np.sumsq, hp.maxabs_img, ds, thr,
+                                          out_rank, s, hp.inv);
+    });
+    if (e != hipSuccess) return hip_fail(e, "true_distance launch");
+    rici::SearchArgs A = {};
+    A.a_planes = np.planes; A.a_groups = (uint32_t)gb; A.nn = n;
+    A.b_planes = hp.planes; A.b_groups = (uint32_t)gb; A.nh = n;
+    A.nmax = hp.maxabs; A.hmax = hp.maxabs; A.hperm = hp.perm;
+    A.thr = thr; A.sumsq = np.sumsq; A.rank = out_rank; A.matrix = nullptr;
+    A.tiles_m = A.tiles_n = tiles;
+    A.paired = 1; A.nperm = hp.perm; A.tile_flags = tile_flags; A.cross = cslots;
+    e = timed(h, "search", s, [&] { return rici::launch_search_paired(A, grid, cnt, s); });
+    if (e != hipSuccess) return hip_fail(e, "search launch");
+    e = timed(h, "fallback", s, [&] {
+        return rici::launch_fallback(images, n, images, n, hp.maxabs_img, hp.maxabs_img, ds, out_rank, nullptr, lst,
+                                     s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "fallback launch");
     return RICI_OK;
 }
 
@@ -459,6 +538,8 @@ int rici_distance_rank(rici_handle h, const uint32_t* needles, uint32_t num_need
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
+    if (use_pairs(h, needles, num_needles, haystack, num_haystack))
+        return rank_paired(h, needles, num_needles, true_index, out_rank, out_true_distance, s);
     SearchScratch S;
     rc = search_scratch(h, num_needles, num_haystack, out_true_distance == nullptr, S);
     if (rc) return rc;
@@ -733,6 +814,12 @@ int rici_set_tuning(rici_handle h, const char* key, int value)
         h->search_variant = value == 128 ? 1 : 0;
         return RICI_OK;
     }
+    if (strcmp(key, "search_pairs") == 0) {
+        if (value != 0 && value != 1)
+            return fail(RICI_ERR_INVALID, "rici_set_tuning: search_pairs must be 0 or 1 (got %d)", value);
+        h->search_pairs = value;
+        return RICI_OK;
+    }
     return fail(RICI_ERR_INVALID, "rici_set_tuning: unknown key '%s'", key);
 }
 
@@ -753,6 +840,10 @@ int rici_get_tuning(rici_handle h, const char* key, int* value)
     }
     if (strcmp(key, "search_tile_m") == 0) {
         *value = (int)rici::search_tile_m(h->search_variant);
+        return RICI_OK;
+    }
+    if (strcmp(key, "search_pairs") == 0) {
+        *value = h->search_pairs;
         return RICI_OK;
     }
     return fail(RICI_ERR_INVALID, "rici_get_tuning: unknown key '%s'", key);
@@ -910,19 +1001,28 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
                      align256(((size_t)j.num_triangles + 63) / 64 * rici::kTriCullBytes) +
                      align256((size_t)j.num_triangles * rici::kTriVertBytes);
     }
+    // paired sets (each mesh ranked against itself): needle planes in the
+    // haystack's slot order, thresholds per slot, tile flags, and one
+    // cross-term slot per persistent search workgroup
+    const bool paired = h->search_pairs && variant == 0 && !h->early_exit;
+    auto needle_groups = [&](uint32_t n) {
+        return paired ? rici::haystack_slots(n) / rici::kGroup : rici::search_groups(n);
+    };
     size_t srch_bytes = 0;
     std::vector<size_t> soff(sorder.size());
     for (size_t i = 0; i < sorder.size(); ++i) {
         const uint32_t n = jobs[sorder[i]].num_points;
-        const size_t ga = rici::search_groups(n), hs = rici::haystack_slots(n), gb = hs / rici::kGroup;
+        const size_t ga = needle_groups(n), hs = rici::haystack_slots(n), gb = hs / rici::kGroup;
         soff[i] = srch_bytes;
         srch_bytes += align256(2 * ga * rici::kPlaneGroupBytes) + align256(3 * gb * rici::kPlaneGroupBytes) +
                       align256(ga * rici::kGroup * 8) + align256(ga * rici::kGroup * 4) + align256(hs * 4) +
-                      align256((size_t)n * 4) + align256(hs * 4) + align256((size_t)n * 4) +
-                      align256((size_t)n * 8) + align256((2 + 2 * (size_t)n) * 4);
+                      align256((size_t)n * 4) + align256(hs * 4) + align256(std::max<size_t>(hs, n) * 4) +
+                      align256((size_t)n * 8) + align256((2 + 2 * (size_t)n) * 4) +
+                      (paired ? align256((size_t)n * 4) + align256(hs / tn * 4) : 0);
     }
+    const size_t cross_bytes = paired && !sorder.empty() ? (size_t)grid * rici::paired_slot_bytes() : 0;
     const size_t tables = align256(gorder.size() * sizeof(rici::GenJob)) +
-                          align256(sorder.size() * sizeof(rici::SearchJob)) + 256;
+                          align256(sorder.size() * sizeof(rici::SearchJob)) + 256 + cross_bytes;
     const size_t total = tables + std::max(gen_bytes, srch_bytes);
 
     rici_batch_ctx* b = new rici_batch_ctx();
@@ -939,7 +1039,8 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
     char* base = (char*)b->scratch;
     rici::GenJob* d_gjobs = (rici::GenJob*)base;
     rici::SearchJob* d_sjobs = (rici::SearchJob*)(base + align256(gorder.size() * sizeof(rici::GenJob)));
-    uint32_t* d_counters = (uint32_t*)(base + tables - 256);
+    uint32_t* d_counters = (uint32_t*)(base + tables - cross_bytes - 256);
+    int32_t* d_cross = cross_bytes ? (int32_t*)(base + tables - cross_bytes) : nullptr;
     char* work = base + tables;
 
     // ---- generation table
@@ -968,7 +1069,7 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
     for (size_t i = 0; i < sorder.size(); ++i) {
         const rici_mesh_job& j = jobs[sorder[i]];
         const uint32_t n = j.num_points;
-        const size_t ga = rici::search_groups(n), hs = rici::haystack_slots(n), gb = hs / rici::kGroup;
+        const size_t ga = needle_groups(n), hs = rici::haystack_slots(n), gb = hs / rici::kGroup;
         rici::SearchJob& S = sj[i];
         char* p = work + soff[i];
         S.np.planes = (int8_t*)p; p += align256(2 * ga * rici::kPlaneGroupBytes);
@@ -978,10 +1079,17 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
         S.hp.maxabs = (uint32_t*)p; p += align256(hs * 4);
         S.hp.maxabs_img = (uint32_t*)p; p += align256((size_t)n * 4);
         S.hp.perm = (uint32_t*)p; p += align256(hs * 4);
-        int32_t* thr = (int32_t*)p; p += align256((size_t)n * 4);
+        int32_t* thr = (int32_t*)p; p += align256(std::max<size_t>(hs, n) * 4);
         int64_t* dstar = (int64_t*)p; p += align256((size_t)n * 8);
-        S.lists = (uint32_t*)p;
+        S.lists = (uint32_t*)p; p += align256((2 + 2 * (size_t)n) * 4);
         S.np.maxabs_img = S.np.maxabs; S.np.perm = nullptr; S.hp.sumsq = nullptr;
+        S.np.inv = S.hp.inv = nullptr;
+        uint32_t* tile_flags = nullptr;
+        if (paired) {
+            S.hp.inv = (uint32_t*)p; p += align256((size_t)n * 4);
+            tile_flags = (uint32_t*)p;
+            S.np.maxabs = S.np.maxabs_img = S.hp.maxabs_img;   // per image
+        }
         S.np.ngroups = (uint32_t)ga; S.hp.ngroups = (uint32_t)gb;
         S.needles = j.out_images; S.hay = j.out_images; S.true_idx = j.true_index;
         S.dstar = j.out_true_distance ? j.out_true_distance : dstar;
@@ -991,14 +1099,17 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
         A.b_planes = S.hp.planes; A.b_groups = S.hp.ngroups; A.nh = n;
         A.nmax = S.np.maxabs; A.hmax = S.hp.maxabs; A.hperm = S.hp.perm;
         A.thr = thr; A.sumsq = S.np.sumsq; A.rank = j.out_rank; A.matrix = nullptr;
-        A.tiles_m = (uint32_t)((n + tm - 1) / tm);
+        A.tiles_m = paired ? (uint32_t)(hs / tn) : (uint32_t)((n + tm - 1) / tm);
         A.tiles_n = (uint32_t)(hs / tn);
         A.per_xcd = 0;
         A.early_exit = (uint32_t)h->early_exit;
+        if (paired) {
+            A.paired = 1; A.nperm = S.hp.perm; A.tile_flags = tile_flags; A.cross = d_cross;
+        }
         S.ngrp_start = T.needle_groups; S.hslot_start = T.hay_slots; S.himg_start = T.hay_images;
         S.hgrp_start = T.hay_groups; S.needle_start = T.needles; S.tile_start = tiles;
         T.needle_groups += ga; T.hay_slots += hs; T.hay_images += n; T.hay_groups += gb; T.needles += n;
-        tiles += A.tiles_m * A.tiles_n;
+        tiles += paired ? rici::paired_items(A.tiles_m) : A.tiles_m * A.tiles_n;
     }
     T.tiles = tiles;
     if (!gj.empty()) e = hipMemcpy(d_gjobs, gj.data(), gj.size() * sizeof(rici::GenJob), hipMemcpyHostToDevice);
@@ -1045,7 +1156,7 @@ int rici_batch_create(rici_handle h, const rici_mesh_job* jobs, uint32_t num_job
                                           d_counters, h->d_err, gen_grid, gen_group, cs, k + 1);
         else
             le = rici::launch_search_batched(d_sjobs, (uint32_t)sj.size(), T, d_counters + 1, grid, variant,
-                                             h->early_exit, cs, k - 1);
+                                             h->early_exit, cs, k - 1, paired ? 1 : 0);
         hipError_t ee = hipStreamEndCapture(cs, &seg[k]);
         if (e == hipSuccess) e = ee;
     }

@@ -100,6 +100,7 @@ struct SearchPrep {
     uint32_t* maxabs;      // max |D| per slot (saturating; padding = 0xFFFFFFFF)
     uint32_t* maxabs_img;  // max |D| per original image (== maxabs for needles)
     uint32_t* perm;        // haystack: slot -> image (0xFFFFFFFF = padding); needles: nullptr
+    uint32_t* inv;         // paired sets (haystack side): image -> slot; else nullptr
     uint32_t ngroups;      // slots / 16
 };
 
@@ -120,6 +121,18 @@ struct SearchArgs {
     // 128 * 63 per remaining row (r >= -128), so a tile stops when every
     // partial sum exceeds its threshold by that slack
     uint32_t early_exit;
+    // Paired mode (rank mode, a set ranked against itself): needles and
+    // haystack share the haystack's slot order, so tile (I, J) holds the pairs
+    // of both directions.  Work items are the tile pairs I <= J; a pair of
+    // tiles whose images all have |D| <= 15 computes the cross term once and
+    // reuses it for the mirrored direction through a per-workgroup slot of
+    // `cross` (BM x BN int32 per resident workgroup).  nperm maps a needle
+    // slot to its image (rank index); tile_flags[t]: bit 0 = some image of
+    // tile t is usable (|D| <= 127), bit 1 = some usable image has |D| > 15.
+    uint32_t paired;
+    const uint32_t* nperm;
+    const uint32_t* tile_flags;
+    int32_t* cross;
 };
 
 // One ranking job of a batched call (device copy): its arguments, its scratch
@@ -158,12 +171,30 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
 // part: 0 everything; 1 the launches before the persistent kernel (delta
 // planes, statistics, true-match distances, work counters); 2 the persistent
 // search kernel alone; 3 the launches after it (exact fallback)
+// paired: every job is a paired set (variant 0, no early exit); its needle
+// planes are then written after the slot assignment
 hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,
-                                 uint32_t grid, int variant, int early_exit, hipStream_t s, int part = 0);
+                                 uint32_t grid, int variant, int early_exit, hipStream_t s, int part = 0,
+                                 int paired = 0);
 size_t haystack_slots(uint32_t nh);   // slots allocated for a haystack of nh images
+// inv (paired sets): thresholds are written per slot, thr[inv[i]]
 hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                                 const uint32_t* true_idx, const int64_t* sumsq, const uint32_t* nmax,
-                                int64_t* dstar, int32_t* thr, uint32_t* rank, hipStream_t s);
+                                int64_t* dstar, int32_t* thr, uint32_t* rank, hipStream_t s,
+                                const uint32_t* inv = nullptr);
+// A set of n images ranked against itself ("paired"): haystack statistics,
+// slot assignment (hp.perm, hp.inv, hp.maxabs), needle planes (np, sumsq per
+// image) and haystack planes in the same slot order, thresholds per slot
+// initialised to INT_MIN, and the flags of each 256-slot tile.  np.ngroups ==
+// hp.ngroups == haystack_slots(n) / 16.
+hipError_t launch_paired_prep(const uint32_t* images, uint32_t n, const SearchPrep& np, const SearchPrep& hp,
+                              int32_t* thr_slots, uint32_t* tile_flags, hipStream_t s);
+// persistent search over the tile pairs of a paired set (A.paired, square
+// tiles); grid <= resident workgroups, each with a paired_slot_bytes() slot
+// of A.cross; counters: 8 words of scratch
+hipError_t launch_search_paired(const SearchArgs& A, uint32_t grid, uint32_t* counters, hipStream_t s);
+uint32_t paired_items(uint32_t tiles);   // work items of a paired set of `tiles` tiles
+size_t paired_slot_bytes();              // cross-term slot per persistent workgroup
 hipError_t launch_search(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
                          const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix, int variant,
                          int early_exit, hipStream_t s);

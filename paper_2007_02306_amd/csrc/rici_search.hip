@@ -34,6 +34,11 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr uint32_t kSlow = 127;     // largest |D| an int8 operand holds
 constexpr uint32_t kSmallD = 15;    // |D| <= 15  =>  D^2 <= 225: q = 0, r = D^2 - 128 fits int8
 constexpr uint32_t kPad = 0xFFFFFFFFu;
+// word 3 of a gfx9 buffer resource for untyped (raw) dword accesses
+constexpr int kBufferWord3 = 0x00020000;
+// cache policy of a buffer access: sc1 (device scope; a load misses in the
+// CU's vector L1)
+constexpr int kDeviceScope = 16;
 
 // ------------------------------------------------------------------ delta prep
 
@@ -110,7 +115,7 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
         if (!needle_side)
             *reinterpret_cast<uint4*>(planes + 2 * plane_stride + frag) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
     }
-    if (perm) return;   // the haystack's statistics come from k_hay_stats
+    if (perm && !needle_side) return;   // the haystack's statistics come from k_hay_stats
     // per-image reductions: 4 lanes (q) per wave and kDeltaWaves waves share image i
 #pragma unroll
     for (int o = 16; o < 64; o <<= 1) {
@@ -125,8 +130,16 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
         int64_t s = 0;
 #pragma unroll
         for (int w = 0; w < kDeltaWaves; ++w) { m = max(m, smax[w][tid]); s += ssum[w][tid]; }
-        maxabs[im] = im < n ? m : kPad;
-        if (sumsq) sumsq[im] = im < n ? s : 0;
+        if (perm) {
+            // needles in the haystack's slot order (paired sets): the constant
+            // is kept per image; max |D| per slot and per image come from the
+            // haystack statistics
+            const uint32_t img = perm[im];
+            if (img != kPad && sumsq) sumsq[img] = s;
+        } else {
+            maxabs[im] = im < n ? m : kPad;
+            if (sumsq) sumsq[im] = im < n ? s : 0;
+        }
     }
 }
 
@@ -143,10 +156,14 @@ k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
 // workgroup, prefix sums) gives images with |D| <= 15 the front slots and the
 // others the back slots, both in image order, so the layout is deterministic.
 __global__ void __launch_bounds__(256)
-k_hay_init(uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs, uint32_t nslots)
+k_hay_init(uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs, int32_t* __restrict__ thr, uint32_t nslots)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < nslots) { perm[s] = kPad; maxabs[s] = kPad; }
+    if (s < nslots) {
+        perm[s] = kPad;
+        maxabs[s] = kPad;
+        if (thr) thr[s] = INT_MIN;   // paired sets: thresholds per slot, none for padding
+    }
 }
 
 __device__ void hay_stats_one(const uint32_t* __restrict__ images, uint32_t* __restrict__ maxabs_img,
@@ -192,7 +209,8 @@ k_copy_u32(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, uint32_
 // consecutive ones (coalesced loads, the next round prefetched); a workgroup
 // scan of the small/other flags gives each image its slot in image order.
 __device__ void hay_assign_block(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslots,
-                                 uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs)
+                                 uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs,
+                                 uint32_t* __restrict__ inv)
 {
     __shared__ uint32_t wsum[2][16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -222,6 +240,7 @@ __device__ void hay_assign_block(const uint32_t* __restrict__ maxabs_img, uint32
                                         : nslots - 1 - (base_o + (uint32_t)tid - small_before);
             perm[slot] = i;
             maxabs[slot] = m;
+            if (inv) inv[i] = slot;
         }
         const uint32_t cnt = min(1024u, n - r0);
         base_s += tot;
@@ -231,9 +250,34 @@ __device__ void hay_assign_block(const uint32_t* __restrict__ maxabs_img, uint32
 
 __global__ void __launch_bounds__(1024)
 k_hay_assign(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslots,
-             uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs)
+             uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs, uint32_t* __restrict__ inv)
 {
-    hay_assign_block(maxabs_img, n, nslots, perm, maxabs);
+    hay_assign_block(maxabs_img, n, nslots, perm, maxabs, inv);
+}
+
+// Paired sets: per tile of 256 slots, bit 0 = some image with |D| <= 127 (the
+// tile takes part in the contraction), bit 1 = some such image with |D| > 15
+// (the tile needs the q phase).  One wavefront per tile.
+__device__ void tile_flags_one(const uint32_t* __restrict__ maxabs, uint32_t* __restrict__ flags, uint32_t t,
+                               int lane)
+{
+    const uint4 m = reinterpret_cast<const uint4*>(maxabs + (size_t)t * 256)[lane];
+    const uint32_t mx[4] = {m.x, m.y, m.z, m.w};
+    bool use = false, big = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        use |= mx[k] <= kSlow;
+        big |= mx[k] > kSmallD && mx[k] <= kSlow;
+    }
+    const uint64_t bu = __ballot(use), bb = __ballot(big);
+    if (lane == 0) flags[t] = (bu ? 1u : 0u) | (bb ? 2u : 0u);
+}
+
+__global__ void __launch_bounds__(256)
+k_tile_flags(const uint32_t* __restrict__ maxabs, uint32_t tiles, uint32_t* __restrict__ flags)
+{
+    const uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t < tiles) tile_flags_one(maxabs, flags, t, threadIdx.x & 63);
 }
 
 // ------------------------------------------------------------ exact int64 CRD
@@ -265,15 +309,17 @@ __device__ __forceinline__ int64_t crd_wave(const uint32_t* __restrict__ nimg, c
     return s;
 }
 
+// thr is indexed by needle, or by the needle's slot (inv) for paired sets.
 __device__ void true_distance_one(const uint32_t* __restrict__ needles, const uint32_t* __restrict__ hay,
                                   uint32_t nh, const uint32_t* __restrict__ true_idx,
                                   const int64_t* __restrict__ sumsq, const uint32_t* __restrict__ nmax,
                                   int64_t* __restrict__ dstar, int32_t* __restrict__ thr, uint32_t* __restrict__ rank,
-                                  uint32_t i, int lane)
+                                  const uint32_t* __restrict__ inv, uint32_t i, int lane)
 {
     const uint32_t t = true_idx[i];
+    const uint32_t ti = inv ? inv[i] : i;
     if (t >= nh) {
-        if (lane == 0) { dstar[i] = -1; thr[i] = INT_MIN; rank[i] = nh; }
+        if (lane == 0) { dstar[i] = -1; thr[ti] = INT_MIN; rank[i] = nh; }
         return;
     }
     const int64_t d = crd_wave(needles + (size_t)i * NPIX, hay + (size_t)t * NPIX, lane);
@@ -281,7 +327,7 @@ __device__ void true_distance_one(const uint32_t* __restrict__ needles, const ui
         dstar[i] = d;
         int64_t th = d - sumsq[i];
         th = min(max(th, (int64_t)INT_MIN + 1), (int64_t)INT_MAX);
-        thr[i] = nmax[i] <= kSlow ? (int32_t)th : INT_MIN;
+        thr[ti] = nmax[i] <= kSlow ? (int32_t)th : INT_MIN;
         rank[i] = 0;
     }
 }
@@ -290,10 +336,11 @@ __global__ void __launch_bounds__(256)
 k_true_distance(const uint32_t* __restrict__ needles, uint32_t nn, const uint32_t* __restrict__ hay, uint32_t nh,
                 const uint32_t* __restrict__ true_idx, const int64_t* __restrict__ sumsq,
                 const uint32_t* __restrict__ nmax, int64_t* __restrict__ dstar, int32_t* __restrict__ thr,
-                uint32_t* __restrict__ rank)
+                uint32_t* __restrict__ rank, const uint32_t* __restrict__ inv)
 {
     const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i < nn) true_distance_one(needles, hay, nh, true_idx, sumsq, nmax, dstar, thr, rank, i, threadIdx.x & 63);
+    if (i < nn)
+        true_distance_one(needles, hay, nh, true_idx, sumsq, nmax, dstar, thr, rank, inv, i, threadIdx.x & 63);
 }
 
 // ----------------------------------------------------------------- MFMA search
@@ -399,12 +446,30 @@ __device__ __forceinline__ void issue_stage(int8_t* lds, int slot, int t, int wv
     }
 }
 
+// Passes over one tile: kModePlain, the whole tile; kModeStore, the same for a
+// tile whose haystack images all have |D| <= 15, also leaving -2 <D_n, D_h> in
+// `cslot` after the cross phase; kModeMirror, the mirrored direction of that
+// tile (paired sets): its rows are then haystack images and its columns
+// needles, the accumulator starts from `cslot` (the cross term is symmetric:
+// <-D_a, D_b> = <-D_b, D_a>) and only the r phase runs, with the row tile's r
+// plane as the first operand and the column tile's mask as the second.
+enum { kModePlain = 0, kModeStore = 1, kModeMirror = 2 };
+
 // One BM x BN (needle x haystack) tile: every workgroup thread takes part.
 // EXIT compiles in the early exit of rank mode (taken when A.early_exit is set).
-template <class C, bool EXIT>
-__device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_t* lds)
+// cform (store and mirror passes): whether this wave's cross term went to
+// `cslot` as int16 (1) or int32 (0); the store pass sets it and its mirror
+// reads it (a wave-uniform value: each wave reads back only what it wrote).
+template <class C, bool EXIT, int MODE = kModePlain>
+__device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_t* lds, int32_t* cslot = nullptr,
+                            uint32_t* cform = nullptr)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    static_assert(MODE == kModePlain || (!EXIT && C::BM == C::BN), "paired passes: square tiles, no early exit");
+    // the thread index is made opaque here so that nothing derived from it is
+    // hoisted out of a persistent kernel's item loop (register pressure)
+    int tid_ = threadIdx.x;
+    asm volatile("" : "+v"(tid_));
+    const int tid = tid_, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / C::kWN, wn = wave % C::kWN;
     const uint32_t ga0 = tm * C::GA, gb0 = tn * C::GB;
 
@@ -418,19 +483,106 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     uint8_t* col_l = reinterpret_cast<uint8_t*>(lds + C::kCol);
     uint32_t* rowcnt = reinterpret_cast<uint32_t*>(lds + C::kRow);
     const bool ranks = A.matrix == nullptr;
+    // needle rows with a threshold: the needles, or every slot of a paired set
+    const uint32_t nrows = A.paired ? A.a_groups * kGroup : A.nn;
+
+    // Block (mb, nb) of wave (wm, wn) in `cslot`: the tile's 16 x 16 blocks,
+    // row-block major, each as the 64 lanes hold it (16 bytes per lane), so a
+    // lane reads back exactly what it wrote; as int16, blocks nb and nb + 1
+    // share block nb's 16 bytes.  Buffer accesses: the lane's 16 bytes are
+    // the only per-lane offset, the block's offset is a scalar, and the
+    // resource's size (one slot) bounds every access.
+    static_assert(C::kNBK % 2 == 0, "int16 cross terms pack pairs of blocks");
+    const int cwave = (__builtin_amdgcn_readfirstlane(wm) * C::kMB * (C::kWN * C::kNBK) +
+                       __builtin_amdgcn_readfirstlane(wn) * C::kNBK) * 1024;
+    auto cslot_soff = [&](int mb, int nb) { return cwave + (mb * (C::kWN * C::kNBK) + nb) * 1024; };
+    // the lane's 16-byte offset, computed where it is used (nothing to keep
+    // live, or to spill, across the stage loop)
+    auto cslot_voff = []() {
+        uint32_t v;
+        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0\n\tv_lshlrev_b32 %0, 4, %0"
+                     : "=v"(v));
+        return v;
+    };
+    // (the slot address is workgroup-uniform: scalar registers, so that the
+    // compiler needs no per-lane loop over resource values)
+    // (readfirstlane returns a signed int: each half is taken back as
+    // uint32_t before widening, so bit 31 of the low half is not sign-extended)
+    const uint64_t caddr = reinterpret_cast<uint64_t>(MODE == kModePlain ? nullptr : cslot);
+    const uint32_t c_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(caddr >> 32));
+    const uint32_t c_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)caddr);
+    int32_t* const cslot_u = reinterpret_cast<int32_t*>(((uint64_t)c_hi << 32) | (uint64_t)c_lo);
+    const __amdgpu_buffer_rsrc_t crsrc = __builtin_amdgcn_make_buffer_rsrc(cslot_u, 0, C::BM * C::BN * 4, kBufferWord3);
+    v4i acc[C::kMB][C::kNBK];
+    bool c16 = false;   // store pass: the wave's cross term fits int16
+
     int flags = 0;
     constexpr int kPro = C::BM > C::BN ? C::BM : C::BN;
-    for (int j = tid; j < kPro; j += C::kThreads) {
-        // both loads before either value is used
-        const uint32_t m = j < C::BN ? A.hmax[gb0 * 16 + j] : kPad;
-        const uint32_t row = ga0 * 16 + j;
-        const int32_t t = (ranks && j < C::BM && row < A.nn) ? A.thr[row] : INT_MIN;
-        if (j < C::BN) {
-            flags |= (m > kSmallD && m <= kSlow) ? 1 : 0;
-            flags |= (m <= kSlow) ? 2 : 0;
-            col_l[j] = m <= kSlow ? 1 : 0;               // padding and |D| > 127 excluded
+    if constexpr (MODE == kModeMirror) {
+        static_assert(kPro <= C::kThreads, "one prologue load per thread");
+        // rows (tile tm) are haystack images: usable flags; columns (tile tn)
+        // are needles: thresholds and counts.  The cross term of the store
+        // pass is requested between the prologue's loads and their use, so
+        // its latency overlaps the prologue and the ring's first stages.
+        uint32_t m = kPad;
+        int32_t t = INT_MIN;
+        if (tid < kPro) {
+            m = A.hmax[ga0 * 16 + tid];
+            t = A.thr[gb0 * 16 + tid];
         }
-        if (j < C::BM) { thr_l[j] = t; rowcnt[j] = 0u; }
+        // this workgroup's own stores of the previous pass (same lanes, same
+        // addresses), retired at its end.  The loads are device-scope (cache
+        // policy sc1): they miss in the CU's vector L1 and read the L2, so no
+        // line of this slot cached by an earlier pair of this workgroup can
+        // be read instead.
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const uint32_t cvo = cslot_voff();
+        if (*cform) {
+#pragma unroll
+            for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; nb += 2) {
+                    const v4i w = __builtin_amdgcn_raw_buffer_load_b128(crsrc, cvo, cslot_soff(mb, nb), kDeviceScope);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        acc[mb][nb][v] = (int32_t)((uint32_t)w[v] << 16) >> 16;   // low half, sign-extended
+                        acc[mb][nb + 1][v] = w[v] >> 16;                           // high half (arithmetic)
+                    }
+                }
+        } else {
+#pragma unroll
+            for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_raw_buffer_load_b128(crsrc, cvo, cslot_soff(mb, nb), kDeviceScope);
+        }
+        if (tid < kPro) {
+            flags |= (m <= kSlow) ? 2 : 0;
+            flags |= (t != INT_MIN) ? 4 : 0;
+            col_l[tid] = m <= kSlow ? 1 : 0;
+            thr_l[tid] = t;
+            rowcnt[tid] = 0u;
+        }
+    }
+    for (int j = tid; j < kPro; j += C::kThreads) {
+        if constexpr (MODE == kModeMirror) {
+            break;
+        } else {
+            // both loads before either value is used
+            const uint32_t m = j < C::BN ? A.hmax[gb0 * 16 + j] : kPad;
+            const uint32_t row = ga0 * 16 + j;
+            const int32_t t = (ranks && j < C::BM && row < nrows) ? A.thr[row] : INT_MIN;
+            if (j < C::BN) {
+                flags |= (m > kSmallD && m <= kSlow) ? 1 : 0;
+                flags |= (m <= kSlow) ? 2 : 0;
+                col_l[j] = m <= kSlow ? 1 : 0;               // padding and |D| > 127 excluded
+            }
+            if (j < C::BM) {
+                flags |= (t != INT_MIN) ? 4 : 0;
+                thr_l[j] = t;
+                rowcnt[j] = 0u;
+            }
+        }
     }
     // workgroup OR of the flags through the early-exit vote words (all of the
     // LDS is the kernel's dynamic block: no static shared array is allocated).
@@ -438,17 +590,19 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // read the flags, so one barrier suffices here.
     {
         volatile uint32_t* red = reinterpret_cast<volatile uint32_t*>(lds + C::kVote);
-        const uint64_t b1 = __ballot(flags & 1), b2 = __ballot(flags & 2);
-        if (lane == 0) red[wave] = (b1 ? 1u : 0u) | (b2 ? 2u : 0u);
+        const uint64_t b1 = __ballot(flags & 1), b2 = __ballot(flags & 2), b4 = __ballot(flags & 4);
+        if (lane == 0) red[wave] = (b1 ? 1u : 0u) | (b2 ? 2u : 0u) | (b4 ? 4u : 0u);
         __syncthreads();
         int all = 0;
 #pragma unroll
         for (int w = 0; w < C::kWaves; ++w) all |= (int)red[w];
         flags = __builtin_amdgcn_readfirstlane(all);   // uniform: scalar control flow below
     }
-    const bool hq = (flags & 1) != 0;
-    if (!(flags & 2)) return;
-    const int nstage = (hq ? 3 : 2) * NB;
+    const bool hq = MODE == kModePlain && (flags & 1) != 0;
+    if (!(flags & 2)) return;                 // no usable haystack image
+    // no needle that can count (the store pass still runs: its mirror needs the cross term)
+    if (ranks && !(flags & 4) && MODE != kModeStore) return;
+    const int nstage = (MODE == kModeMirror ? 1 : hq ? 3 : 2) * NB;
 
     // Stage s = phase s / 64, image row s % 64.  Phase -> planes: needle planes
     // 0 = -D, 1 = mask; haystack planes 0 = D, 1 = r, 2 = q (D^2 = 256 q + r + 128).
@@ -463,8 +617,12 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     constexpr int kJA = C::GA / C::kWaves;             // fragments per wave from the needle planes
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const size_t a_ps = (size_t)A.a_groups * kPlaneGroupBytes, b_ps = (size_t)A.b_groups * kPlaneGroupBytes;
-    const int8_t* a_base = A.a_planes + (size_t)ga0 * kPlaneGroupBytes;
-    const int8_t* b_base = A.b_planes + (size_t)gb0 * kPlaneGroupBytes;
+    // mirrored direction: the row tile's r plane (haystack planes) and the
+    // column tile's mask (needle planes), a single phase
+    const int8_t* a_base = MODE == kModeMirror ? A.b_planes + (size_t)ga0 * kPlaneGroupBytes + b_ps
+                                               : A.a_planes + (size_t)ga0 * kPlaneGroupBytes;
+    const int8_t* b_base = MODE == kModeMirror ? A.a_planes + (size_t)gb0 * kPlaneGroupBytes + a_ps
+                                               : A.b_planes + (size_t)gb0 * kPlaneGroupBytes;
     uint32_t voff[C::kLPW];
 #pragma unroll
     for (int j = 0; j < C::kLPW; ++j) {
@@ -473,21 +631,23 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     }
     // planes of phases 0, 1 (, 2): needles -D, mask; haystack D, r.  With the
     // q phase first (hq): needles mask, -D, mask; haystack q, D, r.
+    const bool mir = MODE == kModeMirror;
     const int8_t* a_p0 = a_base + (hq ? a_ps : 0);
-    const int8_t* a_p1 = a_base + (hq ? 0 : a_ps);
+    const int8_t* a_p1 = a_base + (hq || mir ? 0 : a_ps);
     const int8_t* b_p0 = b_base + (hq ? 2 * b_ps : 0);
-    const int8_t* b_p1 = b_base + (hq ? 0 : b_ps);
-    const int8_t* b_p2 = b_base + b_ps;
+    const int8_t* b_p1 = b_base + (hq || mir ? 0 : b_ps);
+    const int8_t* b_p2 = b_base + (mir ? 0 : b_ps);
     const int last = nstage - 1;
 
     const StageSrc src{a_p0, a_p1, b_p0, b_p1, b_p2};
     auto issue = [&](int slot, int t) { issue_stage<C>(lds, slot, min(t, last), wv, src, voff); };
 
-    v4i acc[C::kMB][C::kNBK];
+    if constexpr (MODE != kModeMirror) {
 #pragma unroll
-    for (int mb = 0; mb < C::kMB; ++mb)
+        for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = v4i{0, 0, 0, 0};
+            for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = v4i{0, 0, 0, 0};
+    }
 
     struct Frags { v4i a[C::kMB]; v4i b[C::kNBK]; };
     auto read_frags = [&](int slot, Frags& F) {
@@ -598,13 +758,68 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
                 for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << sh;
+            if constexpr (MODE == kModeStore) {
+                // end of the cross phase (no q phase here): -2 <D_n, D_h>
+                // for the mirrored pass of this tile, as int16 when every
+                // value of the wave fits (blocks nb and nb + 1 share block
+                // nb's 16 bytes: half the bytes), else as int32
+                if (s + 1 == NB) {
+                    int32_t lo = 0, hi = 0;
+#pragma unroll
+                    for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+                        for (int nb = 0; nb < C::kNBK; ++nb)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                lo = min(lo, acc[mb][nb][v]);
+                                hi = max(hi, acc[mb][nb][v]);
+                            }
+                    c16 = __ballot(lo < -32768 || hi > 32767) == 0;
+                    const uint32_t cvo = cslot_voff();
+                    // Loads and stores share the vector memory counter and
+                    // need not retire in order with respect to each other:
+                    // the ring's in-flight stages land before the stores are
+                    // issued and the stores retire before the next ring wait,
+                    // so that every ring wait counts loads only.
+                    wait_vmcnt<0>();
+                    if (c16) {
+#pragma unroll
+                        for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+                            for (int nb = 0; nb < C::kNBK; nb += 2) {
+                                v4i w;
+#pragma unroll
+                                for (int v = 0; v < 4; ++v)
+                                    w[v] = (int32_t)(((uint32_t)acc[mb][nb][v] & 0xFFFFu) |
+                                                     ((uint32_t)acc[mb][nb + 1][v] << 16));
+                                __builtin_amdgcn_raw_buffer_store_b128(w, crsrc, cvo, cslot_soff(mb, nb), 0);
+                                // a store of more than 8 bytes reads its data
+                                // registers after it issues: two wait states
+                                // before the next pack may rewrite them
+                                __builtin_amdgcn_sched_barrier(0);
+                                asm volatile("s_nop 1");
+                                __builtin_amdgcn_sched_barrier(0);
+                            }
+                    } else {
+#pragma unroll
+                        for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+                            for (int nb = 0; nb < C::kNBK; ++nb)
+                                __builtin_amdgcn_raw_buffer_store_b128(acc[mb][nb], crsrc, cvo, cslot_soff(mb, nb), 0);
+                    }
+                    wait_vmcnt<0>();
+                    if (cform) *cform = c16 ? 1u : 0u;
+                }
+            }
         }
     };
 
     static_assert(C::kNS == 4 && NB % 4 == 0, "the loop below is unrolled for a 4-deep ring");
+    // (mirror pass: the cross-term loads, requested before the prologue, are
+    // older than the ring's and land first: loads retire in order)
     issue(0, 0);
     issue(1, 1);
-    issue(2, 2);                                     // nstage >= 128 > NS
+    issue(2, 2);                                     // nstage >= 64 > NS
     wait_vmcnt<(C::kNS - 2) * C::kLPW>();
     stage_barrier();
     Frags fr0, fr1;
@@ -625,11 +840,50 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             }
         }
     }
-    wait_vmcnt<0>();   // the repeated loads of the last steps have landed
+    wait_vmcnt<0>();   // the repeated loads of the last steps (and any cslot stores) have landed
+    if constexpr (MODE == kModeStore) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
 
     // Epilogue.  16x16 accumulator layout: lane l holds column l % 16 and
     // rows 4 * (l / 16) + v of its block, v = 0..3.
     const int cl = lane & 15, rq = lane >> 4;
+    if constexpr (MODE == kModeMirror) {
+        // counts per column (needle): over the lane's 4 rows of each block,
+        // the wave's row blocks, the 4 lanes of the column (l, l ^ 16, l ^ 32,
+        // l ^ 48) and the kWM waves sharing the column (LDS), then one global
+        // atomic per needle
+        static_assert(C::kNBK <= 4 && C::kMB * 16 < 256, "column counts must fit a byte each");
+        uint32_t rowok[C::kMB];
+#pragma unroll
+        for (int mb = 0; mb < C::kMB; ++mb)
+            rowok[mb] = *reinterpret_cast<const uint32_t*>(col_l + (wm * C::kMB + mb) * 16 + 4 * rq);
+        uint32_t packed = 0;
+#pragma unroll
+        for (int nb = 0; nb < C::kNBK; ++nb) {
+            const int32_t t = thr_l[(wn * C::kNBK + nb) * 16 + cl];
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    cnt += (((rowok[mb] >> (8 * v)) & 1u) && acc[mb][nb][v] < t) ? 1u : 0u;
+            packed |= cnt << (8 * nb);
+        }
+        packed += (uint32_t)__shfl_xor((int)packed, 16, 64);
+        packed += (uint32_t)__shfl_xor((int)packed, 32, 64);
+        if (rq == 0) {
+#pragma unroll
+            for (int nb = 0; nb < C::kNBK; ++nb) {
+                const uint32_t cnt = (packed >> (8 * nb)) & 0xFFu;
+                if (cnt) atomicAdd(rowcnt + (wn * C::kNBK + nb) * 16 + cl, cnt);
+            }
+        }
+        __syncthreads();
+        for (int j = tid; j < C::BN; j += C::kThreads) {
+            const uint32_t c = rowcnt[j];
+            if (c) atomicAdd(A.rank + A.nperm[gb0 * 16 + (uint32_t)j], c);
+        }
+        return;
+    }
     bool colok[C::kNBK];
     uint32_t col[C::kNBK];
 #pragma unroll
@@ -664,7 +918,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
                 for (int v = 0; v < 4; ++v) {
                     const uint32_t cnt = (packed >> (8 * v)) & 0xFFu;
                     const int lrow = (wm * C::kMB + mb) * 16 + 4 * rq + v;   // row within the tile
-                    if (cnt && ga0 * 16 + (uint32_t)lrow < A.nn) atomicAdd(rowcnt + lrow, cnt);
+                    if (cnt && ga0 * 16 + (uint32_t)lrow < nrows) atomicAdd(rowcnt + lrow, cnt);
                 }
             }
         }
@@ -687,8 +941,117 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         __syncthreads();
         for (int j = tid; j < C::BM; j += C::kThreads) {
             const uint32_t c = rowcnt[j], row = ga0 * 16 + (uint32_t)j;
-            if (c && row < A.nn) atomicAdd(A.rank + row, c);
+            if (c && row < nrows) atomicAdd(A.rank + (A.nperm ? A.nperm[row] : row), c);
         }
+    }
+}
+
+// Paired sets: work item k of a T x T tile grid is the tile pair (I, J),
+// I <= J.  Items come in bands of 4 consecutive I (measured best of 2, 4, 8,
+// 16); within a band J-major, so the items running at the same time share
+// their I tiles and a few J tiles.
+__device__ __forceinline__ void pair_coords(uint32_t k, uint32_t T, uint32_t& I, uint32_t& J)
+{
+    constexpr uint32_t BW = 4;
+    uint32_t b0 = 0;
+    while (b0 < T) {
+        const uint32_t bw = min(BW, T - b0);
+        const uint32_t tri = bw * (bw + 1) / 2;           // J inside the band
+        const uint32_t nb = tri + (T - b0 - bw) * bw;     // + J beyond it
+        if (k < nb) {
+            if (k < tri) {
+                uint32_t a = 0;
+                while ((a + 1) * (a + 2) / 2 <= k) ++a;
+                J = b0 + a;
+                I = b0 + (k - a * (a + 1) / 2);
+            } else {
+                const uint32_t r = k - tri;
+                J = b0 + bw + r / bw;
+                I = b0 + r % bw;
+            }
+            return;
+        }
+        k -= nb;
+        b0 += bw;
+    }
+    I = J = 0;   // k beyond the T (T + 1) / 2 items: not reached
+}
+
+__host__ __device__ __forceinline__ uint32_t pair_items(uint32_t T) { return T * (T + 1) / 2; }
+
+// Both directions of tile pair (I, J) of a paired set.  A pair whose images
+// all have |D| <= 15 computes the cross term once (store pass (I, J), then
+// its mirror); a pair with a q phase on either side runs (I, J) and (J, I) as
+// plain tiles.  cslot: this workgroup's BM x BN int32 slot.
+template <class C>
+__device__ void search_pair(const SearchArgs& A, uint32_t I, uint32_t J, int8_t* lds, int32_t* cslot)
+{
+    if (I == J) {
+        search_tile<C, false, kModePlain>(A, I, I, lds);
+        return;
+    }
+    const uint32_t fi = A.tile_flags[I], fj = A.tile_flags[J];
+    if (!(fi & 1u) || !(fj & 1u)) return;   // one side has no usable image: neither direction counts
+    if ((fi | fj) & 2u) {
+        search_tile<C, false, kModePlain>(A, I, J, lds);
+        __syncthreads();
+        search_tile<C, false, kModePlain>(A, J, I, lds);
+        return;
+    }
+    uint32_t cform = 0;
+    search_tile<C, false, kModeStore>(A, I, J, lds, cslot, &cform);
+    __syncthreads();
+    search_tile<C, false, kModeMirror>(A, I, J, lds, cslot, &cform);
+}
+
+// Next work item of a persistent search kernel: items [0, total) are split
+// into 8 contiguous ranges, one per XCD (workgroup ids are dealt to the XCDs
+// round robin, so the items that run at the same time on one XCD are
+// neighbours and share fragments in its L2); a workgroup takes items from its
+// own XCD's counter, then from the others' once its range is used up.  The
+// item is broadcast through the first LDS word; returns total when done.
+__device__ __forceinline__ uint32_t next_item(uint32_t* __restrict__ counters, uint32_t total, uint32_t& visited,
+                                              int8_t* lds)
+{
+    volatile uint32_t* s_item = reinterpret_cast<volatile uint32_t*>(lds);
+    const uint32_t xcd = blockIdx.x & 7u, per = (total + 7) / 8;
+    if (threadIdx.x == 0) {
+        uint32_t item = total;
+        while (visited < 8) {
+            const uint32_t x = (xcd + visited) & 7u;
+            const uint32_t k = atomicAdd(counters + x, 1u);
+            if (k < per && x * per + k < total) {
+                item = x * per + k;
+                break;
+            }
+            ++visited;
+        }
+        *s_item = item;
+    }
+    __syncthreads();
+    // the item is the same in every lane: keep it in a scalar register
+    const uint32_t item = __builtin_amdgcn_readfirstlane(*s_item);
+    __syncthreads();
+    return item;
+}
+
+// Persistent search over the tile pairs of one paired set (one workgroup per
+// CU; each owns a BM x BN int32 slot of A.cross).
+template <class C>
+__global__ void __launch_bounds__(C::kThreads)
+k_search_paired(SearchArgs A, uint32_t* __restrict__ counters)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    const uint32_t total = pair_items(A.tiles_m);
+    int32_t* cslot = A.cross + (size_t)blockIdx.x * C::BM * C::BN;
+    uint32_t visited = 0;   // ranges used up (thread 0 only)
+    for (;;) {
+        const uint32_t item = next_item(counters, total, visited, lds);
+        if (item >= total) break;
+        uint32_t I, J;
+        pair_coords(item, A.tiles_m, I, J);
+        search_pair<C>(A, I, J, lds, cslot);
+        __syncthreads();   // every wave is done with the ring before its first word is reused
     }
 }
 
@@ -720,39 +1083,32 @@ k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t to
 {
     extern __shared__ __align__(16) int8_t lds[];
     // the ring takes all of the LDS: the item is broadcast through its first
-    // word, which no wave reads or fills between two tiles
-    volatile uint32_t* s_item = reinterpret_cast<volatile uint32_t*>(lds);
-    const uint32_t xcd = blockIdx.x & 7u, per = (total + 7) / 8;
+    // word, which no wave reads or fills between two items
     uint32_t visited = 0;   // ranges used up (thread 0 only)
     for (;;) {
-        if (threadIdx.x == 0) {
-            uint32_t item = total;
-            while (visited < 8) {
-                const uint32_t x = (xcd + visited) & 7u;
-                const uint32_t k = atomicAdd(counters + x, 1u);
-                if (k < per && x * per + k < total) {
-                    item = x * per + k;
-                    break;
-                }
-                ++visited;
-            }
-            *s_item = item;
-        }
-        __syncthreads();
-        // the item is the same in every lane: keep it (and the job's
-        // arguments loaded through it) in scalar registers
-        const uint32_t item = __builtin_amdgcn_readfirstlane(*s_item);
-        __syncthreads();
+        const uint32_t item = next_item(counters, total, visited, lds);
         if (item >= total) break;
+        // the job's arguments, loaded through the uniform item, stay scalar
         uint32_t lo = 0, hi = njobs - 1;
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) / 2;
             if (jobs[mid].tile_start <= item) lo = mid; else hi = mid - 1;
         }
         const SearchArgs A = jobs[lo].A;
-        uint32_t tm, tn;
-        tile_coords(item - jobs[lo].tile_start, A.tiles_m, A.tiles_n, tm, tn);
-        search_tile<C, EXIT>(A, tm, tn, lds);
+        bool done = false;
+        if constexpr (!EXIT && C::BM == C::BN) {
+            if (A.paired) {
+                uint32_t I, J;
+                pair_coords(item - jobs[lo].tile_start, A.tiles_m, I, J);
+                search_pair<C>(A, I, J, lds, A.cross + (size_t)blockIdx.x * C::BM * C::BN);
+                done = true;
+            }
+        }
+        if (!done) {
+            uint32_t tm, tn;
+            tile_coords(item - jobs[lo].tile_start, A.tiles_m, A.tiles_n, tm, tn);
+            search_tile<C, EXIT>(A, tm, tn, lds);
+        }
         __syncthreads();   // every wave is done with the ring before its first word is reused
     }
 }
@@ -875,12 +1231,14 @@ __device__ __forceinline__ uint32_t job_of(const SearchJob* __restrict__ jobs, u
     return lo;
 }
 
+// needle planes: in image order, or in the haystack's slot order for a paired
+// set (after the slot assignment)
 __global__ void __launch_bounds__(kDeltaWaves * 64)
 k_needle_prep_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
 {
     const SearchJob& J = jobs[job_of<0>(jobs, njobs, blockIdx.x)];
-    delta_group(J.needles, J.A.nn, 1, J.np.planes, J.np.ngroups, J.np.sumsq, J.np.maxabs, nullptr,
-                (uint32_t)(blockIdx.x - J.ngrp_start));
+    delta_group(J.needles, J.A.nn, 1, J.np.planes, J.np.ngroups, J.np.sumsq, J.np.maxabs,
+                J.A.paired ? J.hp.perm : nullptr, (uint32_t)(blockIdx.x - J.ngrp_start));
 }
 
 __global__ void __launch_bounds__(256)
@@ -892,6 +1250,18 @@ k_hay_init_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint64_t 
     const uint64_t s = x - J.hslot_start;
     J.hp.perm[s] = kPad;
     J.hp.maxabs[s] = kPad;
+    if (J.A.paired) const_cast<int32_t*>(J.A.thr)[s] = INT_MIN;   // thresholds per slot
+}
+
+// paired sets: flags of every 256-slot tile (flattened over the jobs)
+__global__ void __launch_bounds__(256)
+k_tile_flags_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint64_t total)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= total) return;
+    const SearchJob& J = jobs[job_of<3>(jobs, njobs, t * (Cfg::BN / kGroup))];
+    tile_flags_one(J.hp.maxabs, const_cast<uint32_t*>(J.A.tile_flags),
+                   (uint32_t)(t - J.hgrp_start / (Cfg::BN / kGroup)), threadIdx.x & 63);
 }
 
 __global__ void __launch_bounds__(256)
@@ -901,7 +1271,7 @@ k_hay_stats_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint64_t
     if (x >= total) return;
     const SearchJob& J = jobs[job_of<2>(jobs, njobs, x)];
     const uint32_t img = (uint32_t)(x - J.himg_start);
-    if (J.hay == J.needles) {
+    if (J.hay == J.needles && !J.A.paired) {
         // ranking a set against itself: the needle pass already found max |D|
         if ((threadIdx.x & 63) == 0) J.hp.maxabs_img[img] = J.np.maxabs[img];
     } else {
@@ -913,7 +1283,7 @@ __global__ void __launch_bounds__(1024)
 k_hay_assign_batched(const SearchJob* __restrict__ jobs)
 {
     const SearchJob& J = jobs[blockIdx.x];
-    hay_assign_block(J.hp.maxabs_img, J.A.nh, J.hp.ngroups * kGroup, J.hp.perm, J.hp.maxabs);
+    hay_assign_block(J.hp.maxabs_img, J.A.nh, J.hp.ngroups * kGroup, J.hp.perm, J.hp.maxabs, J.hp.inv);
 }
 
 __global__ void __launch_bounds__(kDeltaWaves * 64)
@@ -931,7 +1301,8 @@ k_true_distance_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint
     if (x >= total) return;
     const SearchJob& J = jobs[job_of<4>(jobs, njobs, x)];
     true_distance_one(J.needles, J.hay, J.A.nh, J.true_idx, J.np.sumsq, J.np.maxabs, J.dstar,
-                      const_cast<int32_t*>(J.A.thr), J.A.rank, (uint32_t)(x - J.needle_start), threadIdx.x & 63);
+                      const_cast<int32_t*>(J.A.thr), J.A.rank, J.A.paired ? J.hp.inv : nullptr,
+                      (uint32_t)(x - J.needle_start), threadIdx.x & 63);
 }
 
 __global__ void __launch_bounds__(1024)
@@ -983,7 +1354,8 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
     if (p.ngroups == 0) return hipSuccess;
     if (p.perm) {
         const uint32_t nslots = p.ngroups * kGroup;
-        hipLaunchKernelGGL(k_hay_init, dim3((nslots + 255) / 256), dim3(256), 0, s, p.perm, p.maxabs, nslots);
+        hipLaunchKernelGGL(k_hay_init, dim3((nslots + 255) / 256), dim3(256), 0, s, p.perm, p.maxabs,
+                           (int32_t*)nullptr, nslots);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (n > 0) {
@@ -993,7 +1365,8 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
                 hipLaunchKernelGGL(k_hay_stats, dim3((n + 3) / 4), dim3(256), 0, s, images, n, p.maxabs_img);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_hay_assign, dim3(1), dim3(1024), 0, s, p.maxabs_img, n, nslots, p.perm, p.maxabs);
+            hipLaunchKernelGGL(k_hay_assign, dim3(1), dim3(1024), 0, s, p.maxabs_img, n, nslots, p.perm, p.maxabs,
+                               (uint32_t*)nullptr);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -1006,20 +1379,63 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
 
 hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint32_t* hay, uint32_t nh,
                                 const uint32_t* true_idx, const int64_t* sumsq, const uint32_t* nmax,
-                                int64_t* dstar, int32_t* thr, uint32_t* rank, hipStream_t s)
+                                int64_t* dstar, int32_t* thr, uint32_t* rank, hipStream_t s, const uint32_t* inv)
 {
     if (nn == 0) return hipSuccess;
     hipLaunchKernelGGL(k_true_distance, dim3((nn + 3) / 4), dim3(256), 0, s, needles, nn, hay, nh, true_idx, sumsq,
-                       nmax, dstar, thr, rank);
+                       nmax, dstar, thr, rank, inv);
     return hipGetLastError();
 }
+
+hipError_t launch_paired_prep(const uint32_t* images, uint32_t n, const SearchPrep& np, const SearchPrep& hp,
+                              int32_t* thr_slots, uint32_t* tile_flags, hipStream_t s)
+{
+    const uint32_t nslots = hp.ngroups * kGroup;
+    if (n == 0 || nslots == 0 || np.ngroups != hp.ngroups) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_hay_init, dim3((nslots + 255) / 256), dim3(256), 0, s, hp.perm, hp.maxabs, thr_slots, nslots);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hay_stats, dim3((n + 3) / 4), dim3(256), 0, s, images, n, hp.maxabs_img);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hay_assign, dim3(1), dim3(1024), 0, s, hp.maxabs_img, n, nslots, hp.perm, hp.maxabs, hp.inv);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // needle planes (-D, mask) and haystack planes (D, r, q), both in slot order
+    hipLaunchKernelGGL(k_delta_prep, dim3(np.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, 1, np.planes,
+                       np.ngroups, np.sumsq, np.maxabs, (const uint32_t*)hp.perm);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_delta_prep, dim3(hp.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, 0, hp.planes,
+                       hp.ngroups, (int64_t*)nullptr, hp.maxabs, (const uint32_t*)hp.perm);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint32_t tiles = nslots / Cfg::BN;
+    hipLaunchKernelGGL(k_tile_flags, dim3((tiles + 3) / 4), dim3(256), 0, s, hp.maxabs, tiles, tile_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_search_paired(const SearchArgs& A, uint32_t grid, uint32_t* counters, hipStream_t s)
+{
+    if (!A.paired || A.tiles_m == 0) return hipSuccess;
+    hipError_t e = prepare_search_kernels();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_counters8, dim3(1), dim3(64), 0, s, counters);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_search_paired<Cfg>), dim3(grid), dim3(Cfg::kThreads), (size_t)Cfg::kLds, s, A, counters);
+    return hipGetLastError();
+}
+
+uint32_t paired_items(uint32_t tiles) { return pair_items(tiles); }
+size_t paired_slot_bytes() { return (size_t)Cfg::BM * Cfg::BN * sizeof(int32_t); }
 
 template <class C>
 static hipError_t launch_search_t(const SearchPrep& np, uint32_t nn, const SearchPrep& hp, uint32_t nh,
                                   const int32_t* thr, const int64_t* sumsq, uint32_t* rank, int64_t* matrix,
                                   int early_exit, hipStream_t s)
 {
-    SearchArgs A;
+    SearchArgs A = {};
     A.early_exit = early_exit ? 1u : 0u;
     A.a_planes = np.planes; A.a_groups = np.ngroups; A.nn = nn;
     A.b_planes = hp.planes; A.b_groups = hp.ngroups; A.nh = nh;
@@ -1066,7 +1482,7 @@ hipError_t launch_fallback(const uint32_t* needles, uint32_t nn, const uint32_t*
 }
 
 hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const SearchTotals& T, uint32_t* counter,
-                                 uint32_t grid, int variant, int early_exit, hipStream_t s, int part)
+                                 uint32_t grid, int variant, int early_exit, hipStream_t s, int part, int paired)
 {
     if (njobs == 0) return hipSuccess;
 #define RICI_LAUNCH(...)                                   \
@@ -1075,7 +1491,28 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
         hipError_t e_ = hipGetLastError();                 \
         if (e_ != hipSuccess) return e_;                   \
     } while (0)
-    if (part == 0 || part == 1) {
+    if ((part == 0 || part == 1) && paired) {
+        // paired sets: statistics, slot assignment, then both plane sets in
+        // slot order, tile flags and the true-match distances
+        if (T.hay_slots)
+            RICI_LAUNCH(k_hay_init_batched, dim3((uint32_t)((T.hay_slots + 255) / 256)), dim3(256), 0, s, jobs, njobs,
+                        T.hay_slots);
+        if (T.hay_images)
+            RICI_LAUNCH(k_hay_stats_batched, dim3((uint32_t)((T.hay_images + 3) / 4)), dim3(256), 0, s, jobs, njobs,
+                        T.hay_images);
+        RICI_LAUNCH(k_hay_assign_batched, dim3(njobs), dim3(1024), 0, s, jobs);
+        if (T.needle_groups)
+            RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
+        if (T.hay_groups) {
+            RICI_LAUNCH(k_hay_prep_batched, dim3((uint32_t)T.hay_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
+            const uint64_t tiles = T.hay_groups / (Cfg::BN / kGroup);
+            RICI_LAUNCH(k_tile_flags_batched, dim3((uint32_t)((tiles + 3) / 4)), dim3(256), 0, s, jobs, njobs, tiles);
+        }
+        if (T.needles)
+            RICI_LAUNCH(k_true_distance_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
+                        T.needles);
+        RICI_LAUNCH(k_zero_counters8, dim3(1), dim3(64), 0, s, counter);
+    } else if (part == 0 || part == 1) {
         if (T.needle_groups)
             RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
         if (T.hay_slots)
@@ -1142,8 +1579,14 @@ static hipError_t raise_lds()
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_batched<C, EXIT>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_scan<C, EXIT>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_scan<C, EXIT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if constexpr (!EXIT && C::BM == C::BN) {
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search_paired<C>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    }
+    return e;
 }
 
 hipError_t prepare_search_kernels()
