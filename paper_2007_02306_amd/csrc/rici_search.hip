@@ -46,9 +46,13 @@ constexpr int kDeltaWaves = 8;   // wavefronts per delta-prep workgroup (rows sp
 
 // One block per group of 16 images; thread (row-in-step, lane) with
 // lane = 16 * q + i writes columns 16 q .. 16 q + 15 of image i.
+// needle_side: 1 needle planes (-D, mask) into `planes`; 0 haystack planes
+// (D, r, q) into `planes`; 2 both, needle planes into `planes` and haystack
+// planes into `hplanes` (a set ranked against itself, in slot order).
 __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
                             int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
-                            uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm, uint32_t grp)
+                            uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm, uint32_t grp,
+                            int8_t* __restrict__ hplanes = nullptr)
 {
     __shared__ uint32_t smax[kDeltaWaves][kGroup];
     __shared__ int64_t ssum[kDeltaWaves][kGroup];
@@ -86,34 +90,35 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
 #pragma unroll
             for (int k = 0; k < 16; ++k) d[k] = 0;
         }
-        // pack into the fragment-major planes
+        // pack into the fragment-major planes: needle -D and mask, haystack
+        // D, r = (D^2 mod 256) - 128 and q = D^2 div 256 (int8 bytes)
         const size_t frag = ((size_t)grp * NB + r) * kFragBytes + (size_t)lane * 16;
-        uint32_t w0[4], w1[4], w2[4];
+        uint32_t nd[4], nm[4], hd[4], hr[4], hq[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            uint32_t a0 = 0, a1 = 0, a2 = 0;
+            uint32_t a0 = 0, a1 = 0, b0 = 0, b1 = 0, b2 = 0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int32_t x = d[4 * k + b];
                 const uint32_t sq = (uint32_t)(x * x);
-                uint32_t p0, p1, p2;
-                if (needle_side) {
-                    p0 = (uint32_t)(uint8_t)(int8_t)(-x);
-                    p1 = x != 0 ? 1u : 0u;
-                    p2 = 0u;
-                } else {
-                    p0 = (uint32_t)(uint8_t)(int8_t)x;
-                    p1 = (sq & 255u) ^ 0x80u;   // (D^2 mod 256) - 128 as an int8 byte
-                    p2 = sq >> 8;
-                }
-                a0 |= p0 << (8 * b); a1 |= p1 << (8 * b); a2 |= p2 << (8 * b);
+                a0 |= (uint32_t)(uint8_t)(int8_t)(-x) << (8 * b);
+                a1 |= (x != 0 ? 1u : 0u) << (8 * b);
+                b0 |= (uint32_t)(uint8_t)(int8_t)x << (8 * b);
+                b1 |= ((sq & 255u) ^ 0x80u) << (8 * b);
+                b2 |= (sq >> 8) << (8 * b);
             }
-            w0[k] = a0; w1[k] = a1; w2[k] = a2;
+            nd[k] = a0; nm[k] = a1; hd[k] = b0; hr[k] = b1; hq[k] = b2;
         }
-        *reinterpret_cast<uint4*>(planes + frag) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
-        *reinterpret_cast<uint4*>(planes + plane_stride + frag) = make_uint4(w1[0], w1[1], w1[2], w1[3]);
-        if (!needle_side)
-            *reinterpret_cast<uint4*>(planes + 2 * plane_stride + frag) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
+        if (needle_side) {
+            *reinterpret_cast<uint4*>(planes + frag) = make_uint4(nd[0], nd[1], nd[2], nd[3]);
+            *reinterpret_cast<uint4*>(planes + plane_stride + frag) = make_uint4(nm[0], nm[1], nm[2], nm[3]);
+        }
+        if (needle_side != 1) {
+            int8_t* hp = needle_side == 2 ? hplanes : planes;
+            *reinterpret_cast<uint4*>(hp + frag) = make_uint4(hd[0], hd[1], hd[2], hd[3]);
+            *reinterpret_cast<uint4*>(hp + plane_stride + frag) = make_uint4(hr[0], hr[1], hr[2], hr[3]);
+            *reinterpret_cast<uint4*>(hp + 2 * plane_stride + frag) = make_uint4(hq[0], hq[1], hq[2], hq[3]);
+        }
     }
     if (perm && !needle_side) return;   // the haystack's statistics come from k_hay_stats
     // per-image reductions: 4 lanes (q) per wave and kDeltaWaves waves share image i
@@ -146,9 +151,9 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
 __global__ void __launch_bounds__(kDeltaWaves * 64)
 k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
              int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
-             uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm)
+             uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm, int8_t* __restrict__ hplanes)
 {
-    delta_group(images, n, needle_side, planes, ngroups, sumsq, maxabs, perm, blockIdx.x);
+    delta_group(images, n, needle_side, planes, ngroups, sumsq, maxabs, perm, blockIdx.x, hplanes);
 }
 
 // Haystack slot assignment.  k_hay_init marks every slot as padding;
@@ -1231,14 +1236,14 @@ __device__ __forceinline__ uint32_t job_of(const SearchJob* __restrict__ jobs, u
     return lo;
 }
 
-// needle planes: in image order, or in the haystack's slot order for a paired
-// set (after the slot assignment)
+// needle planes in image order; for a paired set (after the slot assignment)
+// both plane sets in the haystack's slot order
 __global__ void __launch_bounds__(kDeltaWaves * 64)
 k_needle_prep_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
 {
     const SearchJob& J = jobs[job_of<0>(jobs, njobs, blockIdx.x)];
-    delta_group(J.needles, J.A.nn, 1, J.np.planes, J.np.ngroups, J.np.sumsq, J.np.maxabs,
-                J.A.paired ? J.hp.perm : nullptr, (uint32_t)(blockIdx.x - J.ngrp_start));
+    delta_group(J.needles, J.A.nn, J.A.paired ? 2 : 1, J.np.planes, J.np.ngroups, J.np.sumsq, J.np.maxabs,
+                J.A.paired ? J.hp.perm : nullptr, (uint32_t)(blockIdx.x - J.ngrp_start), J.hp.planes);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1372,8 +1377,7 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
         }
     }
     hipLaunchKernelGGL(k_delta_prep, dim3(p.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, needle_side, p.planes,
-                       p.ngroups,
-                       p.sumsq, p.maxabs, p.perm);
+                       p.ngroups, p.sumsq, p.maxabs, p.perm, (int8_t*)nullptr);
     return hipGetLastError();
 }
 
@@ -1401,13 +1405,10 @@ hipError_t launch_paired_prep(const uint32_t* images, uint32_t n, const SearchPr
     hipLaunchKernelGGL(k_hay_assign, dim3(1), dim3(1024), 0, s, hp.maxabs_img, n, nslots, hp.perm, hp.maxabs, hp.inv);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // needle planes (-D, mask) and haystack planes (D, r, q), both in slot order
-    hipLaunchKernelGGL(k_delta_prep, dim3(np.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, 1, np.planes,
-                       np.ngroups, np.sumsq, np.maxabs, (const uint32_t*)hp.perm);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_delta_prep, dim3(hp.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, 0, hp.planes,
-                       hp.ngroups, (int64_t*)nullptr, hp.maxabs, (const uint32_t*)hp.perm);
+    // needle planes (-D, mask) and haystack planes (D, r, q), both in slot
+    // order, from one read of each image
+    hipLaunchKernelGGL(k_delta_prep, dim3(np.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, 2, np.planes,
+                       np.ngroups, np.sumsq, np.maxabs, (const uint32_t*)hp.perm, hp.planes);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const uint32_t tiles = nslots / Cfg::BN;
@@ -1501,10 +1502,9 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
             RICI_LAUNCH(k_hay_stats_batched, dim3((uint32_t)((T.hay_images + 3) / 4)), dim3(256), 0, s, jobs, njobs,
                         T.hay_images);
         RICI_LAUNCH(k_hay_assign_batched, dim3(njobs), dim3(1024), 0, s, jobs);
-        if (T.needle_groups)
+        if (T.needle_groups)   // == T.hay_groups: both plane sets in one pass
             RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
         if (T.hay_groups) {
-            RICI_LAUNCH(k_hay_prep_batched, dim3((uint32_t)T.hay_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
             const uint64_t tiles = T.hay_groups / (Cfg::BN / kGroup);
             RICI_LAUNCH(k_tile_flags_batched, dim3((uint32_t)((tiles + 3) / 4)), dim3(256), 0, s, jobs, njobs, tiles);
         }
