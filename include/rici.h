@@ -136,8 +136,11 @@ int rici_generate_noalloc(rici_handle h,
  *   out_rank      [num_needles] uint32.
  *   out_true_distance  [num_needles] int64 CRD(n_i, h_true[i]), or NULL.
  * Exact integer arithmetic: int8 x int8 -> int32 MFMA contractions when the
- * column deltas fit (|D| <= 127 for every image, |D_h| <= 11 for the two-plane
- * form), exact int64 VALU arithmetic for any image outside that range.
+ * column deltas fit (|D| <= 127 for every image; two contraction phases when
+ * every haystack image of a tile has |D| <= 15, three otherwise), exact int64
+ * VALU arithmetic for any image outside that range.  When needles and
+ * haystack are the same array with the same count, the search runs over
+ * pairs of tiles that share the cross term (tuning key "search_pairs").
  */
 int rici_distance_rank(rici_handle h,
                        const uint32_t* needles, uint32_t num_needles,
@@ -337,11 +340,21 @@ int rici_timing_get(rici_handle h, const char* kernel, double* total_ms, uint64_
  *                    rici_batch_create (per mesh, fixed into the plan).
  *   "search_early_exit"  0 (default) or 1: in rank mode a search tile stops
  *                    once every partial distance of its last contraction phase
- *                    (where partial sums only grow) has reached its needle's
- *                    threshold, so the tile can add to no rank.  Ranks are
- *                    unchanged; it saves work when true matches are close
- *                    (clutter, serving).  Read by rici_distance_rank,
- *                    rici_batch_create and rici_query_create.
+ *                    exceeds its needle's threshold by more than it can still
+ *                    fall (at most 128 x 63 per remaining image row), so the
+ *                    tile can add to no rank.  Ranks are unchanged; it saves
+ *                    work when true matches are close (clutter, serving).
+ *                    Read by rici_distance_rank, rici_batch_create and
+ *                    rici_query_create.
+ *   "search_pairs"   1 (default) or 0: a set ranked against itself (the same
+ *                    array and count as needles and haystack, and every mesh
+ *                    of a batched plan) is searched by pairs of tiles that
+ *                    serve both directions and compute the cross term
+ *                    <D_a, D_b> of Eq. 7 once for both (about a quarter fewer
+ *                    contraction operations).  Taken only with 256-needle
+ *                    tiles and without the early exit.  Read by
+ *                    rici_distance_rank and rici_batch_create (fixed into the
+ *                    plan).
  *   "search_tile_m"  needles per search workgroup tile: 256 (default) or 128.
  *                    The smaller tile wastes less work on padding when a
  *                    needle set is small or just above a multiple of 256.
