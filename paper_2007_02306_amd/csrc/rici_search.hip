@@ -25,6 +25,7 @@
 #include "rici_internal.h"
 
 #include <limits.h>
+#include <type_traits>
 
 namespace rici {
 namespace {
@@ -368,7 +369,16 @@ struct SearchCfg {
     static constexpr int kThr = kVote + 64;
     static constexpr int kCol = kThr + BM * 4;
     static constexpr int kRow = kCol + ((BN + 15) & ~15);
-    static constexpr int kLds = kRow + BM * 4;
+    // tile pairs of a paired set also count the mirrored direction: the
+    // column tile's thresholds (BN int32), the row tile's usability flags (BM
+    // bytes) and per-column hit counts (BN uint32)
+    static constexpr int kThrC = kRow + BM * 4;
+    static constexpr int kRowOk = kThrC + BN * 4;
+    static constexpr int kColCnt = kRowOk + ((BM + 15) & ~15);
+    // ... and the original image ids of both tiles, for the final atomics
+    static constexpr int kPermR = kColCnt + BN * 4;
+    static constexpr int kPermC = kPermR + BM * 4;
+    static constexpr int kLds = kPermC + BN * 4;
     static_assert(kFrags % kWaves == 0, "fragments must split evenly over the waves");
 };
 
@@ -423,9 +433,43 @@ __device__ __forceinline__ uint32_t row16_prefix_sum(uint32_t x)
     return x;
 }
 
-// Row bases of the planes a tile streams in each phase (phase 2 reads the
-// needle plane of phase 0).
-struct StageSrc { const int8_t *a0, *a1, *b0, *b1, *b2; };
+// Global memory through the global address space: a generic (flat) access
+// also counts in the LDS counter, so that every LDS wait issued after it
+// (a barrier's, for one) would also wait for it.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
+// A workgroup-uniform word through the constant address space (a scalar
+// load): for data that no kernel running at the same time writes
+__device__ __forceinline__ uint32_t ldc(const uint32_t* p)
+{
+    return *(const __attribute__((address_space(4))) uint32_t*)p;
+}
+
+__device__ __forceinline__ void red_add(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) uint32_t*)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// LDS add without a result, in asm: written through the builtin, the
+// compiler waits for every direct-to-LDS load in flight before it (it cannot
+// tell that the ring slots and the count words are disjoint), which would
+// drain the ring where the count runs between two phases.  LDS operations
+// retire in order, so the compiler's own LDS waits stay correct (only
+// stricter) with this one among them; a workgroup barrier with its fence
+// orders it before the counts are read.
+__device__ __forceinline__ void lds_add_u32(uint32_t* p, uint32_t v)
+{
+    const uint32_t a = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t*)p;
+    asm volatile("ds_add_u32 %0, %1" ::"v"(a), "v"(v) : "memory");
+}
+
+// Row bases of the planes a tile streams in each phase.
+struct StageSrc { const int8_t *a0, *a1, *a2, *b0, *b1, *b2; };
 
 // Direct global -> LDS loads of stage t into ring slot `slot`: this wave's
 // kLPW fragments, fragment j being fragment wv + j * kWaves of the stage (the
@@ -439,37 +483,44 @@ __device__ __forceinline__ void issue_stage(int8_t* lds, int slot, int t, int wv
     constexpr int kJA = C::GA / C::kWaves;
     const int p = t / NB;
     const size_t roff = (size_t)(t % NB) * kFragBytes;
-    const int8_t* sa = (p == 1 ? src.a1 : src.a0) + roff;
+    const int8_t* sa = (p == 0 ? src.a0 : (p == 1 ? src.a1 : src.a2)) + roff;
     const int8_t* sb = (p == 0 ? src.b0 : (p == 1 ? src.b1 : src.b2)) + roff;
     int8_t* dst = lds + slot * C::kStage;
 #pragma unroll
     for (int j = 0; j < C::kLPW; ++j) {
-        const int8_t* g = (j < kJA ? sa : sb) + voff[j];
+        // the offset is re-read here (opaque), so that its zero extension is
+        // formed next to the load and the load takes the scalar-base form
+        // (a 32-bit offset register instead of a 64-bit address per fragment)
+        uint32_t o = voff[j];
+        asm volatile("" : "+v"(o));
+        const int8_t* g = (j < kJA ? sa : sb) + o;
         __builtin_amdgcn_global_load_lds(
             (const void __attribute__((address_space(1)))*)g,
             (void __attribute__((address_space(3)))*)(dst + (wv + j * C::kWaves) * (int)kFragBytes), 16, 0, 0);
     }
 }
 
-// Passes over one tile: kModePlain, the whole tile; kModeStore, the same for a
-// tile whose haystack images all have |D| <= 15, also leaving -2 <D_n, D_h> in
-// `cslot` after the cross phase; kModeMirror, the mirrored direction of that
-// tile (paired sets): its rows are then haystack images and its columns
-// needles, the accumulator starts from `cslot` (the cross term is symmetric:
-// <-D_a, D_b> = <-D_b, D_a>) and only the r phase runs, with the row tile's r
-// plane as the first operand and the column tile's mask as the second.
-enum { kModePlain = 0, kModeStore = 1, kModeMirror = 2 };
+// Passes over one tile: kModePlain, the whole tile (rows needles, columns
+// haystack images); kModePair, both directions of the tile pair (I, J) =
+// (tm, tn) of a paired set whose images all have |D| <= 15, in one pass of
+// three phases: the cross term -<D_I, D_J> (the same for both directions),
+// doubled and kept in `cslot`; then <m_I, r_J>, after which the rows (needles
+// of tile I against the haystack images of tile J) are counted; then
+// <r_I, m_J> from zero, to which the kept cross term is added, after which
+// the columns (needles of tile J against the haystack images of tile I) are
+// counted.
+// kModeRank is kModePlain known to be in rank mode (no distance matrix):
+// persistent kernels, which rank only, carry no matrix epilogue.
+enum { kModePlain = 0, kModePair = 1, kModeRank = 2 };
 
-// One BM x BN (needle x haystack) tile: every workgroup thread takes part.
-// EXIT compiles in the early exit of rank mode (taken when A.early_exit is set).
-// cform (store and mirror passes): whether this wave's cross term went to
-// `cslot` as int16 (1) or int32 (0); the store pass sets it and its mirror
-// reads it (a wave-uniform value: each wave reads back only what it wrote).
+// One BM x BN (needle x haystack) tile, or tile pair: every workgroup thread
+// takes part.  EXIT compiles in the early exit of rank mode (taken when
+// A.early_exit is set).  cslot (pair mode): this workgroup's BM x BN int32
+// slot.
 template <class C, bool EXIT, int MODE = kModePlain>
-__device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_t* lds, int32_t* cslot = nullptr,
-                            uint32_t* cform = nullptr)
+__device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_t* lds, int32_t* cslot = nullptr)
 {
-    static_assert(MODE == kModePlain || (!EXIT && C::BM == C::BN), "paired passes: square tiles, no early exit");
+    static_assert(MODE != kModePair || (!EXIT && C::BM == C::BN), "tile pairs: square tiles, no early exit");
     // the thread index is made opaque here so that nothing derived from it is
     // hoisted out of a persistent kernel's item loop (register pressure)
     int tid_ = threadIdx.x;
@@ -487,7 +538,12 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     int32_t* thr_l = reinterpret_cast<int32_t*>(lds + C::kThr);
     uint8_t* col_l = reinterpret_cast<uint8_t*>(lds + C::kCol);
     uint32_t* rowcnt = reinterpret_cast<uint32_t*>(lds + C::kRow);
-    const bool ranks = A.matrix == nullptr;
+    int32_t* thrc_l = reinterpret_cast<int32_t*>(lds + C::kThrC);      // pair: tile J's thresholds
+    uint8_t* rowok_l = reinterpret_cast<uint8_t*>(lds + C::kRowOk);    // pair: tile I's usable flags
+    uint32_t* colcnt = reinterpret_cast<uint32_t*>(lds + C::kColCnt);  // pair: tile J's counts
+    uint32_t* permr_l = reinterpret_cast<uint32_t*>(lds + C::kPermR);  // pair: image ids of tile I
+    uint32_t* permc_l = reinterpret_cast<uint32_t*>(lds + C::kPermC);  // pair: image ids of tile J
+    const bool ranks = MODE != kModePlain || A.matrix == nullptr;
     // needle rows with a threshold: the needles, or every slot of a paired set
     const uint32_t nrows = A.paired ? A.a_groups * kGroup : A.nn;
 
@@ -509,77 +565,63 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
                      : "=v"(v));
         return v;
     };
+    // the lane index, recomputed where it is used (likewise)
+    auto lane_here = []() {
+        int v;
+        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
+        return v;
+    };
     // (the slot address is workgroup-uniform: scalar registers, so that the
     // compiler needs no per-lane loop over resource values)
     // (readfirstlane returns a signed int: each half is taken back as
     // uint32_t before widening, so bit 31 of the low half is not sign-extended)
-    const uint64_t caddr = reinterpret_cast<uint64_t>(MODE == kModePlain ? nullptr : cslot);
+    const uint64_t caddr = reinterpret_cast<uint64_t>(MODE == kModePair ? cslot : nullptr);
     const uint32_t c_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(caddr >> 32));
     const uint32_t c_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)caddr);
     int32_t* const cslot_u = reinterpret_cast<int32_t*>(((uint64_t)c_hi << 32) | (uint64_t)c_lo);
     const __amdgpu_buffer_rsrc_t crsrc = __builtin_amdgcn_make_buffer_rsrc(cslot_u, 0, C::BM * C::BN * 4, kBufferWord3);
     v4i acc[C::kMB][C::kNBK];
-    bool c16 = false;   // store pass: the wave's cross term fits int16
+    bool c16 = false;   // pair mode: the wave's cross term fits int16 (wave-uniform)
 
     int flags = 0;
     constexpr int kPro = C::BM > C::BN ? C::BM : C::BN;
-    if constexpr (MODE == kModeMirror) {
-        static_assert(kPro <= C::kThreads, "one prologue load per thread");
-        // rows (tile tm) are haystack images: usable flags; columns (tile tn)
-        // are needles: thresholds and counts.  The cross term of the store
-        // pass is requested between the prologue's loads and their use, so
-        // its latency overlaps the prologue and the ring's first stages.
-        uint32_t m = kPad;
-        int32_t t = INT_MIN;
-        if (tid < kPro) {
-            m = A.hmax[ga0 * 16 + tid];
-            t = A.thr[gb0 * 16 + tid];
-        }
-        // this workgroup's own stores of the previous pass (same lanes, same
-        // addresses), retired at its end.  The loads are device-scope (cache
-        // policy sc1): they miss in the CU's vector L1 and read the L2, so no
-        // line of this slot cached by an earlier pair of this workgroup can
-        // be read instead.
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const uint32_t cvo = cslot_voff();
-        if (*cform) {
-#pragma unroll
-            for (int mb = 0; mb < C::kMB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < C::kNBK; nb += 2) {
-                    const v4i w = __builtin_amdgcn_raw_buffer_load_b128(crsrc, cvo, cslot_soff(mb, nb), kDeviceScope);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        acc[mb][nb][v] = (int32_t)((uint32_t)w[v] << 16) >> 16;   // low half, sign-extended
-                        acc[mb][nb + 1][v] = w[v] >> 16;                           // high half (arithmetic)
-                    }
-                }
-        } else {
-#pragma unroll
-            for (int mb = 0; mb < C::kMB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < C::kNBK; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_raw_buffer_load_b128(crsrc, cvo, cslot_soff(mb, nb), kDeviceScope);
-        }
-        if (tid < kPro) {
-            flags |= (m <= kSlow) ? 2 : 0;
-            flags |= (t != INT_MIN) ? 4 : 0;
-            col_l[tid] = m <= kSlow ? 1 : 0;
-            thr_l[tid] = t;
-            rowcnt[tid] = 0u;
+    if constexpr (MODE == kModePair) {
+        // Both tiles are needles and haystack images: six loads before any
+        // use (every slot of a paired set has a threshold word).  (Issuing
+        // the ring's first stages between the loads and their uses, to
+        // overlap the two latencies, pushed the stage loops into scratch.)
+        static_assert(C::BM == C::BN && C::BM <= C::kThreads, "one prologue slot per thread");
+        const int j = tid < C::BM ? tid : 0;
+        const uint32_t mi = ldg(A.hmax + ga0 * 16 + j), mj = ldg(A.hmax + gb0 * 16 + j);
+        const int32_t ti = ldg(A.thr + ga0 * 16 + j), tj = ldg(A.thr + gb0 * 16 + j);
+        const uint32_t pi = ldg(A.nperm + ga0 * 16 + j), pj = ldg(A.nperm + gb0 * 16 + j);
+        if (tid < C::BM) {
+            flags |= (mi <= kSlow || mj <= kSlow) ? 2 : 0;
+            flags |= (ti != INT_MIN || tj != INT_MIN) ? 4 : 0;
+            flags |= (mj > kSlow) ? 8 : 0;    // a column (tile J image) is not usable
+            flags |= (mi > kSlow) ? 16 : 0;   // a row (tile I image) is not usable
+            col_l[j] = mj <= kSlow ? 1 : 0;
+            rowok_l[j] = mi <= kSlow ? 1 : 0;
+            thr_l[j] = ti;
+            thrc_l[j] = tj;
+            rowcnt[j] = 0u;
+            colcnt[j] = 0u;
+            permr_l[j] = pi;
+            permc_l[j] = pj;
         }
     }
     for (int j = tid; j < kPro; j += C::kThreads) {
-        if constexpr (MODE == kModeMirror) {
+        if constexpr (MODE == kModePair) {
             break;
         } else {
             // both loads before either value is used
-            const uint32_t m = j < C::BN ? A.hmax[gb0 * 16 + j] : kPad;
+            const uint32_t m = j < C::BN ? ldg(A.hmax + gb0 * 16 + j) : kPad;
             const uint32_t row = ga0 * 16 + j;
-            const int32_t t = (ranks && j < C::BM && row < nrows) ? A.thr[row] : INT_MIN;
+            const int32_t t = (ranks && j < C::BM && row < nrows) ? ldg(A.thr + row) : INT_MIN;
             if (j < C::BN) {
                 flags |= (m > kSmallD && m <= kSlow) ? 1 : 0;
                 flags |= (m <= kSlow) ? 2 : 0;
+                flags |= (m > kSlow) ? 8 : 0;                // a column is not usable
                 col_l[j] = m <= kSlow ? 1 : 0;               // padding and |D| > 127 excluded
             }
             if (j < C::BM) {
@@ -589,26 +631,30 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             }
         }
     }
-    // workgroup OR of the flags through the early-exit vote words (all of the
-    // LDS is the kernel's dynamic block: no static shared array is allocated).
-    // The first vote comes many stage barriers later, after every wave has
-    // read the flags, so one barrier suffices here.
-    {
-        volatile uint32_t* red = reinterpret_cast<volatile uint32_t*>(lds + C::kVote);
-        const uint64_t b1 = __ballot(flags & 1), b2 = __ballot(flags & 2), b4 = __ballot(flags & 4);
-        if (lane == 0) red[wave] = (b1 ? 1u : 0u) | (b2 ? 2u : 0u) | (b4 ? 4u : 0u);
-        __syncthreads();
+    // workgroup OR of the flags through the words after the early-exit vote
+    // words (all of the LDS is the kernel's dynamic block: no static shared
+    // array is allocated); they stay for the epilogue, which reads them again
+    // rather than keep the flags in registers through the stage loop
+    static_assert(C::kWaves <= 8, "16 words hold the votes and the flags");
+    volatile __attribute__((address_space(3))) uint32_t* red =
+        (volatile __attribute__((address_space(3))) uint32_t*)(lds + C::kVote) + 8;
+    auto tile_flags_lds = [&]() {
         int all = 0;
 #pragma unroll
         for (int w = 0; w < C::kWaves; ++w) all |= (int)red[w];
-        flags = __builtin_amdgcn_readfirstlane(all);   // uniform: scalar control flow below
+        return __builtin_amdgcn_readfirstlane(all);   // uniform: scalar control flow
+    };
+    {
+        uint32_t w = 0;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) w |= __ballot(flags & (1 << b)) ? 1u << b : 0u;
+        if (lane == 0) red[wave] = w;
+        __syncthreads();
+        flags = tile_flags_lds();
     }
-    const bool hq = MODE == kModePlain && (flags & 1) != 0;
-    if (!(flags & 2)) return;                 // no usable haystack image
-    // no needle that can count (the store pass still runs: its mirror needs the cross term)
-    if (ranks && !(flags & 4) && MODE != kModeStore) return;
-    const int nstage = (MODE == kModeMirror ? 1 : hq ? 3 : 2) * NB;
-
+    const bool hq = MODE != kModePair && (flags & 1) != 0;
+    // no usable haystack image, or no needle that can count
+    if (!(flags & 2) || (ranks && !(flags & 4))) return;
     // Stage s = phase s / 64, image row s % 64.  Phase -> planes: needle planes
     // 0 = -D, 1 = mask; haystack planes 0 = D, 1 = r, 2 = q (D^2 = 256 q + r + 128).
     // Each wave moves kLPW whole fragments (1 KiB, one instruction each) from
@@ -622,37 +668,41 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     constexpr int kJA = C::GA / C::kWaves;             // fragments per wave from the needle planes
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const size_t a_ps = (size_t)A.a_groups * kPlaneGroupBytes, b_ps = (size_t)A.b_groups * kPlaneGroupBytes;
-    // mirrored direction: the row tile's r plane (haystack planes) and the
-    // column tile's mask (needle planes), a single phase
-    const int8_t* a_base = MODE == kModeMirror ? A.b_planes + (size_t)ga0 * kPlaneGroupBytes + b_ps
-                                               : A.a_planes + (size_t)ga0 * kPlaneGroupBytes;
-    const int8_t* b_base = MODE == kModeMirror ? A.a_planes + (size_t)gb0 * kPlaneGroupBytes + a_ps
-                                               : A.b_planes + (size_t)gb0 * kPlaneGroupBytes;
+    const int8_t* a_base = A.a_planes + (size_t)ga0 * kPlaneGroupBytes;
+    const int8_t* b_base = A.b_planes + (size_t)gb0 * kPlaneGroupBytes;
     uint32_t voff[C::kLPW];
 #pragma unroll
     for (int j = 0; j < C::kLPW; ++j) {
         const int g = wv + j * C::kWaves - (j < kJA ? 0 : C::GA);
         voff[j] = (uint32_t)g * (uint32_t)kPlaneGroupBytes + (uint32_t)lane * 16;
     }
-    // planes of phases 0, 1 (, 2): needles -D, mask; haystack D, r.  With the
-    // q phase first (hq): needles mask, -D, mask; haystack q, D, r.
-    const bool mir = MODE == kModeMirror;
-    const int8_t* a_p0 = a_base + (hq ? a_ps : 0);
-    const int8_t* a_p1 = a_base + (hq || mir ? 0 : a_ps);
-    const int8_t* b_p0 = b_base + (hq ? 2 * b_ps : 0);
-    const int8_t* b_p1 = b_base + (hq || mir ? 0 : b_ps);
-    const int8_t* b_p2 = b_base + (mir ? 0 : b_ps);
-    const int last = nstage - 1;
+    // planes of phases 0, 1: needles -D, mask; haystack D, r.  With the q
+    // phase first (hq): needles mask, -D, mask; haystack q, D, r.  Pair mode:
+    // needles -D, mask of tile I against haystack D, r of tile J, then the r
+    // plane of tile I (haystack planes) against the mask of tile J (needle
+    // planes).
+    auto plane_src = [&](bool hq) {
+        const int8_t* a_p0 = a_base + (hq ? a_ps : 0);
+        const int8_t* a_p1 = a_base + (hq ? 0 : a_ps);
+        const int8_t* a_p2 = MODE == kModePair ? A.b_planes + (size_t)ga0 * kPlaneGroupBytes + b_ps : a_p0;
+        const int8_t* b_p0 = b_base + (hq ? 2 * b_ps : 0);
+        const int8_t* b_p1 = b_base + (hq ? 0 : b_ps);
+        const int8_t* b_p2 = MODE == kModePair ? A.a_planes + (size_t)gb0 * kPlaneGroupBytes + a_ps : b_base + b_ps;
+        return StageSrc{a_p0, a_p1, a_p2, b_p0, b_p1, b_p2};
+    };
 
-    const StageSrc src{a_p0, a_p1, b_p0, b_p1, b_p2};
+    const int nstage = (MODE == kModePair || hq ? 3 : 2) * NB;
+    const int last = nstage - 1;
+    const StageSrc src = plane_src(hq);
     auto issue = [&](int slot, int t) { issue_stage<C>(lds, slot, min(t, last), wv, src, voff); };
 
-    if constexpr (MODE != kModeMirror) {
+    auto zero_acc = [&]() {
 #pragma unroll
         for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = v4i{0, 0, 0, 0};
-    }
+    };
+    zero_acc();
 
     struct Frags { v4i a[C::kMB]; v4i b[C::kNBK]; };
     auto read_frags = [&](int slot, Frags& F) {
@@ -686,7 +736,8 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // (the votes read the tile's thresholds and usable columns from LDS:
     // global loads there would drain the stage loads in flight)
     const bool exit_ok = EXIT && A.early_exit && A.thr && ranks;
-    volatile uint32_t* votes = reinterpret_cast<volatile uint32_t*>(lds + C::kVote);
+    volatile __attribute__((address_space(3))) uint32_t* votes =
+        (volatile __attribute__((address_space(3))) uint32_t*)(lds + C::kVote);
     const int last_phase = nstage - NB;
     auto vote = [&](int32_t slack) {
         bool alive = false;
@@ -712,6 +763,58 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
 #pragma unroll
         for (int w = 0; w < C::kWaves; ++w) any |= votes[w];
         return __builtin_amdgcn_readfirstlane(any) == 0;
+    };
+
+    // Rank epilogue of the rows.  16x16 accumulator layout: lane l holds
+    // column l % 16 and rows 4 * (l / 16) + v of its block, v = 0..3.  Per
+    // lane, the counts of its four rows of block mb (each at most kNBK)
+    // packed one per byte; a DPP prefix sum over the lane's row of 16 lanes
+    // (the lanes holding those rows' 16 columns) leaves the block rows'
+    // counts in lane 15 of it, at most 16 * kNBK < 256 per byte.  The kWN
+    // waves sharing a needle row add them in LDS (zeroed in the prologue);
+    // one global atomic per row of the tile follows at the end.
+    auto count_rows = [&]() {
+        static_assert(16 * C::kNBK < 256, "row counts must fit a byte");
+        // (two copies: without the per-column test when every column is usable)
+        auto body = [&](auto all_usable) {
+            constexpr bool kAll = decltype(all_usable)::value;
+            const int ln = lane_here(), cl = ln & 15, rq = ln >> 4;
+            const int wm = wv / C::kWN, wn = wv % C::kWN;   // scalar
+            bool colok[C::kNBK];
+#pragma unroll
+            for (int nb = 0; nb < C::kNBK; ++nb) colok[nb] = kAll || col_l[(wn * C::kNBK + nb) * 16 + cl] != 0;
+#pragma unroll
+            for (int mb = 0; mb < C::kMB; ++mb) {
+                // the four thresholds of this lane's rows in the block (INT_MIN past the needles)
+                const v4i t4 = *reinterpret_cast<const v4i*>(thr_l + (wm * C::kMB + mb) * 16 + 4 * rq);
+                uint32_t packed = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    uint32_t cnt = 0;
+#pragma unroll
+                    for (int nb = 0; nb < C::kNBK; ++nb)
+                        cnt += ((kAll || colok[nb]) && acc[mb][nb][v] < t4[v]) ? 1u : 0u;
+                    packed |= cnt << (8 * v);
+                }
+                packed = row16_prefix_sum(packed);
+                if (cl == 15) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const uint32_t cnt = (packed >> (8 * v)) & 0xFFu;
+                        const int lrow = (wm * C::kMB + mb) * 16 + 4 * rq + v;   // row within the tile
+                        // (every row of a tile pair is a slot of the set;
+                        // no wait for the ring's loads in flight)
+                        if constexpr (MODE == kModePair) {
+                            lds_add_u32(rowcnt + lrow, cnt);   // (no branch per count)
+                        } else {
+                            if (cnt && ga0 * 16 + (uint32_t)lrow < nrows) atomicAdd(rowcnt + lrow, cnt);
+                        }
+                    }
+                }
+            }
+        };
+        if (!(tile_flags_lds() & 8)) body(std::true_type{});   // every column usable
+        else body(std::false_type{});
     };
 
     auto step = [&](int k, int s, const Frags& cur, Frags& nxt) {   // k = s % NS, a literal
@@ -756,178 +859,211 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             constexpr int kRest = kMfma - 1 - 2 * kReads + (kTight ? 1 : 0);
             if constexpr (kRest > 0) __builtin_amdgcn_sched_group_barrier(0x008, kRest, 0);
         }
-        if (k == C::kNS - 1 && (s + 1) % NB == 0 && s + 1 < nstage) {
-            // end of a phase: scale the partial sum (x128 after q, x2 after -D.D)
-            const int sh = (hq && s + 1 == NB) ? 7 : 1;
+        if constexpr (MODE != kModePair) {
+            if (k == C::kNS - 1 && (s + 1) % NB == 0 && s + 1 < nstage) {
+                // end of a phase: scale the partial sum (x128 after q, x2 after -D.D)
+                const int sh = (hq && s + 1 == NB) ? 7 : 1;
 #pragma unroll
-            for (int mb = 0; mb < C::kMB; ++mb)
+                for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
-                for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << sh;
-            if constexpr (MODE == kModeStore) {
-                // end of the cross phase (no q phase here): -2 <D_n, D_h>
-                // for the mirrored pass of this tile, as int16 when every
-                // value of the wave fits (blocks nb and nb + 1 share block
-                // nb's 16 bytes: half the bytes), else as int32
-                if (s + 1 == NB) {
-                    int32_t lo = 0, hi = 0;
-#pragma unroll
-                    for (int mb = 0; mb < C::kMB; ++mb)
-#pragma unroll
-                        for (int nb = 0; nb < C::kNBK; ++nb)
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                lo = min(lo, acc[mb][nb][v]);
-                                hi = max(hi, acc[mb][nb][v]);
-                            }
-                    c16 = __ballot(lo < -32768 || hi > 32767) == 0;
-                    const uint32_t cvo = cslot_voff();
-                    // Loads and stores share the vector memory counter and
-                    // need not retire in order with respect to each other:
-                    // the ring's in-flight stages land before the stores are
-                    // issued and the stores retire before the next ring wait,
-                    // so that every ring wait counts loads only.
-                    wait_vmcnt<0>();
-                    if (c16) {
-#pragma unroll
-                        for (int mb = 0; mb < C::kMB; ++mb)
-#pragma unroll
-                            for (int nb = 0; nb < C::kNBK; nb += 2) {
-                                v4i w;
-#pragma unroll
-                                for (int v = 0; v < 4; ++v)
-                                    w[v] = (int32_t)(((uint32_t)acc[mb][nb][v] & 0xFFFFu) |
-                                                     ((uint32_t)acc[mb][nb + 1][v] << 16));
-                                __builtin_amdgcn_raw_buffer_store_b128(w, crsrc, cvo, cslot_soff(mb, nb), 0);
-                                // a store of more than 8 bytes reads its data
-                                // registers after it issues: two wait states
-                                // before the next pack may rewrite them
-                                __builtin_amdgcn_sched_barrier(0);
-                                asm volatile("s_nop 1");
-                                __builtin_amdgcn_sched_barrier(0);
-                            }
-                    } else {
-#pragma unroll
-                        for (int mb = 0; mb < C::kMB; ++mb)
-#pragma unroll
-                            for (int nb = 0; nb < C::kNBK; ++nb)
-                                __builtin_amdgcn_raw_buffer_store_b128(acc[mb][nb], crsrc, cvo, cslot_soff(mb, nb), 0);
-                    }
-                    wait_vmcnt<0>();
-                    if (cform) *cform = c16 ? 1u : 0u;
-                }
+                    for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << sh;
             }
         }
     };
 
+    // Pair mode, end of the cross phase: -2 <D_I, D_J> kept for the third
+    // phase, as int16 when every value of the wave fits (blocks nb and nb + 1
+    // share block nb's 16 bytes: half the bytes), else as int32.
+    auto keep_cross = [&]() {
+#pragma unroll
+        for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << 1;
+        int32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < C::kNBK; ++nb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    lo = min(lo, acc[mb][nb][v]);
+                    hi = max(hi, acc[mb][nb][v]);
+                }
+        c16 = __ballot(lo < -32768 || hi > 32767) == 0;
+        const uint32_t cvo = cslot_voff();
+        // Loads and stores share the vector memory counter and need not
+        // retire in order with respect to each other: the stores (and the
+        // ring's stages in flight) retire before the next ring wait, so that
+        // every ring wait counts loads only.
+        if (c16) {
+#pragma unroll
+            for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; nb += 2) {
+                    v4i w;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        w[v] = (int32_t)(((uint32_t)acc[mb][nb][v] & 0xFFFFu) |
+                                         ((uint32_t)acc[mb][nb + 1][v] << 16));
+                    __builtin_amdgcn_raw_buffer_store_b128(w, crsrc, cvo, cslot_soff(mb, nb), 0);
+                    // a store of more than 8 bytes reads its data
+                    // registers after it issues: two wait states
+                    // before the next pack may rewrite them
+                    __builtin_amdgcn_sched_barrier(0);
+                    asm volatile("s_nop 1");
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+        } else {
+#pragma unroll
+            for (int mb = 0; mb < C::kMB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; ++nb)
+                    __builtin_amdgcn_raw_buffer_store_b128(acc[mb][nb], crsrc, cvo, cslot_soff(mb, nb), 0);
+        }
+        wait_vmcnt<0>();
+    };
+
     static_assert(C::kNS == 4 && NB % 4 == 0, "the loop below is unrolled for a 4-deep ring");
-    // (mirror pass: the cross-term loads, requested before the prologue, are
-    // older than the ring's and land first: loads retire in order)
     issue(0, 0);
     issue(1, 1);
-    issue(2, 2);                                     // nstage >= 64 > NS
+    issue(2, 2);
     wait_vmcnt<(C::kNS - 2) * C::kLPW>();
     stage_barrier();
     Frags fr0, fr1;
     read_frags(0, fr0);
-    for (int s = 0; s < nstage; s += 4) {   // nstage is a multiple of 64
-        step(0, s, fr0, fr1);
-        step(1, s + 1, fr1, fr0);
-        step(2, s + 2, fr0, fr1);
-        step(3, s + 3, fr1, fr0);
-        // after 16, 32 and 48 rows of the last phase: vote, publish, decide
-        if (exit_ok && s + 4 > last_phase && (s + 4 - last_phase) % 16 == 0 && s + 4 < nstage) {
-            vote(128 * 63 * (NB - (s + 4 - last_phase)));
-            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the votes are written
-            stage_barrier();
-            if (all_done()) {
-                wait_vmcnt<0>();   // no load may land in LDS after the tile is left
-                return;
+    // stages [s0, s1), s0 and s1 multiples of 4
+    auto run = [&](int s0, int s1) {
+        for (int s = s0; s < s1; s += 4) {
+            step(0, s, fr0, fr1);
+            step(1, s + 1, fr1, fr0);
+            step(2, s + 2, fr0, fr1);
+            step(3, s + 3, fr1, fr0);
+            // after 16, 32 and 48 rows of the last phase: vote, publish, decide
+            if (exit_ok && s + 4 > last_phase && (s + 4 - last_phase) % 16 == 0 && s + 4 < nstage) {
+                vote(128 * 63 * (NB - (s + 4 - last_phase)));
+                __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the votes are written
+                stage_barrier();
+                if (all_done()) {
+                    wait_vmcnt<0>();   // no load may land in LDS after the tile is left
+                    return true;
+                }
             }
         }
+        return false;
+    };
+    if constexpr (MODE == kModePair) {
+        // one loop per phase, so that what happens between phases holds no
+        // registers inside the loops; the ring keeps prefetching across
+        run(0, NB);
+        keep_cross();
+        run(NB, 2 * NB);
+        // end of the (I -> J) direction: its rows are counted (LDS only: the
+        // stages in flight keep landing), and the (J -> I) r phase starts
+        // from zero
+        count_rows();
+        zero_acc();
+        run(2 * NB, 3 * NB);
+    } else {
+        if (run(0, nstage)) return;   // nstage is a multiple of 64
     }
-    wait_vmcnt<0>();   // the repeated loads of the last steps (and any cslot stores) have landed
-    if constexpr (MODE == kModeStore) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    wait_vmcnt<0>();   // the repeated loads of the last steps have landed
 
-    // Epilogue.  16x16 accumulator layout: lane l holds column l % 16 and
-    // rows 4 * (l / 16) + v of its block, v = 0..3.
-    const int cl = lane & 15, rq = lane >> 4;
-    if constexpr (MODE == kModeMirror) {
-        // counts per column (needle): over the lane's 4 rows of each block,
-        // the wave's row blocks, the 4 lanes of the column (l, l ^ 16, l ^ 32,
-        // l ^ 48) and the kWM waves sharing the column (LDS), then one global
-        // atomic per needle
-        static_assert(C::kNBK <= 4 && C::kMB * 16 < 256, "column counts must fit a byte each");
-        uint32_t rowok[C::kMB];
+    if constexpr (MODE == kModePair) {
+        const int ln = lane_here(), cl = ln & 15, rq = ln >> 4;
+        const int wm = wv / C::kWN, wn = wv % C::kWN;   // scalar
+        // The kept cross term: this wave's own stores, retired in the cross
+        // phase.  The loads are device-scope (cache policy sc1): they miss in
+        // the CU's vector L1 and read the L2, so no line of the slot cached
+        // by an earlier pair of this workgroup can be read instead.
+        const uint32_t cvo = cslot_voff();
+        if (c16) {
 #pragma unroll
-        for (int mb = 0; mb < C::kMB; ++mb)
-            rowok[mb] = *reinterpret_cast<const uint32_t*>(col_l + (wm * C::kMB + mb) * 16 + 4 * rq);
-        uint32_t packed = 0;
+            for (int mb = 0; mb < C::kMB; ++mb) {
+                v4i w[C::kNBK / 2];
 #pragma unroll
-        for (int nb = 0; nb < C::kNBK; ++nb) {
-            const int32_t t = thr_l[(wn * C::kNBK + nb) * 16 + cl];
-            uint32_t cnt = 0;
+                for (int nb = 0; nb < C::kNBK; nb += 2)
+                    w[nb / 2] = __builtin_amdgcn_raw_buffer_load_b128(crsrc, cvo, cslot_soff(mb, nb), kDeviceScope);
 #pragma unroll
-            for (int mb = 0; mb < C::kMB; ++mb)
+                for (int nb = 0; nb < C::kNBK; nb += 2)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    cnt += (((rowok[mb] >> (8 * v)) & 1u) && acc[mb][nb][v] < t) ? 1u : 0u;
-            packed |= cnt << (8 * nb);
+                    for (int v = 0; v < 4; ++v) {
+                        acc[mb][nb][v] += (int32_t)((uint32_t)w[nb / 2][v] << 16) >> 16;   // low half, sign-extended
+                        acc[mb][nb + 1][v] += w[nb / 2][v] >> 16;                         // high half (arithmetic)
+                    }
+            }
+        } else {
+#pragma unroll
+            for (int mb = 0; mb < C::kMB; ++mb) {
+                v4i w[C::kNBK];
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; ++nb)
+                    w[nb] = __builtin_amdgcn_raw_buffer_load_b128(crsrc, cvo, cslot_soff(mb, nb), kDeviceScope);
+#pragma unroll
+                for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] += w[nb];
+            }
         }
-        packed += (uint32_t)__shfl_xor((int)packed, 16, 64);
-        packed += (uint32_t)__shfl_xor((int)packed, 32, 64);
+        // counts per column (needle of tile J): over the lane's 4 rows of
+        // each block, the wave's row blocks, the 4 lanes of the column (l,
+        // l ^ 16, l ^ 32, l ^ 48: lane-half swaps) and the kWM waves sharing
+        // the column (LDS)
+        static_assert(C::kNBK <= 4 && C::kMB * 16 < 256, "column counts must fit a byte each");
+        auto body = [&](auto all_usable) {
+            constexpr bool kAll = decltype(all_usable)::value;
+            uint32_t packed = 0;
+#pragma unroll
+            for (int nb = 0; nb < C::kNBK; ++nb) {
+                const int32_t t = thrc_l[(wn * C::kNBK + nb) * 16 + cl];
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int mb = 0; mb < C::kMB; ++mb) {
+                    const uint32_t rowok =
+                        kAll ? 0x01010101u
+                             : *reinterpret_cast<const uint32_t*>(rowok_l + (wm * C::kMB + mb) * 16 + 4 * rq);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        cnt += ((kAll || ((rowok >> (8 * v)) & 1u)) && acc[mb][nb][v] < t) ? 1u : 0u;
+                }
+                packed |= cnt << (8 * nb);
+            }
+            return packed;
+        };
+        // (every row usable: no per-row test)
+        uint32_t packed = !(tile_flags_lds() & 16) ? body(std::true_type{}) : body(std::false_type{});
+        {
+            const auto h = __builtin_amdgcn_permlane32_swap(packed, packed, false, false);
+            packed = h[0] + h[1];
+            const auto q = __builtin_amdgcn_permlane16_swap(packed, packed, false, false);
+            packed = q[0] + q[1];
+        }
         if (rq == 0) {
 #pragma unroll
             for (int nb = 0; nb < C::kNBK; ++nb) {
                 const uint32_t cnt = (packed >> (8 * nb)) & 0xFFu;
-                if (cnt) atomicAdd(rowcnt + (wn * C::kNBK + nb) * 16 + cl, cnt);
+                if (cnt) atomicAdd(colcnt + (wn * C::kNBK + nb) * 16 + cl, cnt);
             }
         }
         __syncthreads();
-        for (int j = tid; j < C::BN; j += C::kThreads) {
-            const uint32_t c = rowcnt[j];
-            if (c) atomicAdd(A.rank + A.nperm[gb0 * 16 + (uint32_t)j], c);
+        // every slot of a paired set is a row (nrows covers the tiles)
+        for (int j = tid; j < C::BM; j += C::kThreads) {
+            const uint32_t r = rowcnt[j], c = colcnt[j];
+            if (r) red_add(A.rank + permr_l[j], r);
+            if (c) red_add(A.rank + permc_l[j], c);
         }
         return;
     }
-    bool colok[C::kNBK];
-    uint32_t col[C::kNBK];
-#pragma unroll
-    for (int nb = 0; nb < C::kNBK; ++nb) {
-        const uint32_t slot = (gb0 + wn * C::kNBK + nb) * 16 + cl;
-        colok[nb] = col_l[(wn * C::kNBK + nb) * 16 + cl] != 0;
-        col[nb] = (!ranks && colok[nb]) ? A.hperm[slot] : 0u;   // original haystack index (matrix mode)
-    }
+    const int cl = lane & 15, rq = lane >> 4;
     if (ranks) {
-        // Per lane, the counts of its four rows of block mb (each at most
-        // kNBK) packed one per byte; a DPP prefix sum over the lane's row of 16
-        // lanes (the lanes holding those rows' 16 columns) leaves the block
-        // rows' counts in lane 15 of it, at most 16 * kNBK < 256 per byte.
-        // The kWN waves sharing a needle row add them in LDS (zeroed in the
-        // prologue), then one global atomic per row of the tile.
-        static_assert(16 * C::kNBK < 256, "row counts must fit a byte");
-#pragma unroll
-        for (int mb = 0; mb < C::kMB; ++mb) {
-            // the four thresholds of this lane's rows in the block (INT_MIN past the needles)
-            const v4i t4 = *reinterpret_cast<const v4i*>(thr_l + (wm * C::kMB + mb) * 16 + 4 * rq);
-            uint32_t packed = 0;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                uint32_t cnt = 0;
-#pragma unroll
-                for (int nb = 0; nb < C::kNBK; ++nb) cnt += (colok[nb] && acc[mb][nb][v] < t4[v]) ? 1u : 0u;
-                packed |= cnt << (8 * v);
-            }
-            packed = row16_prefix_sum(packed);
-            if (cl == 15) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const uint32_t cnt = (packed >> (8 * v)) & 0xFFu;
-                    const int lrow = (wm * C::kMB + mb) * 16 + 4 * rq + v;   // row within the tile
-                    if (cnt && ga0 * 16 + (uint32_t)lrow < nrows) atomicAdd(rowcnt + lrow, cnt);
-                }
-            }
-        }
+        count_rows();
     } else {
+        // original haystack index of each of the lane's columns (matrix mode)
+        bool colok[C::kNBK];
+        uint32_t col[C::kNBK];
+#pragma unroll
+        for (int nb = 0; nb < C::kNBK; ++nb) {
+            const uint32_t slot = (gb0 + wn * C::kNBK + nb) * 16 + cl;
+            colok[nb] = col_l[(wn * C::kNBK + nb) * 16 + cl] != 0;
+            col[nb] = colok[nb] ? A.hperm[slot] : 0u;
+        }
 #pragma unroll
         for (int mb = 0; mb < C::kMB; ++mb) {
 #pragma unroll
@@ -946,7 +1082,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         __syncthreads();
         for (int j = tid; j < C::BM; j += C::kThreads) {
             const uint32_t c = rowcnt[j], row = ga0 * 16 + (uint32_t)j;
-            if (c && row < nrows) atomicAdd(A.rank + (A.nperm ? A.nperm[row] : row), c);
+            if (c && row < nrows) red_add(A.rank + (A.nperm ? ldg(A.nperm + row) : row), c);
         }
     }
 }
@@ -985,28 +1121,28 @@ __device__ __forceinline__ void pair_coords(uint32_t k, uint32_t T, uint32_t& I,
 __host__ __device__ __forceinline__ uint32_t pair_items(uint32_t T) { return T * (T + 1) / 2; }
 
 // Both directions of tile pair (I, J) of a paired set.  A pair whose images
-// all have |D| <= 15 computes the cross term once (store pass (I, J), then
-// its mirror); a pair with a q phase on either side runs (I, J) and (J, I) as
+// all have |D| <= 15 computes the cross term once (one pass of three
+// phases); a pair with a q phase on either side runs (I, J) and (J, I) as
 // plain tiles.  cslot: this workgroup's BM x BN int32 slot.
 template <class C>
 __device__ void search_pair(const SearchArgs& A, uint32_t I, uint32_t J, int8_t* lds, int32_t* cslot)
 {
-    if (I == J) {
-        search_tile<C, false, kModePlain>(A, I, I, lds);
-        return;
+    if (I != J) {
+        const uint32_t fi = ldc(A.tile_flags + I), fj = ldc(A.tile_flags + J);
+        if (!(fi & 1u) || !(fj & 1u)) return;   // one side has no usable image: neither direction counts
+        if (!((fi | fj) & 2u)) {
+            search_tile<C, false, kModePair>(A, I, J, lds, cslot);
+            return;
+        }
     }
-    const uint32_t fi = A.tile_flags[I], fj = A.tile_flags[J];
-    if (!(fi & 1u) || !(fj & 1u)) return;   // one side has no usable image: neither direction counts
-    if ((fi | fj) & 2u) {
-        search_tile<C, false, kModePlain>(A, I, J, lds);
-        __syncthreads();
-        search_tile<C, false, kModePlain>(A, J, I, lds);
-        return;
+    // plain tiles: the diagonal one, or both directions of a pair with a q
+    // phase (one copy of the tile code, hence the loop)
+    const uint32_t n = I == J ? 1u : 2u;
+#pragma nounroll
+    for (uint32_t d = 0; d < n; ++d) {
+        if (d) __syncthreads();
+        search_tile<C, false, kModeRank>(A, d ? J : I, d ? I : J, lds);
     }
-    uint32_t cform = 0;
-    search_tile<C, false, kModeStore>(A, I, J, lds, cslot, &cform);
-    __syncthreads();
-    search_tile<C, false, kModeMirror>(A, I, J, lds, cslot, &cform);
 }
 
 // Next work item of a persistent search kernel: items [0, total) are split
@@ -1015,10 +1151,14 @@ __device__ void search_pair(const SearchArgs& A, uint32_t I, uint32_t J, int8_t*
 // neighbours and share fragments in its L2); a workgroup takes items from its
 // own XCD's counter, then from the others' once its range is used up.  The
 // item is broadcast through the first LDS word; returns total when done.
+// (Claiming one item ahead, to hide the atomic's latency, was measured
+// slower: a workgroup then holds a second item while others run dry at the
+// end of the queue.)
 __device__ __forceinline__ uint32_t next_item(uint32_t* __restrict__ counters, uint32_t total, uint32_t& visited,
                                               int8_t* lds)
 {
-    volatile uint32_t* s_item = reinterpret_cast<volatile uint32_t*>(lds);
+    volatile __attribute__((address_space(3))) uint32_t* s_item =
+        (volatile __attribute__((address_space(3))) uint32_t*)lds;
     const uint32_t xcd = blockIdx.x & 7u, per = (total + 7) / 8;
     if (threadIdx.x == 0) {
         uint32_t item = total;
@@ -1090,14 +1230,22 @@ k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t to
     // the ring takes all of the LDS: the item is broadcast through its first
     // word, which no wave reads or fills between two items
     uint32_t visited = 0;   // ranges used up (thread 0 only)
+    // the job of the last item and its item range: consecutive items mostly
+    // belong to one job, which saves the dependent loads of the search
+    uint32_t lo = 0, j_begin = 0, j_end = 0;
     for (;;) {
         const uint32_t item = next_item(counters, total, visited, lds);
         if (item >= total) break;
         // the job's arguments, loaded through the uniform item, stay scalar
-        uint32_t lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) / 2;
-            if (jobs[mid].tile_start <= item) lo = mid; else hi = mid - 1;
+        if (item < j_begin || item >= j_end) {
+            uint32_t hi = njobs - 1;
+            lo = 0;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) / 2;
+                if (jobs[mid].tile_start <= item) lo = mid; else hi = mid - 1;
+            }
+            j_begin = jobs[lo].tile_start;
+            j_end = lo + 1 < njobs ? jobs[lo + 1].tile_start : total;
         }
         const SearchArgs A = jobs[lo].A;
         bool done = false;
@@ -1112,7 +1260,7 @@ k_search_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint32_t to
         if (!done) {
             uint32_t tm, tn;
             tile_coords(item - jobs[lo].tile_start, A.tiles_m, A.tiles_n, tm, tn);
-            search_tile<C, EXIT>(A, tm, tn, lds);
+            search_tile<C, EXIT, kModeRank>(A, tm, tn, lds);   // batched jobs rank
         }
         __syncthreads();   // every wave is done with the ring before its first word is reused
     }
@@ -1133,7 +1281,7 @@ k_search_scan(ScanTable T)
     while (k + 1 < T.njobs && T.m_start[k + 1] <= r) ++k;
     const uint32_t tm = r - T.m_start[k];
     const uint32_t tn = (T.tile_begin + tnl) % T.db_tiles;
-    search_tile<C, EXIT>(T.A[k], tm, tn, lds);
+    search_tile<C, EXIT, kModeRank>(T.A[k], tm, tn, lds);   // a query ranks
 }
 
 // ------------------------------------------------------- out-of-range images
