@@ -468,6 +468,22 @@ __device__ __forceinline__ void lds_add_u32(uint32_t* p, uint32_t v)
     asm volatile("ds_add_u32 %0, %1" ::"v"(a), "v"(v) : "memory");
 }
 
+// Thresholds as the counts use them: limited to +-2^30, which changes no
+// comparison (an accumulator of the int8 path stays below 2^28 in
+// magnitude; INT_MIN, no count, becomes -2^30), so that below() cannot
+// overflow.
+__device__ __forceinline__ int32_t clamp_thr(int32_t t)
+{
+    return min(max(t, -(1 << 30)), 1 << 30);
+}
+
+// [acc < t] as the sign bit of the difference: plain vector arithmetic, no
+// compare mask (whose readers need wait states after each compare)
+__device__ __forceinline__ uint32_t below(int32_t acc, int32_t t)
+{
+    return ((uint32_t)acc - (uint32_t)t) >> 31;   // (unsigned: kept as arithmetic)
+}
+
 // Row bases of the planes a tile streams in each phase.
 struct StageSrc { const int8_t *a0, *a1, *a2, *b0, *b1, *b2; };
 
@@ -602,8 +618,8 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             flags |= (mi > kSlow) ? 16 : 0;   // a row (tile I image) is not usable
             col_l[j] = mj <= kSlow ? 1 : 0;
             rowok_l[j] = mi <= kSlow ? 1 : 0;
-            thr_l[j] = ti;
-            thrc_l[j] = tj;
+            thr_l[j] = clamp_thr(ti);
+            thrc_l[j] = clamp_thr(tj);
             rowcnt[j] = 0u;
             colcnt[j] = 0u;
             permr_l[j] = pi;
@@ -626,7 +642,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             }
             if (j < C::BM) {
                 flags |= (t != INT_MIN) ? 4 : 0;
-                thr_l[j] = t;
+                thr_l[j] = clamp_thr(t);
                 rowcnt[j] = 0u;
             }
         }
@@ -780,9 +796,9 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
             constexpr bool kAll = decltype(all_usable)::value;
             const int ln = lane_here(), cl = ln & 15, rq = ln >> 4;
             const int wm = wv / C::kWN, wn = wv % C::kWN;   // scalar
-            bool colok[C::kNBK];
+            uint32_t colok[C::kNBK];
 #pragma unroll
-            for (int nb = 0; nb < C::kNBK; ++nb) colok[nb] = kAll || col_l[(wn * C::kNBK + nb) * 16 + cl] != 0;
+            for (int nb = 0; nb < C::kNBK; ++nb) colok[nb] = kAll ? 1u : col_l[(wn * C::kNBK + nb) * 16 + cl];
 #pragma unroll
             for (int mb = 0; mb < C::kMB; ++mb) {
                 // the four thresholds of this lane's rows in the block (INT_MIN past the needles)
@@ -793,7 +809,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
                     uint32_t cnt = 0;
 #pragma unroll
                     for (int nb = 0; nb < C::kNBK; ++nb)
-                        cnt += ((kAll || colok[nb]) && acc[mb][nb][v] < t4[v]) ? 1u : 0u;
+                        cnt += kAll ? below(acc[mb][nb][v], t4[v]) : below(acc[mb][nb][v], t4[v]) & colok[nb];
                     packed |= cnt << (8 * v);
                 }
                 packed = row16_prefix_sum(packed);
@@ -1021,7 +1037,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
                              : *reinterpret_cast<const uint32_t*>(rowok_l + (wm * C::kMB + mb) * 16 + 4 * rq);
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        cnt += ((kAll || ((rowok >> (8 * v)) & 1u)) && acc[mb][nb][v] < t) ? 1u : 0u;
+                        cnt += kAll ? below(acc[mb][nb][v], t) : below(acc[mb][nb][v], t) & (rowok >> (8 * v));
                 }
                 packed |= cnt << (8 * nb);
             }
