@@ -81,6 +81,29 @@ def test_paired_ranks_equal_oracle_and_unpaired(ctx, n, big, huge):
         assert int(o_rk.max()) > 0 and int(np.median(o_rk)) < n - 1   # ranks are not trivial
 
 
+def test_paired_cross_terms_beyond_int16(ctx):
+    """Dense images whose steps all have |D| = 15 (rows alternating 0 and 15,
+    or 15 and 0) share tiles with sparse ones: the kept cross term
+    -2 <D_a, D_b> reaches 2 * 63 * 64 * 225 = 1 814 400 for two equal dense
+    images, past the int16 form, so those waves keep it as int32 while the
+    sparse waves use int16.  Ranks and distances must equal the oracle's."""
+    rng = np.random.default_rng(77)
+    n = 900
+    imgs = synth.step_images(rng, n, density=0.1, delta_scale=2)
+    dense = rng.random(n) < 0.4
+    cols = np.arange(64)
+    for k in np.flatnonzero(dense):
+        phase = rng.integers(0, 2, size=64)                       # per row: which columns hold 15
+        imgs[k] = np.where(((cols[None, :] + phase[:, None]) % 2) == 1, 15, 0).astype(np.uint32)
+        imgs[k, rng.integers(0, 64, 3)] = 0                         # a few flat rows: not all equal
+    assert int(np.abs(np.diff(imgs.astype(np.int64), axis=2)).max()) == 15
+    t = _truth(91, n)
+    p_rk, p_ds = _rank(ctx, imgs, t, 1)
+    o_rk, o_ds = oracle.rank(imgs, imgs, t)
+    _same(p_ds, o_ds, "paired true distances")
+    _same(p_rk, o_rk, "paired ranks")
+
+
 def test_paired_identity_truth_and_duplicates(ctx):
     """t(i) = i gives rank 0 for every image; exact duplicates tie at the
     true distance 0 and keep the best rank."""
