@@ -526,7 +526,8 @@ __device__ __forceinline__ void issue_stage(int8_t* lds, int slot, int t, int wv
 // the columns (needles of tile J against the haystack images of tile I) are
 // counted.
 // kModeRank is kModePlain known to be in rank mode (no distance matrix):
-// persistent kernels, which rank only, carry no matrix epilogue.
+// the kernels that only rank (the persistent and the scan kernels) carry no
+// matrix epilogue.
 enum { kModePlain = 0, kModePair = 1, kModeRank = 2 };
 
 // One BM x BN (needle x haystack) tile, or tile pair: every workgroup thread
@@ -922,9 +923,9 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
                         w[v] = (int32_t)(((uint32_t)acc[mb][nb][v] & 0xFFFFu) |
                                          ((uint32_t)acc[mb][nb + 1][v] << 16));
                     __builtin_amdgcn_raw_buffer_store_b128(w, crsrc, cvo, cslot_soff(mb, nb), 0);
-                    // a store of more than 8 bytes reads its data
-                    // registers after it issues: two wait states
-                    // before the next pack may rewrite them
+                    // a store of more than 8 bytes reads its data registers
+                    // after it issues: two wait states before the next pack
+                    // may rewrite them
                     __builtin_amdgcn_sched_barrier(0);
                     asm volatile("s_nop 1");
                     __builtin_amdgcn_sched_barrier(0);
