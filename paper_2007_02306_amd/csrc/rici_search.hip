@@ -1108,31 +1108,34 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
 // I <= J.  Items come in bands of 4 consecutive I (measured best of 2, 4, 8,
 // 16); within a band J-major, so the items running at the same time share
 // their I tiles and a few J tiles.
-__device__ __forceinline__ void pair_coords(uint32_t k, uint32_t T, uint32_t& I, uint32_t& J)
+// Items before full band b: b (4T - 6) - 16 b (b - 1) / 2 = b (4T + 2 - 8b);
+// the band of item k is the largest b with that count <= k, found from the
+// quadratic's smaller root and settled by integer comparisons (O(1) per
+// item: a large mesh has hundreds of bands).
+__host__ __device__ __forceinline__ void pair_coords(uint32_t k, uint32_t T, uint32_t& I, uint32_t& J)
 {
     constexpr uint32_t BW = 4;
-    uint32_t b0 = 0;
-    while (b0 < T) {
-        const uint32_t bw = min(BW, T - b0);
-        const uint32_t tri = bw * (bw + 1) / 2;           // J inside the band
-        const uint32_t nb = tri + (T - b0 - bw) * bw;     // + J beyond it
-        if (k < nb) {
-            if (k < tri) {
-                uint32_t a = 0;
-                while ((a + 1) * (a + 2) / 2 <= k) ++a;
-                J = b0 + a;
-                I = b0 + (k - a * (a + 1) / 2);
-            } else {
-                const uint32_t r = k - tri;
-                J = b0 + bw + r / bw;
-                I = b0 + r % bw;
-            }
-            return;
-        }
-        k -= nb;
-        b0 += bw;
+    const uint64_t nfull = T / BW;
+    auto before = [&](uint64_t b) { return b * (4ull * T + 2ull) - 8ull * b * b; };
+    const double p = 4.0 * T + 2.0, disc = p * p - 32.0 * (double)k;
+    uint64_t b = disc > 0.0 ? (uint64_t)((p - sqrt(disc)) / 16.0) : nfull;
+    if (b > nfull) b = nfull;
+    while (b > 0 && before(b) > k) --b;
+    while (b < nfull && before(b + 1) <= k) ++b;
+    const uint32_t b0 = (uint32_t)(BW * b);
+    const uint32_t bw = min(BW, T - b0);                  // the last band may be narrower
+    const uint32_t r = k - (uint32_t)before(b);
+    const uint32_t tri = bw * (bw + 1) / 2;               // J inside the band
+    if (r < tri) {
+        uint32_t a = 0;
+        while ((a + 1) * (a + 2) / 2 <= r) ++a;
+        J = b0 + a;
+        I = b0 + (r - a * (a + 1) / 2);
+    } else {
+        const uint32_t q = r - tri;                       // J beyond the band
+        J = b0 + bw + q / bw;
+        I = b0 + q % bw;
     }
-    I = J = 0;   // k beyond the T (T + 1) / 2 items: not reached
 }
 
 __host__ __device__ __forceinline__ uint32_t pair_items(uint32_t T) { return T * (T + 1) / 2; }
