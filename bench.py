@@ -70,7 +70,8 @@ def parse():
 
 
 GEN_SOURCES = ["paper_2007_02306_amd/csrc/rici_gen.hip", "paper_2007_02306_amd/csrc/rici_internal.h"]
-SEARCH_SOURCES = ["paper_2007_02306_amd/csrc/rici_search.hip", "paper_2007_02306_amd/csrc/rici_internal.h"]
+SEARCH_SOURCES = ["paper_2007_02306_amd/csrc/rici_search.hip", "paper_2007_02306_amd/csrc/rici_internal.h",
+                  "paper_2007_02306_amd/csrc/rici_pairs.h"]
 KERNEL_SOURCES = {"k_gen": GEN_SOURCES, "k_gen_batched": GEN_SOURCES,
                   "k_search": SEARCH_SOURCES, "k_search_batched": SEARCH_SOURCES,
                   "k_search_paired": SEARCH_SOURCES}

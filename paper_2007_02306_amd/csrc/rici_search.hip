@@ -23,6 +23,7 @@
 // sum of per-tile counts, so tiles add their counts with integer atomics and
 // the result is exact and independent of the order of tiles.
 #include "rici_internal.h"
+#include "rici_pairs.h"
 
 #include <limits.h>
 #include <type_traits>
@@ -1104,43 +1105,6 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     }
 }
 
-// Paired sets: work item k of a T x T tile grid is the tile pair (I, J),
-// I <= J.  Items come in bands of BW = 8 consecutive I; within a band J-major,
-// so the items running at the same time share their I tiles and a few J
-// tiles.  (On the 256-mesh workload 8 measured 1.4 % faster than 4, whose
-// bands stream every J tile twice as often, and 12 and 16 slower; on a single
-// set of 92 tiles 4 and 8 are within 1.4 %.)
-// Items before full band b: b (BW T - BW (BW - 1) / 2) - BW^2 b (b - 1) / 2
-// = b (BW T + BW / 2) - (BW^2 / 2) b^2; the band of item k is the largest b
-// with that count <= k, found from the quadratic's smaller root and settled
-// by integer comparisons (O(1) per item: a large mesh has hundreds of bands).
-__host__ __device__ __forceinline__ void pair_coords(uint32_t k, uint32_t T, uint32_t& I, uint32_t& J)
-{
-    constexpr uint32_t BW = 8;
-    const uint64_t nfull = T / BW;
-    auto before = [&](uint64_t b) { return b * ((uint64_t)BW * T + BW / 2) - (uint64_t)(BW * BW / 2) * b * b; };
-    const double p = (double)BW * T + BW / 2, disc = p * p - 2.0 * BW * BW * (double)k;
-    uint64_t b = disc > 0.0 ? (uint64_t)((p - sqrt(disc)) / (double)(BW * BW)) : nfull;
-    if (b > nfull) b = nfull;
-    while (b > 0 && before(b) > k) --b;
-    while (b < nfull && before(b + 1) <= k) ++b;
-    const uint32_t b0 = (uint32_t)(BW * b);
-    const uint32_t bw = min(BW, T - b0);                  // the last band may be narrower
-    const uint32_t r = k - (uint32_t)before(b);
-    const uint32_t tri = bw * (bw + 1) / 2;               // J inside the band
-    if (r < tri) {
-        uint32_t a = 0;
-        while ((a + 1) * (a + 2) / 2 <= r) ++a;
-        J = b0 + a;
-        I = b0 + (r - a * (a + 1) / 2);
-    } else {
-        const uint32_t q = r - tri;                       // J beyond the band
-        J = b0 + bw + q / bw;
-        I = b0 + q % bw;
-    }
-}
-
-__host__ __device__ __forceinline__ uint32_t pair_items(uint32_t T) { return T * (T + 1) / 2; }
 
 // Both directions of tile pair (I, J) of a paired set.  A pair whose images
 // all have |D| <= 15 computes the cross term once (one pass of three
@@ -1196,10 +1160,11 @@ __device__ __forceinline__ uint32_t next_item(uint32_t* __restrict__ counters, u
         *s_item = item;
     }
     __syncthreads();
-    // the item is the same in every lane: keep it in a scalar register
-    const uint32_t item = __builtin_amdgcn_readfirstlane(*s_item);
-    __syncthreads();
-    return item;
+    // the item is the same in every lane: keep it in a scalar register.
+    // (No second barrier: the word is next written by the ring's first stage
+    // or by the next call, both behind a later workgroup barrier that every
+    // wave reaches only after this read.)
+    return __builtin_amdgcn_readfirstlane(*s_item);
 }
 
 // Persistent search over the tile pairs of one paired set (one workgroup per
