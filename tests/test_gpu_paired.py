@@ -180,3 +180,21 @@ def test_batched_plan_paired_equals_unpaired(ctx):
     o_rk, o_ds = oracle.rank(img, img, meshes[2][3])
     assert np.array_equal(results[0][2][0], o_rk) and np.array_equal(results[0][2][1], o_ds)
     torch.cuda.synchronize()
+
+
+def test_paired_benchmark_sized_set_sampled(ctx):
+    """A set of 23 352 images ranked against itself (92 tiles: 11 full bands
+    of 8 tile rows and a partial one; 4 278 tile pairs), with 6 % of the
+    images stepping beyond 15 and a few beyond 127, so that shared pairs,
+    pairs with a q phase and the exact path all occur.  A sample of 64
+    needles is ranked by the oracle over the whole set."""
+    n = 23_352
+    imgs = _set(99, n, big=0.06, huge=5)
+    t = _truth(99, n)
+    rk, ds = _rank(ctx, imgs, t, 1)
+    rng = np.random.default_rng(100)
+    sel = np.unique(np.concatenate([[0, 255, 256, n - 1], rng.choice(n, 60, replace=False)]))
+    o_rk, o_ds = oracle.rank(imgs[sel], imgs, t[sel])
+    _same(ds[sel], o_ds, "paired true distances (sample)")
+    _same(rk[sel], o_rk, "paired ranks (sample)")
+    assert int(o_rk.max()) > 0
