@@ -86,8 +86,10 @@ constexpr int kGroup = 16;                       // images per fragment group
 constexpr size_t kFragBytes = 1024;              // 16 images x 64 columns
 constexpr size_t kPlaneGroupBytes = NB * kFragBytes;   // one group, all 64 rows
 
-// needle planes: 0 = -D (int8), 1 = mask [D != 0] (0/1)
+// needle planes: 0 = D (int8), 1 = mask [D != 0] (0/1)
 // haystack planes: 0 = D, 1 = r = (D^2 mod 256) - 128, 2 = q = D^2 div 256
+// (a set ranked against itself writes needle plane 1 only: its needles read
+// the haystack's D plane, in the same slot order)
 // Needles keep their order (slot = image).  The haystack is permuted: images
 // whose deltas all satisfy |D| <= 15 (so q = 0) take slots from the front, the others
 // from the back, with at least one whole tile of padding in between, so that a

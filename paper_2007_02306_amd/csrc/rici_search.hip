@@ -7,11 +7,11 @@
 // |D_n|^2 is one number per needle, so a (needle, haystack) pair costs two
 // length-4096 int8 dot products -- a dense int8 x int8 -> int32 GEMM over all
 // pairs, which is what MFMA does best.  Operands stay exact int8 under a range
-// check: needles with |D| <= 127 use planes (-D_n, m_n); haystack images with
+// check: needles with |D| <= 127 use planes (D_n, m_n); haystack images with
 // |D| <= 127 use (D_h, r, q) with D_h^2 = 256 q + r + 128, i.e.
 // r = (D_h^2 mod 256) - 128 in [-128, 127] and q = D_h^2 div 256 in [0, 63].
 // The accumulator is scaled between phases so a single int32 accumulator holds
-//     128 <m, q> ... (x128) ... - <D_n, D_h> ... (x2) ... + <m, r>
+//     <m, q> ... (x -128) ... + <D_n, D_h> ... (x -2) ... + <m, r>
 //   = <m, D_h^2> - 2 <D_n, D_h> - 128 |m|,
 // and the needle's constant |D_n|^2 + 128 |m| (|m| = its non-zero deltas) is
 // added outside.  The q phase is skipped for haystack tiles where every
@@ -36,6 +36,9 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr uint32_t kSlow = 127;     // largest |D| an int8 operand holds
 constexpr uint32_t kSmallD = 15;    // |D| <= 15  =>  D^2 <= 225: q = 0, r = D^2 - 128 fits int8
 constexpr uint32_t kPad = 0xFFFFFFFFu;
+// paired sets keep one flag word per tile of this many slots (the paired
+// search's tile width)
+constexpr uint32_t kFlagTile = 256;
 // word 3 of a gfx9 buffer resource for untyped (raw) dword accesses
 constexpr int kBufferWord3 = 0x00020000;
 // cache policy of a buffer access: sc1 (device scope; a load misses in the
@@ -48,13 +51,16 @@ constexpr int kDeltaWaves = 8;   // wavefronts per delta-prep workgroup (rows sp
 
 // One block per group of 16 images; thread (row-in-step, lane) with
 // lane = 16 * q + i writes columns 16 q .. 16 q + 15 of image i.
-// needle_side: 1 needle planes (-D, mask) into `planes`; 0 haystack planes
-// (D, r, q) into `planes`; 2 both, needle planes into `planes` and haystack
-// planes into `hplanes` (a set ranked against itself, in slot order).
+// needle_side: 1 needle planes (D, mask) into `planes`; 0 haystack planes
+// (D, r, q) into `planes`; 2 both, in slot order (a set ranked against
+// itself): the mask plane into `planes` and the haystack planes into
+// `hplanes`, whose D plane serves as the needles' D plane too.  With
+// `qflags` (the set's tile flags) the q plane is written only in tiles whose
+// bit 1 is set: no other tile runs the q phase, so none reads it.
 __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
                             int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
                             uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm, uint32_t grp,
-                            int8_t* __restrict__ hplanes = nullptr)
+                            int8_t* __restrict__ hplanes = nullptr, const uint32_t* __restrict__ qflags = nullptr)
 {
     __shared__ uint32_t smax[kDeltaWaves][kGroup];
     __shared__ int64_t ssum[kDeltaWaves][kGroup];
@@ -64,6 +70,7 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
     const uint32_t img = perm ? perm[slot] : slot;
     const bool live = perm ? img != kPad : slot < n;
     const size_t plane_stride = (size_t)ngroups * kPlaneGroupBytes;
+    const bool write_q = !qflags || (qflags[grp / (kFlagTile / kGroup)] & 2u);
 
     uint32_t mx = 0;
     int64_t ss = 0;
@@ -92,34 +99,34 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
 #pragma unroll
             for (int k = 0; k < 16; ++k) d[k] = 0;
         }
-        // pack into the fragment-major planes: needle -D and mask, haystack
-        // D, r = (D^2 mod 256) - 128 and q = D^2 div 256 (int8 bytes)
+        // pack into the fragment-major planes: D (both sides), needle mask,
+        // haystack r = (D^2 mod 256) - 128 and q = D^2 div 256 (int8 bytes)
         const size_t frag = ((size_t)grp * NB + r) * kFragBytes + (size_t)lane * 16;
-        uint32_t nd[4], nm[4], hd[4], hr[4], hq[4];
+        uint32_t nm[4], hd[4], hr[4], hq[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            uint32_t a0 = 0, a1 = 0, b0 = 0, b1 = 0, b2 = 0;
+            uint32_t a1 = 0, b0 = 0, b1 = 0, b2 = 0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int32_t x = d[4 * k + b];
                 const uint32_t sq = (uint32_t)(x * x);
-                a0 |= (uint32_t)(uint8_t)(int8_t)(-x) << (8 * b);
                 a1 |= (x != 0 ? 1u : 0u) << (8 * b);
                 b0 |= (uint32_t)(uint8_t)(int8_t)x << (8 * b);
                 b1 |= ((sq & 255u) ^ 0x80u) << (8 * b);
                 b2 |= (sq >> 8) << (8 * b);
             }
-            nd[k] = a0; nm[k] = a1; hd[k] = b0; hr[k] = b1; hq[k] = b2;
+            nm[k] = a1; hd[k] = b0; hr[k] = b1; hq[k] = b2;
         }
-        if (needle_side) {
-            *reinterpret_cast<uint4*>(planes + frag) = make_uint4(nd[0], nd[1], nd[2], nd[3]);
+        if (needle_side == 1)
+            *reinterpret_cast<uint4*>(planes + frag) = make_uint4(hd[0], hd[1], hd[2], hd[3]);
+        if (needle_side)
             *reinterpret_cast<uint4*>(planes + plane_stride + frag) = make_uint4(nm[0], nm[1], nm[2], nm[3]);
-        }
         if (needle_side != 1) {
             int8_t* hp = needle_side == 2 ? hplanes : planes;
             *reinterpret_cast<uint4*>(hp + frag) = make_uint4(hd[0], hd[1], hd[2], hd[3]);
             *reinterpret_cast<uint4*>(hp + plane_stride + frag) = make_uint4(hr[0], hr[1], hr[2], hr[3]);
-            *reinterpret_cast<uint4*>(hp + 2 * plane_stride + frag) = make_uint4(hq[0], hq[1], hq[2], hq[3]);
+            if (write_q)
+                *reinterpret_cast<uint4*>(hp + 2 * plane_stride + frag) = make_uint4(hq[0], hq[1], hq[2], hq[3]);
         }
     }
     if (perm && !needle_side) return;   // the haystack's statistics come from k_hay_stats
@@ -153,9 +160,10 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
 __global__ void __launch_bounds__(kDeltaWaves * 64)
 k_delta_prep(const uint32_t* __restrict__ images, uint32_t n, int needle_side,
              int8_t* __restrict__ planes, uint32_t ngroups, int64_t* __restrict__ sumsq,
-             uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm, int8_t* __restrict__ hplanes)
+             uint32_t* __restrict__ maxabs, const uint32_t* __restrict__ perm, int8_t* __restrict__ hplanes,
+             const uint32_t* __restrict__ qflags)
 {
-    delta_group(images, n, needle_side, planes, ngroups, sumsq, maxabs, perm, blockIdx.x, hplanes);
+    delta_group(images, n, needle_side, planes, ngroups, sumsq, maxabs, perm, blockIdx.x, hplanes, qflags);
 }
 
 // Haystack slot assignment.  k_hay_init marks every slot as padding;
@@ -262,13 +270,14 @@ k_hay_assign(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslot
     hay_assign_block(maxabs_img, n, nslots, perm, maxabs, inv);
 }
 
-// Paired sets: per tile of 256 slots, bit 0 = some image with |D| <= 127 (the
+// Paired sets: per tile of kFlagTile slots, bit 0 = some image with |D| <= 127 (the
 // tile takes part in the contraction), bit 1 = some such image with |D| > 15
 // (the tile needs the q phase).  One wavefront per tile.
 __device__ void tile_flags_one(const uint32_t* __restrict__ maxabs, uint32_t* __restrict__ flags, uint32_t t,
                                int lane)
 {
-    const uint4 m = reinterpret_cast<const uint4*>(maxabs + (size_t)t * 256)[lane];
+    static_assert(kFlagTile == 4 * 64, "one wavefront of uint4 loads per tile");
+    const uint4 m = reinterpret_cast<const uint4*>(maxabs + (size_t)t * kFlagTile)[lane];
     const uint32_t mx[4] = {m.x, m.y, m.z, m.w};
     bool use = false, big = false;
 #pragma unroll
@@ -387,6 +396,7 @@ struct SearchCfg {
 // one-row stages (4 x 32 KiB) filled by direct global -> LDS loads two stages
 // ahead of their use (measured on MI355X: 3- and 5-deep rings are slower)
 using Cfg = SearchCfg<2, 4, 8, 4, 4>;
+static_assert(Cfg::BM == kFlagTile && Cfg::BN == kFlagTile, "paired tiles are the flag tiles");
 // 128 x 256 tile (8 waves of 64 x 64, 4-deep ring of 24 KiB stages): less
 // padding for needle sets of at most 128 images
 using CfgS = SearchCfg<2, 4, 4, 4, 4>;
@@ -674,7 +684,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
     // no usable haystack image, or no needle that can count
     if (!(flags & 2) || (ranks && !(flags & 4))) return;
     // Stage s = phase s / 64, image row s % 64.  Phase -> planes: needle planes
-    // 0 = -D, 1 = mask; haystack planes 0 = D, 1 = r, 2 = q (D^2 = 256 q + r + 128).
+    // 0 = D, 1 = mask; haystack planes 0 = D, 1 = r, 2 = q (D^2 = 256 q + r + 128).
     // Each wave moves kLPW whole fragments (1 KiB, one instruction each) from
     // global memory straight into the stage's LDS slot.  Fragment j of wave w
     // is fragment w + j * kWaves of the stage (the GA needle groups, then the
@@ -694,14 +704,16 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         const int g = wv + j * C::kWaves - (j < kJA ? 0 : C::GA);
         voff[j] = (uint32_t)g * (uint32_t)kPlaneGroupBytes + (uint32_t)lane * 16;
     }
-    // planes of phases 0, 1: needles -D, mask; haystack D, r.  With the q
-    // phase first (hq): needles mask, -D, mask; haystack q, D, r.  Pair mode:
-    // needles -D, mask of tile I against haystack D, r of tile J, then the r
+    // planes of phases 0, 1: needles D, mask; haystack D, r.  With the q
+    // phase first (hq): needles mask, D, mask; haystack q, D, r.  Pair mode:
+    // needles D, mask of tile I against haystack D, r of tile J, then the r
     // plane of tile I (haystack planes) against the mask of tile J (needle
-    // planes).
+    // planes).  A paired set keeps one D plane, the haystack's (same slot
+    // order).
     auto plane_src = [&](bool hq) {
-        const int8_t* a_p0 = a_base + (hq ? a_ps : 0);
-        const int8_t* a_p1 = a_base + (hq ? 0 : a_ps);
+        const int8_t* a_d = (MODE == kModePair || A.paired) ? A.b_planes + (size_t)ga0 * kPlaneGroupBytes : a_base;
+        const int8_t* a_p0 = hq ? a_base + a_ps : a_d;
+        const int8_t* a_p1 = hq ? a_d : a_base + a_ps;
         const int8_t* a_p2 = MODE == kModePair ? A.b_planes + (size_t)ga0 * kPlaneGroupBytes + b_ps : a_p0;
         const int8_t* b_p0 = b_base + (hq ? 2 * b_ps : 0);
         const int8_t* b_p1 = b_base + (hq ? 0 : b_ps);
@@ -879,12 +891,13 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
         }
         if constexpr (MODE != kModePair) {
             if (k == C::kNS - 1 && (s + 1) % NB == 0 && s + 1 < nstage) {
-                // end of a phase: scale the partial sum (x128 after q, x2 after -D.D)
+                // end of a phase: scale the partial sum (x -128 after q, x -2
+                // after D.D)
                 const int sh = (hq && s + 1 == NB) ? 7 : 1;
 #pragma unroll
                 for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
-                    for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << sh;
+                    for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = -(acc[mb][nb] << sh);
             }
         }
     };
@@ -896,7 +909,7 @@ __device__ void search_tile(const SearchArgs& A, uint32_t tm, uint32_t tn, int8_
 #pragma unroll
         for (int mb = 0; mb < C::kMB; ++mb)
 #pragma unroll
-            for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = acc[mb][nb] << 1;
+            for (int nb = 0; nb < C::kNBK; ++nb) acc[mb][nb] = -(acc[mb][nb] << 1);
         int32_t lo = 0, hi = 0;
 #pragma unroll
         for (int mb = 0; mb < C::kMB; ++mb)
@@ -1378,7 +1391,8 @@ k_needle_prep_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
 {
     const SearchJob& J = jobs[job_of<0>(jobs, njobs, blockIdx.x)];
     delta_group(J.needles, J.A.nn, J.A.paired ? 2 : 1, J.np.planes, J.np.ngroups, J.np.sumsq, J.np.maxabs,
-                J.A.paired ? J.hp.perm : nullptr, (uint32_t)(blockIdx.x - J.ngrp_start), J.hp.planes);
+                J.A.paired ? J.hp.perm : nullptr, (uint32_t)(blockIdx.x - J.ngrp_start), J.hp.planes,
+                J.A.paired ? J.A.tile_flags : nullptr);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1399,9 +1413,9 @@ k_tile_flags_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint64_
 {
     const uint64_t t = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= total) return;
-    const SearchJob& J = jobs[job_of<3>(jobs, njobs, t * (Cfg::BN / kGroup))];
+    const SearchJob& J = jobs[job_of<3>(jobs, njobs, t * (kFlagTile / kGroup))];
     tile_flags_one(J.hp.maxabs, const_cast<uint32_t*>(J.A.tile_flags),
-                   (uint32_t)(t - J.hgrp_start / (Cfg::BN / kGroup)), threadIdx.x & 63);
+                   (uint32_t)(t - J.hgrp_start / (kFlagTile / kGroup)), threadIdx.x & 63);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1512,7 +1526,7 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
         }
     }
     hipLaunchKernelGGL(k_delta_prep, dim3(p.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, needle_side, p.planes,
-                       p.ngroups, p.sumsq, p.maxabs, p.perm, (int8_t*)nullptr);
+                       p.ngroups, p.sumsq, p.maxabs, p.perm, (int8_t*)nullptr, (const uint32_t*)nullptr);
     return hipGetLastError();
 }
 
@@ -1540,14 +1554,15 @@ hipError_t launch_paired_prep(const uint32_t* images, uint32_t n, const SearchPr
     hipLaunchKernelGGL(k_hay_assign, dim3(1), dim3(1024), 0, s, hp.maxabs_img, n, nslots, hp.perm, hp.maxabs, hp.inv);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // needle planes (-D, mask) and haystack planes (D, r, q), both in slot
-    // order, from one read of each image
-    hipLaunchKernelGGL(k_delta_prep, dim3(np.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, 2, np.planes,
-                       np.ngroups, np.sumsq, np.maxabs, (const uint32_t*)hp.perm, hp.planes);
+    const uint32_t tiles = nslots / kFlagTile;
+    hipLaunchKernelGGL(k_tile_flags, dim3((tiles + 3) / 4), dim3(256), 0, s, hp.maxabs, tiles, tile_flags);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const uint32_t tiles = nslots / Cfg::BN;
-    hipLaunchKernelGGL(k_tile_flags, dim3((tiles + 3) / 4), dim3(256), 0, s, hp.maxabs, tiles, tile_flags);
+    // the needles' mask plane and the haystack planes (D, r, q), both in slot
+    // order, from one read of each image; q only where the tile flags ask
+    hipLaunchKernelGGL(k_delta_prep, dim3(np.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, 2, np.planes,
+                       np.ngroups, np.sumsq, np.maxabs, (const uint32_t*)hp.perm, hp.planes,
+                       (const uint32_t*)tile_flags);
     return hipGetLastError();
 }
 
@@ -1628,8 +1643,9 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
         if (e_ != hipSuccess) return e_;                   \
     } while (0)
     if ((part == 0 || part == 1) && paired) {
-        // paired sets: statistics, slot assignment, then both plane sets in
-        // slot order, tile flags and the true-match distances
+        // paired sets: statistics, slot assignment, tile flags, then both
+        // plane sets in slot order (q only where the flags ask) and the
+        // true-match distances
         if (T.hay_slots)
             RICI_LAUNCH(k_hay_init_batched, dim3((uint32_t)((T.hay_slots + 255) / 256)), dim3(256), 0, s, jobs, njobs,
                         T.hay_slots);
@@ -1637,12 +1653,12 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
             RICI_LAUNCH(k_hay_stats_batched, dim3((uint32_t)((T.hay_images + 3) / 4)), dim3(256), 0, s, jobs, njobs,
                         T.hay_images);
         RICI_LAUNCH(k_hay_assign_batched, dim3(njobs), dim3(1024), 0, s, jobs);
-        if (T.needle_groups)   // == T.hay_groups: both plane sets in one pass
-            RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
         if (T.hay_groups) {
-            const uint64_t tiles = T.hay_groups / (Cfg::BN / kGroup);
+            const uint64_t tiles = T.hay_groups / (kFlagTile / kGroup);
             RICI_LAUNCH(k_tile_flags_batched, dim3((uint32_t)((tiles + 3) / 4)), dim3(256), 0, s, jobs, njobs, tiles);
         }
+        if (T.needle_groups)   // == T.hay_groups: both plane sets in one pass
+            RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
         if (T.needles)
             RICI_LAUNCH(k_true_distance_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
                         T.needles);
