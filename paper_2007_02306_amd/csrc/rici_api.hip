@@ -466,14 +466,11 @@ int rank_paired(rici_ctx* h, const uint32_t* images, uint32_t n, const uint32_t*
     np.maxabs = np.maxabs_img = hp.maxabs_img;   // per image (the needle pass writes no statistics)
     np.ngroups = hp.ngroups = (uint32_t)gb;
 
-    hipError_t e = timed(h, "paired_prep", s,
-                         [&] { return rici::launch_paired_prep(images, n, np, hp, thr, tile_flags, s); });
-    if (e != hipSuccess) return hip_fail(e, "paired_prep launch");
-    e = timed(h, "true_distance", s, [&] {
-        return rici::launch_true_distance(images, n, images, n, true_index, np.sumsq, hp.maxabs_img, ds, thr,
-                                          out_rank, s, hp.inv);
+    // statistics, true-match distances, thresholds and planes
+    hipError_t e = timed(h, "paired_prep", s, [&] {
+        return rici::launch_paired_prep(images, n, true_index, np, hp, thr, tile_flags, ds, out_rank, s);
     });
-    if (e != hipSuccess) return hip_fail(e, "true_distance launch");
+    if (e != hipSuccess) return hip_fail(e, "paired_prep launch");
     rici::SearchArgs A = {};
     A.a_planes = np.planes; A.a_groups = (uint32_t)gb; A.nn = n;
     A.b_planes = hp.planes; A.b_groups = (uint32_t)gb; A.nh = n;

@@ -184,13 +184,16 @@ hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint
                                 const uint32_t* true_idx, const int64_t* sumsq, const uint32_t* nmax,
                                 int64_t* dstar, int32_t* thr, uint32_t* rank, hipStream_t s,
                                 const uint32_t* inv = nullptr);
-// A set of n images ranked against itself ("paired"): haystack statistics,
-// slot assignment (hp.perm, hp.inv, hp.maxabs), needle planes (np, sumsq per
-// image) and haystack planes in the same slot order, thresholds per slot
-// initialised to INT_MIN, and the flags of each 256-slot tile.  np.ngroups ==
+// A set of n images ranked against itself ("paired"): statistics per image
+// (hp.maxabs_img, np.sumsq) and the true-match distances (dstar, -1 for
+// true_idx[i] >= n) in one pass, slot assignment (hp.perm, hp.inv,
+// hp.maxabs) with the thresholds per slot (INT_MIN where no count) and the
+// ranks' start values, the flags of each 256-slot tile, then the needle mask
+// plane and the haystack planes in the same slot order.  np.ngroups ==
 // hp.ngroups == haystack_slots(n) / 16.
-hipError_t launch_paired_prep(const uint32_t* images, uint32_t n, const SearchPrep& np, const SearchPrep& hp,
-                              int32_t* thr_slots, uint32_t* tile_flags, hipStream_t s);
+hipError_t launch_paired_prep(const uint32_t* images, uint32_t n, const uint32_t* true_idx, const SearchPrep& np,
+                              const SearchPrep& hp, int32_t* thr_slots, uint32_t* tile_flags, int64_t* dstar,
+                              uint32_t* rank, hipStream_t s);
 // persistent search over the tile pairs of a paired set (A.paired, square
 // tiles); grid <= resident workgroups, each with a paired_slot_bytes() slot
 // of A.cross; counters: 8 words of scratch

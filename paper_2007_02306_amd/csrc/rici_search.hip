@@ -129,7 +129,9 @@ __device__ void delta_group(const uint32_t* __restrict__ images, uint32_t n, int
                 *reinterpret_cast<uint4*>(hp + 2 * plane_stride + frag) = make_uint4(hq[0], hq[1], hq[2], hq[3]);
         }
     }
-    if (perm && !needle_side) return;   // the haystack's statistics come from k_hay_stats
+    // the haystack's statistics come from k_hay_stats; a paired set's
+    // needle constants from k_stats_true (sumsq == nullptr)
+    if (perm && (!needle_side || !sumsq)) return;
     // per-image reductions: 4 lanes (q) per wave and kDeltaWaves waves share image i
 #pragma unroll
     for (int o = 16; o < 64; o <<= 1) {
@@ -223,9 +225,16 @@ k_copy_u32(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, uint32_
 // One workgroup of 1024 threads walks the images in rounds of 1024
 // consecutive ones (coalesced loads, the next round prefetched); a workgroup
 // scan of the small/other flags gives each image its slot in image order.
+// A set ranked against itself (thr != nullptr) also gets, per image, its
+// threshold in its slot, CRD(i, t(i)) minus the needle constant (none when
+// t(i) is outside the set or max |D| > 127), and its rank's start value
+// (0, or n for a true index outside the set: Sec. 4.1 step 6c).
 __device__ void hay_assign_block(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslots,
                                  uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs,
-                                 uint32_t* __restrict__ inv)
+                                 uint32_t* __restrict__ inv, const uint32_t* __restrict__ true_idx = nullptr,
+                                 const int64_t* __restrict__ dstar = nullptr,
+                                 const int64_t* __restrict__ sumsq = nullptr, int32_t* __restrict__ thr = nullptr,
+                                 uint32_t* __restrict__ rank = nullptr)
 {
     __shared__ uint32_t wsum[2][16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -256,6 +265,13 @@ __device__ void hay_assign_block(const uint32_t* __restrict__ maxabs_img, uint32
             perm[slot] = i;
             maxabs[slot] = m;
             if (inv) inv[i] = slot;
+            if (thr) {
+                const bool in_set = true_idx[i] < n;
+                int64_t th = dstar[i] - sumsq[i];
+                th = min(max(th, (int64_t)INT_MIN + 1), (int64_t)INT_MAX);
+                thr[slot] = (in_set && m <= kSlow) ? (int32_t)th : INT_MIN;
+                rank[i] = in_set ? 0u : n;
+            }
         }
         const uint32_t cnt = min(1024u, n - r0);
         base_s += tot;
@@ -265,9 +281,11 @@ __device__ void hay_assign_block(const uint32_t* __restrict__ maxabs_img, uint32
 
 __global__ void __launch_bounds__(1024)
 k_hay_assign(const uint32_t* __restrict__ maxabs_img, uint32_t n, uint32_t nslots,
-             uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs, uint32_t* __restrict__ inv)
+             uint32_t* __restrict__ perm, uint32_t* __restrict__ maxabs, uint32_t* __restrict__ inv,
+             const uint32_t* __restrict__ true_idx, const int64_t* __restrict__ dstar,
+             const int64_t* __restrict__ sumsq, int32_t* __restrict__ thr, uint32_t* __restrict__ rank)
 {
-    hay_assign_block(maxabs_img, n, nslots, perm, maxabs, inv);
+    hay_assign_block(maxabs_img, n, nslots, perm, maxabs, inv, true_idx, dstar, sumsq, thr, rank);
 }
 
 // Paired sets: per tile of kFlagTile slots, bit 0 = some image with |D| <= 127 (the
@@ -346,6 +364,75 @@ __device__ void true_distance_one(const uint32_t* __restrict__ needles, const ui
         thr[ti] = nmax[i] <= kSlow ? (int32_t)th : INT_MIN;
         rank[i] = 0;
     }
+}
+
+// A set ranked against itself: one wavefront reads image i and its true
+// match t(i) once and finds max |D| of image i (saturating as k_hay_stats),
+// its constant |D|^2 + 128 #(D != 0) and CRD(i, t(i)) (Eq. 6-7; -1 for a true
+// index outside the set), with the bits of the int64 sums.  The slot
+// assignment, which needs max |D| of every image first, turns them into
+// thresholds.  Lane layout as crd_wave.  Per pixel the work is 32-bit: |D| is
+// an unsigned absolute difference, squares are 32 x 32 -> 64-bit products,
+// and D_n - D_h is exact in 32 bits while both deltas are below 2^30 in
+// magnitude; a wavefront that meets a wider delta takes the distance from
+// crd_wave instead.
+__device__ void stats_true_one(const uint32_t* __restrict__ images, uint32_t n,
+                               const uint32_t* __restrict__ true_idx, uint32_t* __restrict__ maxabs_img,
+                               int64_t* __restrict__ sumsq, int64_t* __restrict__ dstar, uint32_t i, int lane)
+{
+    const uint32_t t = true_idx[i];
+    const bool in_set = t < n;   // one needle per wavefront: uniform
+    const uint32_t* nimg = images + (size_t)i * NPIX;
+    const uint32_t* himg = images + (size_t)(in_set ? t : i) * NPIX;
+    const uint4* a4 = reinterpret_cast<const uint4*>(nimg);
+    const uint4* b4 = reinterpret_cast<const uint4*>(himg);
+    const bool first = (lane & 15) == 0;
+    uint32_t mx = 0, nz = 0, wide = 0;
+    uint64_t sq = 0, s = 0;
+#pragma unroll 4
+    for (int it = 0; it < NB / 4; ++it) {
+        const uint4 a = a4[it * 64 + lane];
+        const uint4 b = b4[it * 64 + lane];
+        const uint32_t al = __shfl_up(a.w, 1, 64), bl = __shfl_up(b.w, 1, 64);
+        const uint32_t an[5] = {al, a.x, a.y, a.z, a.w}, bn[5] = {bl, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            // column 0 of a row has no delta: no term, no statistic
+            const bool none = k == 0 && first;
+            const uint32_t ad = none ? 0u : __usad(an[k + 1], an[k], 0u);
+            const uint32_t bd = none ? 0u : __usad(bn[k + 1], bn[k], 0u);
+            mx = max(mx, ad);
+            nz += min(ad, 1u);
+            sq += (uint64_t)ad * ad;
+            wide |= ad | bd;
+            const int32_t e = (int32_t)((an[k + 1] - an[k]) - (bn[k + 1] - bn[k]));
+            const uint32_t ae = ad ? (uint32_t)(e < 0 ? -e : e) : 0u;
+            s += (uint64_t)ae * ae;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+        nz += (uint32_t)__shfl_xor((int)nz, o, 64);
+        wide |= (uint32_t)__shfl_xor((int)wide, o, 64);
+        sq += (uint64_t)__shfl_xor((long long)sq, o, 64);
+        s += (uint64_t)__shfl_xor((long long)s, o, 64);
+    }
+    int64_t d = (int64_t)s;
+    if (in_set && wide >= (1u << 30)) d = crd_wave(nimg, himg, lane);
+    if (lane == 0) {
+        maxabs_img[i] = min(mx, 0xFFFFFFFEu);
+        sumsq[i] = (int64_t)(sq + 128ull * nz);
+        dstar[i] = in_set ? d : -1;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_stats_true(const uint32_t* __restrict__ images, uint32_t n, const uint32_t* __restrict__ true_idx,
+             uint32_t* __restrict__ maxabs_img, int64_t* __restrict__ sumsq, int64_t* __restrict__ dstar)
+{
+    const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i < n) stats_true_one(images, n, true_idx, maxabs_img, sumsq, dstar, i, threadIdx.x & 63);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1390,7 +1477,8 @@ __global__ void __launch_bounds__(kDeltaWaves * 64)
 k_needle_prep_batched(const SearchJob* __restrict__ jobs, uint32_t njobs)
 {
     const SearchJob& J = jobs[job_of<0>(jobs, njobs, blockIdx.x)];
-    delta_group(J.needles, J.A.nn, J.A.paired ? 2 : 1, J.np.planes, J.np.ngroups, J.np.sumsq, J.np.maxabs,
+    delta_group(J.needles, J.A.nn, J.A.paired ? 2 : 1, J.np.planes, J.np.ngroups,
+                J.A.paired ? nullptr : J.np.sumsq, J.np.maxabs,
                 J.A.paired ? J.hp.perm : nullptr, (uint32_t)(blockIdx.x - J.ngrp_start), J.hp.planes,
                 J.A.paired ? J.A.tile_flags : nullptr);
 }
@@ -1437,7 +1525,11 @@ __global__ void __launch_bounds__(1024)
 k_hay_assign_batched(const SearchJob* __restrict__ jobs)
 {
     const SearchJob& J = jobs[blockIdx.x];
-    hay_assign_block(J.hp.maxabs_img, J.A.nh, J.hp.ngroups * kGroup, J.hp.perm, J.hp.maxabs, J.hp.inv);
+    if (J.A.paired)
+        hay_assign_block(J.hp.maxabs_img, J.A.nh, J.hp.ngroups * kGroup, J.hp.perm, J.hp.maxabs, J.hp.inv,
+                         J.true_idx, J.dstar, J.np.sumsq, const_cast<int32_t*>(J.A.thr), J.A.rank);
+    else
+        hay_assign_block(J.hp.maxabs_img, J.A.nh, J.hp.ngroups * kGroup, J.hp.perm, J.hp.maxabs, J.hp.inv);
 }
 
 __global__ void __launch_bounds__(kDeltaWaves * 64)
@@ -1457,6 +1549,18 @@ k_true_distance_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint
     true_distance_one(J.needles, J.hay, J.A.nh, J.true_idx, J.np.sumsq, J.np.maxabs, J.dstar,
                       const_cast<int32_t*>(J.A.thr), J.A.rank, J.A.paired ? J.hp.inv : nullptr,
                       (uint32_t)(x - J.needle_start), threadIdx.x & 63);
+}
+
+// paired sets: statistics and true-match distances in one pass over the
+// images (flattened over the jobs; needles and haystack are the same set)
+__global__ void __launch_bounds__(256)
+k_stats_true_batched(const SearchJob* __restrict__ jobs, uint32_t njobs, uint64_t total)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (x >= total) return;
+    const SearchJob& J = jobs[job_of<4>(jobs, njobs, x)];
+    stats_true_one(J.hay, J.A.nh, J.true_idx, J.hp.maxabs_img, J.np.sumsq, J.dstar, (uint32_t)(x - J.needle_start),
+                   threadIdx.x & 63);
 }
 
 __global__ void __launch_bounds__(1024)
@@ -1520,7 +1624,8 @@ hipError_t launch_delta_prep(const uint32_t* images, uint32_t n, int needle_side
             e = hipGetLastError();
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_hay_assign, dim3(1), dim3(1024), 0, s, p.maxabs_img, n, nslots, p.perm, p.maxabs,
-                               (uint32_t*)nullptr);
+                               (uint32_t*)nullptr, (const uint32_t*)nullptr, (const int64_t*)nullptr,
+                               (const int64_t*)nullptr, (int32_t*)nullptr, (uint32_t*)nullptr);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -1540,18 +1645,21 @@ hipError_t launch_true_distance(const uint32_t* needles, uint32_t nn, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_paired_prep(const uint32_t* images, uint32_t n, const SearchPrep& np, const SearchPrep& hp,
-                              int32_t* thr_slots, uint32_t* tile_flags, hipStream_t s)
+hipError_t launch_paired_prep(const uint32_t* images, uint32_t n, const uint32_t* true_idx, const SearchPrep& np,
+                              const SearchPrep& hp, int32_t* thr_slots, uint32_t* tile_flags, int64_t* dstar,
+                              uint32_t* rank, hipStream_t s)
 {
     const uint32_t nslots = hp.ngroups * kGroup;
     if (n == 0 || nslots == 0 || np.ngroups != hp.ngroups) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_hay_init, dim3((nslots + 255) / 256), dim3(256), 0, s, hp.perm, hp.maxabs, thr_slots, nslots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_hay_stats, dim3((n + 3) / 4), dim3(256), 0, s, images, n, hp.maxabs_img);
+    hipLaunchKernelGGL(k_stats_true, dim3((n + 3) / 4), dim3(256), 0, s, images, n, true_idx, hp.maxabs_img,
+                       np.sumsq, dstar);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_hay_assign, dim3(1), dim3(1024), 0, s, hp.maxabs_img, n, nslots, hp.perm, hp.maxabs, hp.inv);
+    hipLaunchKernelGGL(k_hay_assign, dim3(1), dim3(1024), 0, s, hp.maxabs_img, n, nslots, hp.perm, hp.maxabs, hp.inv,
+                       true_idx, (const int64_t*)dstar, (const int64_t*)np.sumsq, thr_slots, rank);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const uint32_t tiles = nslots / kFlagTile;
@@ -1561,7 +1669,7 @@ hipError_t launch_paired_prep(const uint32_t* images, uint32_t n, const SearchPr
     // the needles' mask plane and the haystack planes (D, r, q), both in slot
     // order, from one read of each image; q only where the tile flags ask
     hipLaunchKernelGGL(k_delta_prep, dim3(np.ngroups), dim3(kDeltaWaves * 64), 0, s, images, n, 2, np.planes,
-                       np.ngroups, np.sumsq, np.maxabs, (const uint32_t*)hp.perm, hp.planes,
+                       np.ngroups, (int64_t*)nullptr, np.maxabs, (const uint32_t*)hp.perm, hp.planes,
                        (const uint32_t*)tile_flags);
     return hipGetLastError();
 }
@@ -1643,15 +1751,15 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
         if (e_ != hipSuccess) return e_;                   \
     } while (0)
     if ((part == 0 || part == 1) && paired) {
-        // paired sets: statistics, slot assignment, tile flags, then both
-        // plane sets in slot order (q only where the flags ask) and the
-        // true-match distances
+        // paired sets: statistics with the true-match distances (one read of
+        // each image), slot assignment with the thresholds, tile flags, then
+        // both plane sets in slot order (q only where the flags ask)
         if (T.hay_slots)
             RICI_LAUNCH(k_hay_init_batched, dim3((uint32_t)((T.hay_slots + 255) / 256)), dim3(256), 0, s, jobs, njobs,
                         T.hay_slots);
-        if (T.hay_images)
-            RICI_LAUNCH(k_hay_stats_batched, dim3((uint32_t)((T.hay_images + 3) / 4)), dim3(256), 0, s, jobs, njobs,
-                        T.hay_images);
+        if (T.needles)   // == T.hay_images
+            RICI_LAUNCH(k_stats_true_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
+                        T.needles);
         RICI_LAUNCH(k_hay_assign_batched, dim3(njobs), dim3(1024), 0, s, jobs);
         if (T.hay_groups) {
             const uint64_t tiles = T.hay_groups / (kFlagTile / kGroup);
@@ -1659,9 +1767,6 @@ hipError_t launch_search_batched(const SearchJob* jobs, uint32_t njobs, const Se
         }
         if (T.needle_groups)   // == T.hay_groups: both plane sets in one pass
             RICI_LAUNCH(k_needle_prep_batched, dim3((uint32_t)T.needle_groups), dim3(kDeltaWaves * 64), 0, s, jobs, njobs);
-        if (T.needles)
-            RICI_LAUNCH(k_true_distance_batched, dim3((uint32_t)((T.needles + 3) / 4)), dim3(256), 0, s, jobs, njobs,
-                        T.needles);
         RICI_LAUNCH(k_zero_counters8, dim3(1), dim3(64), 0, s, counter);
     } else if (part == 0 || part == 1) {
         if (T.needle_groups)
