@@ -104,6 +104,38 @@ def test_paired_cross_terms_beyond_int16(ctx):
     _same(p_rk, o_rk, "paired ranks")
 
 
+def test_paired_true_distances_with_deltas_beyond_2_30(ctx):
+    """The pass that finds each image's statistics and true-match distance
+    works in 32 bits while every delta of both images stays below 2^30 and
+    takes the exact int64 sum otherwise.  Images with one step of about 2^30
+    up, or down, in the same pixel: the true match of W0 is W1, so the
+    difference of their deltas there is about 2^31 (past int32); W2's true
+    match is an ordinary image, and an ordinary image's true match is W3.
+    Every sum stays below 2^63.  Ranks and distances must equal the oracle's
+    (these images have |D| > 127, so their ranks come from the exact path)."""
+    n = 700
+    imgs = _set(2024, n)
+    t = _truth(2024, n)
+    w = [17, 300, 511, 650]
+    big = [(1 << 30) + 12345, (1 << 30) + 777, (1 << 30) + 5, (1 << 30) + 99]
+    r0, c0 = 9, 40
+    imgs[w[0], r0, c0:] += np.uint32(big[0])          # one delta of +big[0] at (r0, c0)
+    imgs[w[1], r0, :c0] += np.uint32(big[1])          # one delta of about -big[1] at the same pixel
+    imgs[w[2], 33, 5:] += np.uint32(big[2])
+    imgs[w[3], 50, 63:] += np.uint32(big[3])
+    t[w[0]] = w[1]
+    t[w[2]] = 3
+    t[123] = w[3]
+    d0 = np.diff(imgs[w[0]].astype(np.int64), axis=1)[r0, c0 - 1]
+    d1 = np.diff(imgs[w[1]].astype(np.int64), axis=1)[r0, c0 - 1]
+    assert d0 >= 1 << 30 and d1 <= -(1 << 30) and d0 - d1 > (1 << 31)
+    p_rk, p_ds = _rank(ctx, imgs, t, 1)
+    o_rk, o_ds = oracle.rank(imgs, imgs, t)
+    assert int(o_ds[w[0]]) > 1 << 62 and int(o_ds.max()) < 1 << 63
+    _same(p_ds, o_ds, "paired true distances")
+    _same(p_rk, o_rk, "paired ranks")
+
+
 def test_paired_identity_truth_and_duplicates(ctx):
     """t(i) = i gives rank 0 for every image; exact duplicates tie at the
     true distance 0 and keep the best rank."""
